@@ -1,0 +1,186 @@
+"""Plain serial FP64 CPU oracle for the truncated-normal MDS likelihood path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the bench may import this package; the product library never does.
+The arithmetic lives in ``mds_oracle.c`` (compiled with gcc -O2, no fast-math);
+this module only marshals numpy arrays into it.
+
+Functions follow Holbrook et al., "Massive parallelization boosts big
+Bayesian multidimensional scaling":
+  * ``log_phi``/``mills``   -- ln Phi(t) and phi(t)/Phi(t) (Eq. 2, Eq. 9)
+  * ``evaluate``            -- L, dL/dX, dL/dsigma (Eq. 2, Eq. 9)
+  * ``leapfrog``            -- one HMC leapfrog trajectory (Section 2.3)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mds_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libmds_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_ubyte)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, strict IEEE: no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
+             "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.oracle_log_phi.restype = ctypes.c_double
+    lib.oracle_log_phi.argtypes = [ctypes.c_double]
+    lib.oracle_mills.restype = ctypes.c_double
+    lib.oracle_mills.argtypes = [ctypes.c_double]
+    lib.oracle_count_observed.restype = ctypes.c_int64
+    lib.oracle_count_observed.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _u8p,
+                                          ctypes.c_int64]
+    lib.oracle_eval.restype = ctypes.c_int
+    lib.oracle_eval.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
+                                ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
+                                _dp, _dp, _dp, _dp, _dp, _dp, _i64p]
+    lib.oracle_leapfrog.restype = ctypes.c_int
+    lib.oracle_leapfrog.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, _dp, _dp,
+                                    ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
+                                    _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                    _dp, _dp, _dp, _dp, _dp]
+    _lib = lib
+    return lib
+
+
+def _ptr(a, typ=_dp):
+    if a is None:
+        return None
+    return a.ctypes.data_as(typ)
+
+
+def _as_y(y):
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return y
+
+
+def _as_mask(mask, n):
+    if mask is None:
+        return None
+    m = np.ascontiguousarray(mask)
+    if m.dtype != np.uint8:
+        m = (m != 0).astype(np.uint8)
+    assert m.shape == (n, n)
+    return m
+
+
+def log_phi(t) -> np.ndarray:
+    """ln Phi(t) elementwise (any real t)."""
+    lib = _load()
+    t = np.asarray(t, dtype=np.float64)
+    return np.vectorize(lib.oracle_log_phi, otypes=[np.float64])(t)
+
+
+def mills(t) -> np.ndarray:
+    """phi(t)/Phi(t) elementwise (any real t)."""
+    lib = _load()
+    t = np.asarray(t, dtype=np.float64)
+    return np.vectorize(lib.oracle_mills, otypes=[np.float64])(t)
+
+
+def count_observed(y, mask=None) -> int:
+    lib = _load()
+    y = _as_y(y)
+    n = y.shape[0]
+    m = _as_mask(mask, n)
+    return int(lib.oracle_count_observed(n, _ptr(y), y.shape[1], _ptr(m, _u8p),
+                                         n if m is not None else 0))
+
+
+@dataclass
+class Evaluation:
+    loglik: float
+    grad: np.ndarray      # N x D
+    dsigma: float
+    absrow: np.ndarray    # N: sum_j |w_ij|, the scale of each gradient row
+    abs_loglik: float     # sum |r_ij| + M |ln sigma|
+    abs_dsigma: float     # sum |d r_ij/d sigma| + M / sigma
+    m_obs: int
+
+
+def evaluate(x, y, sigma: float, mask=None) -> Evaluation:
+    """L, dL/dX and dL/dsigma of Eq. (2)/(9) at X for dissimilarities Y."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    n, d = x.shape
+    y = _as_y(y)
+    assert y.shape[0] == n and y.shape[1] >= n
+    m = _as_mask(mask, n)
+    grad = np.zeros((n, d), dtype=np.float64)
+    absrow = np.zeros(n, dtype=np.float64)
+    out = (ctypes.c_double * 5)()
+    mobs = ctypes.c_int64(0)
+    rc = lib.oracle_eval(n, d, _ptr(x), d, _ptr(y), y.shape[1], _ptr(m, _u8p),
+                         n if m is not None else 0, float(sigma),
+                         ctypes.cast(ctypes.byref(out, 0), _dp), _ptr(grad),
+                         ctypes.cast(ctypes.byref(out, 8), _dp), _ptr(absrow),
+                         ctypes.cast(ctypes.byref(out, 16), _dp),
+                         ctypes.cast(ctypes.byref(out, 24), _dp), ctypes.byref(mobs))
+    if rc != 0:
+        raise ValueError("oracle_eval rejected its arguments")
+    return Evaluation(out[0], grad, out[1], absrow, out[2], out[3], int(mobs.value))
+
+
+@dataclass
+class Trajectory:
+    x: np.ndarray
+    p: np.ndarray
+    grad_end: np.ndarray
+    loglik_start: float
+    loglik_end: float
+    energy_start: float
+    energy_end: float
+
+
+def leapfrog(x, p, y, sigma: float, eps: float, n_steps: int, mask=None,
+             inv_mass=None, prior_precision: float = 0.0) -> Trajectory:
+    """One leapfrog trajectory (Section 2.3); returns copies, inputs untouched."""
+    lib = _load()
+    x = np.array(x, dtype=np.float64, copy=True, order="C")
+    p = np.array(p, dtype=np.float64, copy=True, order="C")
+    n, d = x.shape
+    assert p.shape == (n, d)
+    y = _as_y(y)
+    m = _as_mask(mask, n)
+    im = None if inv_mass is None else np.ascontiguousarray(inv_mass, dtype=np.float64)
+    if im is not None:
+        assert im.shape == (n, d)
+    g = np.zeros((n, d), dtype=np.float64)
+    out = (ctypes.c_double * 4)()
+    rc = lib.oracle_leapfrog(n, d, _ptr(x), _ptr(p), _ptr(y), y.shape[1], _ptr(m, _u8p),
+                             n if m is not None else 0, float(sigma), _ptr(im), float(eps),
+                             float(prior_precision), int(n_steps), _ptr(g),
+                             ctypes.cast(ctypes.byref(out, 0), _dp),
+                             ctypes.cast(ctypes.byref(out, 8), _dp),
+                             ctypes.cast(ctypes.byref(out, 16), _dp),
+                             ctypes.cast(ctypes.byref(out, 24), _dp))
+    if rc != 0:
+        raise ValueError("oracle_leapfrog rejected its arguments")
+    return Trajectory(x, p, g, out[0], out[1], out[2], out[3])

@@ -1,0 +1,306 @@
+/*
+ * mds_oracle.c -- plain, serial, FP64 CPU oracle for the truncated-normal
+ * multidimensional-scaling (MDS) likelihood of Holbrook et al.,
+ * "Massive parallelization boosts big Bayesian multidimensional scaling".
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file defines what the GPU path must
+ * compute; it is slow on purpose (one pair at a time, compensated sums, libm
+ * special functions) so that it can be checked against the paper by eye.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the bench
+ * may load it.  It shares no code, header, table or constant with the HIP
+ * library, and the HIP library never calls it.
+ *
+ * Conventions (the readings of the paper this oracle takes):
+ *   - A pair (i, j) with i > j is one observation y_ij (Section 2.1, Eq. 1);
+ *     each unordered pair is counted once.  Y is read from its lower triangle
+ *     (row i, column j < i) of a row-major array with leading dimension ldy.
+ *   - A pair is missing when its mask byte is non-zero or its y is NaN.
+ *     Missing pairs are left out of the sums and of the count M.
+ *   - The log-likelihood keeps the sigma normalisation of Eq. (2) for the
+ *     observed pairs and drops the 2*pi constant, as the proportionality sign
+ *     of Eq. (2) does:  L = -M ln(sigma) - sum_{observed i>j} r_ij,
+ *     r_ij = (y_ij - delta_ij)^2 / (2 sigma^2) + ln Phi(delta_ij / sigma).
+ *   - Gradient rows follow Eq. (9); a coincident pair (delta = 0) has an
+ *     undefined direction and contributes zero to the gradient.
+ *   - dL/dsigma is the derivative of the same L with respect to sigma.
+ *   - Leapfrog follows Section 2.3 (Eqs. 6-8) with xdot = M^{-1} p (the
+ *     printed factor 1/2 in Eq. 7 is read as a typesetting error) and an
+ *     optional isotropic Gaussian prior -(lambda/2)||X||^2 in the target.
+ *
+ * Every sum uses Neumaier's compensated summation, so the oracle's own
+ * rounding error stays far below the 1e-12 parity tolerance even for tens of
+ * millions of terms.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_SQRT2 1.41421356237309504880
+#define ORACLE_LN_SQRT_2PI 0.91893853320467274178 /* ln(sqrt(2 pi)) */
+#define ORACLE_INV_SQRT_2PI 0.39894228040143267794 /* 1/sqrt(2 pi) */
+
+/* ---------------------------------------------------------------- sums -- */
+
+typedef struct {
+    double s; /* running sum */
+    double c; /* running compensation */
+} nsum;
+
+static void nsum_add(nsum* a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double nsum_get(const nsum* a) { return a->s + a->c; }
+
+/* ------------------------------------------------- normal distribution -- */
+
+/* Mills ratio R(z) = Phi(-z)/phi(z) for z > 0 by Laplace's continued fraction
+ * R(z) = 1/(z + 1/(z + 2/(z + 3/(z + ...)))), evaluated from the tail with a
+ * fixed depth (used only for z >= 5, where 400 levels are far beyond
+ * convergence in double precision). */
+static double mills_ratio_cf(double z)
+{
+    double f = z;
+    for (int k = 400; k >= 1; --k) f = z + (double)k / f;
+    return 1.0 / f;
+}
+
+/* ln Phi(t), the log of the standard normal CDF named in Eq. (2), for any
+ * real t.  For t >= 0 it is log1p(-Phi(-t)) with Phi(-t) = erfc(t/sqrt 2)/2,
+ * which keeps full relative accuracy as Phi(t) -> 1.  For -5 <= t < 0 the
+ * CDF itself is well conditioned.  Below -5 the Mills-ratio continued
+ * fraction gives ln Phi(t) = ln phi(t) + ln R(-t) without underflow. */
+double oracle_log_phi(double t)
+{
+    if (t >= 0.0) return log1p(-0.5 * erfc(t / ORACLE_SQRT2));
+    if (t >= -5.0) return log(0.5 * erfc(-t / ORACLE_SQRT2));
+    return -0.5 * t * t - ORACLE_LN_SQRT_2PI + log(mills_ratio_cf(-t));
+}
+
+/* phi(t)/Phi(t), the ratio that appears in the gradient of Eq. (9). */
+double oracle_mills(double t)
+{
+    if (t >= -5.0) {
+        double phi = exp(-0.5 * t * t) * ORACLE_INV_SQRT_2PI;
+        return phi / (0.5 * erfc(-t / ORACLE_SQRT2));
+    }
+    return 1.0 / mills_ratio_cf(-t);
+}
+
+/* --------------------------------------------------------- likelihood -- */
+
+static int pair_observed(int64_t i, int64_t j, const double* y, int64_t ldy,
+                         const unsigned char* mask, int64_t ldm)
+{
+    if (mask && mask[i * ldm + j] != 0) return 0;
+    return !isnan(y[i * ldy + j]);
+}
+
+/* Number of observed pairs i > j. */
+int64_t oracle_count_observed(int64_t n, const double* y, int64_t ldy,
+                              const unsigned char* mask, int64_t ldm)
+{
+    int64_t m = 0;
+    for (int64_t i = 1; i < n; ++i)
+        for (int64_t j = 0; j < i; ++j) m += pair_observed(i, j, y, ldy, mask, ldm);
+    return m;
+}
+
+/*
+ * Log-likelihood of Eq. (2), its gradient with respect to every row of X
+ * (Eq. 9) and its derivative with respect to sigma, in one pass over the
+ * pairs i > j.
+ *
+ *   x      n*d row-major, leading dimension ldx
+ *   y      n*n row-major, leading dimension ldy (lower triangle read)
+ *   mask   optional n*n bytes, leading dimension ldm; non-zero = missing
+ *   sigma  observation standard deviation (> 0)
+ * Outputs (each may be NULL):
+ *   loglik    L
+ *   grad      n*d row-major, contiguous: dL/dx_i
+ *   dsigma    dL/dsigma
+ *   absrow    n values: A_i = sum_j |w_ij|, the scale of row i's sum
+ *   abs_l     sum_j |r_ij| + M |ln sigma|, the scale of L's sum
+ *   abs_ds    sum |dsigma terms| + M / sigma, the scale of dL/dsigma's sum
+ *   m_obs     number of observed pairs
+ * Returns 0, or -1 on bad arguments or allocation failure.
+ */
+int oracle_eval(int64_t n, int d, const double* x, int64_t ldx, const double* y,
+                int64_t ldy, const unsigned char* mask, int64_t ldm, double sigma,
+                double* loglik, double* grad, double* dsigma, double* absrow,
+                double* abs_l, double* abs_ds, int64_t* m_obs)
+{
+    if (n < 0 || d < 1 || ldx < d || (n > 0 && ldy < n)) return -1;
+    if (mask && n > 0 && ldm < n) return -1;
+
+    nsum* g = NULL;
+    nsum* a = NULL;
+    if (n > 0) {
+        g = (nsum*)calloc((size_t)(n * d), sizeof(nsum));
+        a = (nsum*)calloc((size_t)n, sizeof(nsum));
+        if (!g || !a) {
+            free(g);
+            free(a);
+            return -1;
+        }
+    }
+    nsum sr = {0, 0}, sr_abs = {0, 0}, ss = {0, 0}, ss_abs = {0, 0};
+    int64_t m = 0;
+    double* u = (double*)malloc(sizeof(double) * (size_t)d);
+    if (!u) {
+        free(g);
+        free(a);
+        return -1;
+    }
+
+    const double s2 = sigma * sigma;
+    for (int64_t i = 1; i < n; ++i) {
+        for (int64_t j = 0; j < i; ++j) {
+            if (!pair_observed(i, j, y, ldy, mask, ldm)) continue;
+            ++m;
+            const double yij = y[i * ldy + j];
+            /* delta_ij = ||x_i - x_j||_2  (Section 2.1) */
+            double dd = 0.0;
+            for (int k = 0; k < d; ++k) {
+                double diff = x[i * ldx + k] - x[j * ldx + k];
+                u[k] = diff;
+                dd += diff * diff;
+            }
+            const double delta = sqrt(dd);
+            const double t = delta / sigma;
+            /* truncation terms of Eq. (2) and Eq. (9) */
+            const double q = 0.5 * erfc(t / ORACLE_SQRT2); /* Phi(-t) */
+            const double lnphi = log1p(-q);                /* ln Phi(t) */
+            const double phi = exp(-0.5 * t * t) * ORACLE_INV_SQRT_2PI;
+            const double mills = phi / (1.0 - q); /* phi(t)/Phi(t) */
+            const double resid = yij - delta;
+            /* r_ij of Eq. (2) */
+            const double r = resid * resid / (2.0 * s2) + lnphi;
+            nsum_add(&sr, r);
+            nsum_add(&sr_abs, fabs(r));
+            /* the bracket of Eq. (9) */
+            const double w = (delta - yij) / s2 + mills / sigma;
+            nsum_add(&a[i], fabs(w));
+            nsum_add(&a[j], fabs(w));
+            if (delta > 0.0) {
+                for (int k = 0; k < d; ++k) {
+                    const double c = w * (u[k] / delta);
+                    nsum_add(&g[i * d + k], -c); /* row i: -w (x_i - x_j)/delta */
+                    nsum_add(&g[j * d + k], c);  /* row j: the same pair, mirrored */
+                }
+            }
+            /* d r_ij / d sigma, negated: contribution to dL/dsigma */
+            const double ds = resid * resid / (s2 * sigma) + (delta / s2) * mills;
+            nsum_add(&ss, ds);
+            nsum_add(&ss_abs, fabs(ds));
+        }
+    }
+    free(u);
+
+    const double lns = log(sigma);
+    if (loglik) {
+        /* L = -M ln sigma - sum r: the sum is exact-compensated, the final
+         * combination is one rounding */
+        *loglik = -(double)m * lns - nsum_get(&sr);
+        if (m == 0) *loglik = 0.0;
+    }
+    if (dsigma) *dsigma = (m == 0) ? 0.0 : -(double)m / sigma + nsum_get(&ss);
+    if (abs_l) *abs_l = nsum_get(&sr_abs) + (double)m * fabs(lns);
+    if (abs_ds) *abs_ds = nsum_get(&ss_abs) + (double)m / sigma;
+    if (grad)
+        for (int64_t k = 0; k < n * d; ++k) grad[k] = nsum_get(&g[k]);
+    if (absrow)
+        for (int64_t k = 0; k < n; ++k) absrow[k] = nsum_get(&a[k]);
+    if (m_obs) *m_obs = m;
+    free(g);
+    free(a);
+    return 0;
+}
+
+/* ----------------------------------------------------------- leapfrog -- */
+
+/* gradient of the HMC target log pi(x) = L(x) - (lambda/2)||x||^2 */
+static int target_grad(int64_t n, int d, const double* x, const double* y, int64_t ldy,
+                       const unsigned char* mask, int64_t ldm, double sigma, double lambda,
+                       double* g, double* loglik)
+{
+    int rc = oracle_eval(n, d, x, d, y, ldy, mask, ldm, sigma, loglik, g, NULL, NULL, NULL,
+                         NULL, NULL);
+    if (rc) return rc;
+    if (lambda != 0.0)
+        for (int64_t k = 0; k < n * d; ++k) g[k] -= lambda * x[k];
+    return 0;
+}
+
+/*
+ * One leapfrog trajectory of n_steps steps (Section 2.3).  x and p are n*d
+ * contiguous and are updated in place.  inv_mass is an optional n*d diagonal
+ * of M^{-1} (NULL = identity).  The momentum update uses p_dot = grad log pi
+ * (Eq. 7): half kick, then n_steps-1 pairs of (drift, full kick), then a last
+ * drift and half kick.
+ *
+ * Outputs (each may be NULL): grad_end = grad log pi at the final x,
+ * loglik_start / loglik_end = L at the first and final x, and
+ * energy_start / energy_end = H = -log pi(x) + p^T M^{-1} p / 2 (Eq. 6)
+ * before and after the trajectory.
+ */
+int oracle_leapfrog(int64_t n, int d, double* x, double* p, const double* y, int64_t ldy,
+                    const unsigned char* mask, int64_t ldm, double sigma,
+                    const double* inv_mass, double eps, double lambda, int n_steps,
+                    double* grad_end, double* loglik_start, double* loglik_end,
+                    double* energy_start, double* energy_end)
+{
+    if (n < 0 || d < 1 || n_steps < 0) return -1;
+    const int64_t nd = n * d;
+    double* g = (double*)malloc(sizeof(double) * (size_t)(nd > 0 ? nd : 1));
+    if (!g) return -1;
+    double L = 0.0;
+    int rc = target_grad(n, d, x, y, ldy, mask, ldm, sigma, lambda, g, &L);
+    if (rc) {
+        free(g);
+        return rc;
+    }
+
+    /* H = -log pi + kinetic, both as compensated sums */
+    nsum kin = {0, 0}, pri = {0, 0};
+    for (int64_t k = 0; k < nd; ++k) {
+        const double im = inv_mass ? inv_mass[k] : 1.0;
+        nsum_add(&kin, 0.5 * p[k] * p[k] * im);
+        nsum_add(&pri, 0.5 * lambda * x[k] * x[k]);
+    }
+    if (loglik_start) *loglik_start = L;
+    if (energy_start) *energy_start = -(L - nsum_get(&pri)) + nsum_get(&kin);
+
+    if (n_steps > 0) {
+        for (int64_t k = 0; k < nd; ++k) p[k] += 0.5 * eps * g[k];
+        for (int s = 1; s <= n_steps; ++s) {
+            for (int64_t k = 0; k < nd; ++k) x[k] += eps * (inv_mass ? inv_mass[k] : 1.0) * p[k];
+            rc = target_grad(n, d, x, y, ldy, mask, ldm, sigma, lambda, g, &L);
+            if (rc) {
+                free(g);
+                return rc;
+            }
+            const double c = (s < n_steps) ? eps : 0.5 * eps;
+            for (int64_t k = 0; k < nd; ++k) p[k] += c * g[k];
+        }
+    }
+
+    nsum kin2 = {0, 0}, pri2 = {0, 0};
+    for (int64_t k = 0; k < nd; ++k) {
+        const double im = inv_mass ? inv_mass[k] : 1.0;
+        nsum_add(&kin2, 0.5 * p[k] * p[k] * im);
+        nsum_add(&pri2, 0.5 * lambda * x[k] * x[k]);
+    }
+    if (loglik_end) *loglik_end = L;
+    if (energy_end) *energy_end = -(L - nsum_get(&pri2)) + nsum_get(&kin2);
+    if (grad_end) memcpy(grad_end, g, sizeof(double) * (size_t)nd);
+    free(g);
+    return 0;
+}
