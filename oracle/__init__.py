@@ -64,6 +64,10 @@ def _load():
                                     ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
                                     _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                     _dp, _dp, _dp, _dp, _dp]
+    lib.oracle_grad_rows.restype = ctypes.c_int
+    lib.oracle_grad_rows.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
+                                     ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
+                                     _i64p, ctypes.c_int64, _dp, _dp]
     _lib = lib
     return lib
 
@@ -146,6 +150,24 @@ def evaluate(x, y, sigma: float, mask=None) -> Evaluation:
     if rc != 0:
         raise ValueError("oracle_eval rejected its arguments")
     return Evaluation(out[0], grad, out[1], absrow, out[2], out[3], int(mobs.value))
+
+
+def grad_rows(x, y, sigma: float, rows, mask=None):
+    """Gradient rows (Eq. 9) of the listed points only, and their A_i scales."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n, d = x.shape
+    y = _as_y(y)
+    m = _as_mask(mask, n)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    g = np.zeros((rows.size, d), dtype=np.float64)
+    a = np.zeros(rows.size, dtype=np.float64)
+    rc = lib.oracle_grad_rows(n, d, _ptr(x), d, _ptr(y), y.shape[1], _ptr(m, _u8p),
+                              n if m is not None else 0, float(sigma), _ptr(rows, _i64p),
+                              rows.size, _ptr(g), _ptr(a))
+    if rc != 0:
+        raise ValueError("oracle_grad_rows rejected its arguments")
+    return g, a
 
 
 @dataclass

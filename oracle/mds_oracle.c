@@ -304,3 +304,62 @@ int oracle_leapfrog(int64_t n, int d, double* x, double* p, const double* y, int
     free(g);
     return 0;
 }
+
+/* ------------------------------------------------------- sampled rows -- */
+
+/*
+ * Gradient rows of Eq. (9) for a subset of points only, for checks at sizes
+ * where the full O(N^2) pass is too slow: for each listed row i, the sum over
+ * every observed j != i of -w_ij (x_i - x_j)/delta_ij, with y_ij read from
+ * the lower triangle (row max(i,j), column min(i,j)).  Also returns
+ * A_i = sum_j |w_ij|.  grad_rows is nrows*d contiguous.
+ */
+int oracle_grad_rows(int64_t n, int d, const double* x, int64_t ldx, const double* y,
+                     int64_t ldy, const unsigned char* mask, int64_t ldm, double sigma,
+                     const int64_t* rows, int64_t nrows, double* grad_rows, double* absrow)
+{
+    if (n < 0 || d < 1 || ldx < d || (n > 0 && ldy < n)) return -1;
+    double* u = (double*)malloc(sizeof(double) * (size_t)d);
+    nsum* g = (nsum*)calloc((size_t)d, sizeof(nsum));
+    if (!u || !g) {
+        free(u);
+        free(g);
+        return -1;
+    }
+    const double s2 = sigma * sigma;
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t i = rows[r];
+        if (i < 0 || i >= n) {
+            free(u);
+            free(g);
+            return -1;
+        }
+        memset(g, 0, sizeof(nsum) * (size_t)d);
+        nsum a = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const int64_t hi = i > j ? i : j, lo = i > j ? j : i;
+            if (!pair_observed(hi, lo, y, ldy, mask, ldm)) continue;
+            const double yij = y[hi * ldy + lo];
+            double dd = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double diff = x[i * ldx + k] - x[j * ldx + k];
+                u[k] = diff;
+                dd += diff * diff;
+            }
+            const double delta = sqrt(dd);
+            const double t = delta / sigma;
+            const double q = 0.5 * erfc(t / ORACLE_SQRT2);
+            const double mills = exp(-0.5 * t * t) * ORACLE_INV_SQRT_2PI / (1.0 - q);
+            const double w = (delta - yij) / s2 + mills / sigma;
+            nsum_add(&a, fabs(w));
+            if (delta > 0.0)
+                for (int k = 0; k < d; ++k) nsum_add(&g[k], -w * (u[k] / delta));
+        }
+        for (int k = 0; k < d; ++k) grad_rows[r * d + k] = nsum_get(&g[k]);
+        if (absrow) absrow[r] = nsum_get(&a);
+    }
+    free(u);
+    free(g);
+    return 0;
+}

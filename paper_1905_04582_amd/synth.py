@@ -23,6 +23,7 @@ Recipe (one problem):
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -69,20 +70,35 @@ def _mirror_lower(a):
             a[j0:j1, i0:i1] = a[i0:i1, j0:j1].T
 
 
-def truncated_normal_y(x_true, sigma, rng):
-    """Symmetric Y with y_ij ~ N(delta_ij, sigma^2) I(y_ij > 0) for i > j."""
+def _tn_block(delta, u, sigma):
+    lo = ndtr(-delta / sigma)           # P(y <= 0) under N(delta, sigma^2), <= 1/2
+    z = ndtri(np.clip(lo + u * (1.0 - lo), 1e-300, 1.0 - 2.0 ** -53))
+    return np.maximum(delta + sigma * z, np.finfo(np.float64).tiny)
+
+
+def truncated_normal_y(x_true, sigma, rng, threads: int = 8):
+    """Symmetric Y with y_ij ~ N(delta_ij, sigma^2) I(y_ij > 0) for i > j.
+    The uniforms are consumed row by row over j < i (row-major order of the
+    packed lower triangle), whatever the block size used to draw them; the
+    inverse-CDF transform of each block then runs on a thread pool."""
     n = x_true.shape[0]
     y = np.zeros((n, n), dtype=np.float64)
-    for i0 in range(1, n, _ROW_BLOCK):
-        i1 = min(n, i0 + _ROW_BLOCK)
+
+    def work(i0, i1, u):
         dist = cdist(x_true[i0:i1], x_true[:i1])
-        for r, i in enumerate(range(i0, i1)):
-            delta = dist[r, :i]
-            u = rng.random(i)
-            lo = ndtr(-delta / sigma)           # P(y <= 0) under N(delta, sigma^2)
-            hi = ndtr(delta / sigma)            # 1 - lo, without cancellation
-            z = ndtri(np.clip(lo + u * hi, 1e-300, 1.0 - 2.0 ** -53))
-            y[i, :i] = np.maximum(delta + sigma * z, np.finfo(np.float64).tiny)
+        lower = np.arange(i1)[None, :] < np.arange(i0, i1)[:, None]
+        blk = np.zeros((i1 - i0, i1), dtype=np.float64)
+        blk[lower] = _tn_block(dist[lower], u, sigma)
+        y[i0:i1, :i1] = blk
+
+    with cf.ThreadPoolExecutor(max(1, threads)) as ex:
+        futs = []
+        for i0 in range(1, n, _ROW_BLOCK):
+            i1 = min(n, i0 + _ROW_BLOCK)
+            cnt = (i1 - i0) * (i0 + i1 - 1) // 2        # sum of i over the block's rows
+            futs.append(ex.submit(work, i0, i1, rng.random(cnt)))
+        for f in futs:
+            f.result()
     _mirror_lower(y)
     np.fill_diagonal(y, 0.0)
     return y
@@ -92,8 +108,12 @@ def symmetric_mask(n, rate, rng):
     if rate <= 0.0:
         return None
     m = np.zeros((n, n), dtype=np.uint8)
-    for i in range(1, n):
-        m[i, :i] = rng.random(i) < rate
+    for i0 in range(1, n, _ROW_BLOCK):
+        i1 = min(n, i0 + _ROW_BLOCK)
+        lower = np.arange(i1)[None, :] < np.arange(i0, i1)[:, None]
+        blk = np.zeros((i1 - i0, i1), dtype=np.uint8)
+        blk[lower] = rng.random(int(lower.sum())) < rate
+        m[i0:i1, :i1] = blk
     _mirror_lower(m)
     np.fill_diagonal(m, 0)
     return m

@@ -352,3 +352,16 @@ def test_leapfrog_unit_mass_matches_explicit_identity():
     im[0, 0] = 0.0
     c = oracle.leapfrog(x, p, y, 0.5, eps=1e-3, n_steps=5, inv_mass=im)
     assert c.x[0, 0] == x[0, 0]
+
+
+def test_grad_rows_vs_brute_force():
+    # the per-row oracle (for sampled checks at large N) against mpmath
+    x, y, mask = _rand_problem(8, 3, 0.4, 25, missing=0.2, nan_frac=0.1)
+    ref = mpr.brute_force(x, y, 0.4, mask)
+    rows = [0, 3, 7]
+    g, a = oracle.grad_rows(x, y, 0.4, rows, mask)
+    ev = oracle.evaluate(x, y, 0.4, mask)
+    for r, i in enumerate(rows):
+        gref = np.array([float(v) for v in ref["grad"][i]])
+        assert np.max(np.abs(g[r] - gref)) <= 1e-14 * ev.absrow[i]
+        assert a[r] == pytest.approx(ev.absrow[i], rel=1e-15)
