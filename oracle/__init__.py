@@ -58,7 +58,7 @@ def _load():
     lib.oracle_eval.restype = ctypes.c_int
     lib.oracle_eval.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
                                 ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
-                                _dp, _dp, _dp, _dp, _dp, _dp, _i64p]
+                                _dp, _dp, _dp, _dp, _dp, _dp, _dp, _i64p]
     lib.oracle_leapfrog.restype = ctypes.c_int
     lib.oracle_leapfrog.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, _dp, _dp,
                                     ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
@@ -67,7 +67,7 @@ def _load():
     lib.oracle_grad_rows.restype = ctypes.c_int
     lib.oracle_grad_rows.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
                                      ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
-                                     _i64p, ctypes.c_int64, _dp, _dp]
+                                     _i64p, ctypes.c_int64, _dp, _dp, _dp]
     _lib = lib
     return lib
 
@@ -121,7 +121,8 @@ class Evaluation:
     loglik: float
     grad: np.ndarray      # N x D
     dsigma: float
-    absrow: np.ndarray    # N: sum_j |w_ij|, the scale of each gradient row
+    absrow: np.ndarray    # N: A_i = sum_j |w_ij|
+    condrow: np.ndarray   # N: B_i = sum_j (delta+|y|)/sigma^2 + m/sigma, row rounding scale
     abs_loglik: float     # sum |r_ij| + M |ln sigma|
     abs_dsigma: float     # sum |d r_ij/d sigma| + M / sigma
     m_obs: int
@@ -139,21 +140,22 @@ def evaluate(x, y, sigma: float, mask=None) -> Evaluation:
     m = _as_mask(mask, n)
     grad = np.zeros((n, d), dtype=np.float64)
     absrow = np.zeros(n, dtype=np.float64)
+    condrow = np.zeros(n, dtype=np.float64)
     out = (ctypes.c_double * 5)()
     mobs = ctypes.c_int64(0)
     rc = lib.oracle_eval(n, d, _ptr(x), d, _ptr(y), y.shape[1], _ptr(m, _u8p),
                          n if m is not None else 0, float(sigma),
                          ctypes.cast(ctypes.byref(out, 0), _dp), _ptr(grad),
-                         ctypes.cast(ctypes.byref(out, 8), _dp), _ptr(absrow),
+                         ctypes.cast(ctypes.byref(out, 8), _dp), _ptr(absrow), _ptr(condrow),
                          ctypes.cast(ctypes.byref(out, 16), _dp),
                          ctypes.cast(ctypes.byref(out, 24), _dp), ctypes.byref(mobs))
     if rc != 0:
         raise ValueError("oracle_eval rejected its arguments")
-    return Evaluation(out[0], grad, out[1], absrow, out[2], out[3], int(mobs.value))
+    return Evaluation(out[0], grad, out[1], absrow, condrow, out[2], out[3], int(mobs.value))
 
 
 def grad_rows(x, y, sigma: float, rows, mask=None):
-    """Gradient rows (Eq. 9) of the listed points only, and their A_i scales."""
+    """Gradient rows (Eq. 9) of the listed points only, with their A_i and B_i."""
     lib = _load()
     x = np.ascontiguousarray(x, dtype=np.float64)
     n, d = x.shape
@@ -162,12 +164,13 @@ def grad_rows(x, y, sigma: float, rows, mask=None):
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     g = np.zeros((rows.size, d), dtype=np.float64)
     a = np.zeros(rows.size, dtype=np.float64)
+    b = np.zeros(rows.size, dtype=np.float64)
     rc = lib.oracle_grad_rows(n, d, _ptr(x), d, _ptr(y), y.shape[1], _ptr(m, _u8p),
                               n if m is not None else 0, float(sigma), _ptr(rows, _i64p),
-                              rows.size, _ptr(g), _ptr(a))
+                              rows.size, _ptr(g), _ptr(a), _ptr(b))
     if rc != 0:
         raise ValueError("oracle_grad_rows rejected its arguments")
-    return g, a
+    return g, a, b
 
 
 @dataclass

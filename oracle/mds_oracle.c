@@ -126,7 +126,11 @@ int64_t oracle_count_observed(int64_t n, const double* y, int64_t ldy,
  *   loglik    L
  *   grad      n*d row-major, contiguous: dL/dx_i
  *   dsigma    dL/dsigma
- *   absrow    n values: A_i = sum_j |w_ij|, the scale of row i's sum
+ *   absrow    n values: A_i = sum_j |w_ij|
+ *   condrow   n values: B_i = sum_j [(delta_ij + |y_ij|)/sigma^2 + m_ij/sigma],
+ *             the rounding scale of row i: w_ij = (delta - y)/sigma^2 + m/sigma
+ *             subtracts two terms of size delta/sigma^2, so any 1-ulp change
+ *             of delta moves w_ij by ~eps*delta/sigma^2 even when w_ij ~ 0
  *   abs_l     sum_j |r_ij| + M |ln sigma|, the scale of L's sum
  *   abs_ds    sum |dsigma terms| + M / sigma, the scale of dL/dsigma's sum
  *   m_obs     number of observed pairs
@@ -135,19 +139,22 @@ int64_t oracle_count_observed(int64_t n, const double* y, int64_t ldy,
 int oracle_eval(int64_t n, int d, const double* x, int64_t ldx, const double* y,
                 int64_t ldy, const unsigned char* mask, int64_t ldm, double sigma,
                 double* loglik, double* grad, double* dsigma, double* absrow,
-                double* abs_l, double* abs_ds, int64_t* m_obs)
+                double* condrow, double* abs_l, double* abs_ds, int64_t* m_obs)
 {
     if (n < 0 || d < 1 || ldx < d || (n > 0 && ldy < n)) return -1;
     if (mask && n > 0 && ldm < n) return -1;
 
     nsum* g = NULL;
     nsum* a = NULL;
+    nsum* b = NULL;
     if (n > 0) {
         g = (nsum*)calloc((size_t)(n * d), sizeof(nsum));
         a = (nsum*)calloc((size_t)n, sizeof(nsum));
-        if (!g || !a) {
+        b = (nsum*)calloc((size_t)n, sizeof(nsum));
+        if (!g || !a || !b) {
             free(g);
             free(a);
+            free(b);
             return -1;
         }
     }
@@ -157,6 +164,7 @@ int oracle_eval(int64_t n, int d, const double* x, int64_t ldx, const double* y,
     if (!u) {
         free(g);
         free(a);
+        free(b);
         return -1;
     }
 
@@ -189,6 +197,9 @@ int oracle_eval(int64_t n, int d, const double* x, int64_t ldx, const double* y,
             const double w = (delta - yij) / s2 + mills / sigma;
             nsum_add(&a[i], fabs(w));
             nsum_add(&a[j], fabs(w));
+            const double cw = (delta + fabs(yij)) / s2 + mills / sigma;
+            nsum_add(&b[i], cw);
+            nsum_add(&b[j], cw);
             if (delta > 0.0) {
                 for (int k = 0; k < d; ++k) {
                     const double c = w * (u[k] / delta);
@@ -218,9 +229,12 @@ int oracle_eval(int64_t n, int d, const double* x, int64_t ldx, const double* y,
         for (int64_t k = 0; k < n * d; ++k) grad[k] = nsum_get(&g[k]);
     if (absrow)
         for (int64_t k = 0; k < n; ++k) absrow[k] = nsum_get(&a[k]);
+    if (condrow)
+        for (int64_t k = 0; k < n; ++k) condrow[k] = nsum_get(&b[k]);
     if (m_obs) *m_obs = m;
     free(g);
     free(a);
+    free(b);
     return 0;
 }
 
@@ -232,7 +246,7 @@ static int target_grad(int64_t n, int d, const double* x, const double* y, int64
                        double* g, double* loglik)
 {
     int rc = oracle_eval(n, d, x, d, y, ldy, mask, ldm, sigma, loglik, g, NULL, NULL, NULL,
-                         NULL, NULL);
+                         NULL, NULL, NULL);
     if (rc) return rc;
     if (lambda != 0.0)
         for (int64_t k = 0; k < n * d; ++k) g[k] -= lambda * x[k];
@@ -312,11 +326,13 @@ int oracle_leapfrog(int64_t n, int d, double* x, double* p, const double* y, int
  * where the full O(N^2) pass is too slow: for each listed row i, the sum over
  * every observed j != i of -w_ij (x_i - x_j)/delta_ij, with y_ij read from
  * the lower triangle (row max(i,j), column min(i,j)).  Also returns
- * A_i = sum_j |w_ij|.  grad_rows is nrows*d contiguous.
+ * A_i = sum_j |w_ij| and the rounding scale B_i of oracle_eval.  grad_rows
+ * is nrows*d contiguous.
  */
 int oracle_grad_rows(int64_t n, int d, const double* x, int64_t ldx, const double* y,
                      int64_t ldy, const unsigned char* mask, int64_t ldm, double sigma,
-                     const int64_t* rows, int64_t nrows, double* grad_rows, double* absrow)
+                     const int64_t* rows, int64_t nrows, double* grad_rows, double* absrow,
+                     double* condrow)
 {
     if (n < 0 || d < 1 || ldx < d || (n > 0 && ldy < n)) return -1;
     double* u = (double*)malloc(sizeof(double) * (size_t)d);
@@ -335,7 +351,7 @@ int oracle_grad_rows(int64_t n, int d, const double* x, int64_t ldx, const doubl
             return -1;
         }
         memset(g, 0, sizeof(nsum) * (size_t)d);
-        nsum a = {0, 0};
+        nsum a = {0, 0}, b = {0, 0};
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
             const int64_t hi = i > j ? i : j, lo = i > j ? j : i;
@@ -353,11 +369,13 @@ int oracle_grad_rows(int64_t n, int d, const double* x, int64_t ldx, const doubl
             const double mills = exp(-0.5 * t * t) * ORACLE_INV_SQRT_2PI / (1.0 - q);
             const double w = (delta - yij) / s2 + mills / sigma;
             nsum_add(&a, fabs(w));
+            nsum_add(&b, (delta + fabs(yij)) / s2 + mills / sigma);
             if (delta > 0.0)
                 for (int k = 0; k < d; ++k) nsum_add(&g[k], -w * (u[k] / delta));
         }
         for (int k = 0; k < d; ++k) grad_rows[r * d + k] = nsum_get(&g[k]);
         if (absrow) absrow[r] = nsum_get(&a);
+        if (condrow) condrow[r] = nsum_get(&b);
     }
     free(u);
     free(g);

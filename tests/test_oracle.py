@@ -359,9 +359,17 @@ def test_grad_rows_vs_brute_force():
     x, y, mask = _rand_problem(8, 3, 0.4, 25, missing=0.2, nan_frac=0.1)
     ref = mpr.brute_force(x, y, 0.4, mask)
     rows = [0, 3, 7]
-    g, a = oracle.grad_rows(x, y, 0.4, rows, mask)
+    g, a, b = oracle.grad_rows(x, y, 0.4, rows, mask)
     ev = oracle.evaluate(x, y, 0.4, mask)
     for r, i in enumerate(rows):
         gref = np.array([float(v) for v in ref["grad"][i]])
         assert np.max(np.abs(g[r] - gref)) <= 1e-14 * ev.absrow[i]
         assert a[r] == pytest.approx(ev.absrow[i], rel=1e-15)
+        assert b[r] == pytest.approx(ev.condrow[i], rel=1e-15)
+
+
+def test_row_rounding_scale_bounds_the_row():
+    # B_i = sum (delta + |y|)/sigma^2 + m/sigma bounds every |w_ij|, so B_i >= A_i
+    x, y, mask = _rand_problem(40, 2, 0.3, 26, missing=0.1)
+    ev = oracle.evaluate(x, y, 0.3, mask)
+    assert np.all(ev.condrow >= ev.absrow) and np.all(ev.absrow >= np.abs(ev.grad).max(axis=1))
