@@ -1,0 +1,202 @@
+/*
+ * massivemds.h -- C-ABI of libmassivemds, the MI355X (gfx950) hot path of
+ * Bayesian multidimensional scaling fitted by Hamiltonian Monte Carlo, after
+ * Holbrook et al., "Massive parallelization boosts big Bayesian
+ * multidimensional scaling" (arXiv:1905.04582).
+ *
+ * What it computes.  For N latent locations x_1..x_N in R^D (rows of X) and a
+ * symmetric dissimilarity matrix Y, every unordered pair i > j contributes
+ *     r_ij = (y_ij - delta_ij)^2 / (2 sigma^2) + ln Phi(delta_ij / sigma),
+ *     delta_ij = ||x_i - x_j||_2,
+ * and the log-likelihood of the truncated-normal observation model (Section
+ * 2.1, Eq. 1 and Eq. 2) is
+ *     L = -M ln sigma - sum_{observed i > j} r_ij,
+ * with M the number of observed pairs and the 2*pi constant dropped (the
+ * proportionality of Eq. 2).  The gradient rows are Eq. (9):
+ *     dL/dx_i = -sum_{j != i} w_ij (x_i - x_j) / delta_ij,
+ *     w_ij = (delta_ij - y_ij) / sigma^2 + phi(t) / (sigma Phi(t)), t = delta_ij/sigma,
+ * and dL/dsigma = -M/sigma + sum [(y - delta)^2 / sigma^3 + delta phi(t)/(sigma^2 Phi(t))].
+ * A coincident pair (delta = 0) contributes ln Phi(0) = -ln 2 to L and
+ * nothing to the gradient.  With no observed pair, L = 0 and every
+ * derivative is 0.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns an int status (MDS_OK or a negative MDS_ERR_*); the
+ *     detail of the last failure on the calling thread is in mds_last_error().
+ *     No C++ exception crosses this interface.
+ *   - Arguments are validated on the host before any HIP call; a rejected
+ *     call has no side effects.
+ *   - Array arguments are DEVICE pointers owned by the caller; they must stay
+ *     valid until the work enqueued on `stream` has completed.  Scalars that
+ *     may change between replays of a captured graph (sigma, the step size,
+ *     the upstream gradient scale, the prior precision) are device pointers
+ *     to one double.
+ *   - Every call is asynchronous on `stream` (NULL = the default stream),
+ *     writes its results to device memory, never synchronises and never
+ *     allocates: scratch memory is the caller's workspace, sized by
+ *     mds_workspace_bytes().  Calls are therefore capturable into a HIP
+ *     graph.  Calls that run concurrently need distinct workspaces.
+ *   - X, the gradient, P and the mass diagonal are FP64.  Y is FP64
+ *     (MDS_F64: FP64 pair arithmetic) or FP32 (MDS_F32: FP32 pair arithmetic
+ *     with the pair difference formed and the sums finished in FP64).
+ *   - Y is N x N row-major with leading dimension ldy >= N elements; only its
+ *     strict lower triangle (row i > column j) is read, so Y must be
+ *     symmetric for the result to be the paper's.  NaN entries are missing
+ *     pairs (mds_prepare_y folds a mask into NaN).
+ *   - sigma must be finite and > 0; this is not checked on the device (the
+ *     value lives in device memory), a bad sigma yields NaN/Inf outputs.
+ *     NaN or Inf in X or in observed entries of Y propagate to the outputs.
+ *   - Results are deterministic: the same inputs on the same device give
+ *     bitwise identical outputs (fixed-order reductions, no float atomics).
+ *   - Pair tiling: `tile_rows` (rows per tile: 32, 64, 128 or 256) and
+ *     `tile_waves` (64-wide column groups per tile: 1, 2, 4 or 8) pick the
+ *     tile shape; 0 selects the built-in default for (dtype, D, N).  One of
+ *     tile_rows and 64*tile_waves must divide the other.  The workspace
+ *     must be sized with the same values.
+ */
+#ifndef MASSIVEMDS_H
+#define MASSIVEMDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status -- */
+enum mds_status {
+    MDS_OK = 0,
+    MDS_ERR_INVALID_ARGUMENT = -1, /* null pointer, bad size, bad stride, misalignment */
+    MDS_ERR_UNSUPPORTED = -2,      /* D outside 1..MDS_MAX_DIM, unknown dtype, bad tiling */
+    MDS_ERR_WORKSPACE_TOO_SMALL = -3,
+    MDS_ERR_HIP = -4 /* a HIP runtime call failed; mds_last_error() names it */
+};
+
+/* element types */
+enum mds_dtype { MDS_F64 = 0, MDS_F32 = 1 };
+
+#define MDS_MAX_DIM 8
+/* largest N accepted: tile and row indices are 32-bit on the device */
+#define MDS_MAX_N ((int64_t)1 << 30)
+/* workspace pointers must be aligned to this many bytes */
+#define MDS_WORKSPACE_ALIGN 256
+
+/* Human-readable name of a status code (static string). */
+const char* mds_status_string(int status);
+
+/* Detail of the last failed call on this thread ("" if none). */
+const char* mds_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int mds_version(void);
+
+/*
+ * Workspace size, in bytes, for mds_loglik / mds_gradient / mds_leapfrog on
+ * an N-point, D-dimensional problem with the given Y dtype and tiling
+ * (0 = default).  Writes *bytes; returns a status.
+ */
+int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
+                        int32_t tile_waves, size_t* bytes);
+
+/*
+ * Prepare Y for the sweeps (not part of the per-evaluation path).
+ *   y_src       N x N, dtype src_dtype, leading dimension ld_src (elements)
+ *   missing     optional N x N bytes, leading dimension ld_mask; non-zero
+ *               marks a missing pair (NULL = no mask).  Must be symmetric.
+ *   y_out       N x N, dtype out_dtype, leading dimension ldy; receives
+ *               y_src converted to out_dtype, with NaN where the mask is set
+ *               or y_src is NaN.  y_out may alias y_src only when the two
+ *               dtypes and leading dimensions are equal.
+ *   m_obs_dev   optional device int64: the number of observed pairs i > j.
+ * Missing data are not part of the paper's model; they are excluded from
+ * every sum and from M.
+ */
+int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src,
+                  const uint8_t* missing, int64_t ld_mask, void* y_out, int32_t out_dtype,
+                  int64_t ldy, int64_t n, int64_t* m_obs_dev, hipStream_t stream);
+
+/*
+ * Log-likelihood L of Eq. (2) (see the header comment).
+ *   x          N x D FP64, leading dimension ldx >= D
+ *   y          prepared Y (y_dtype, ldy)
+ *   sigma_dev  device double, sigma > 0
+ *   loglik_dev device double receiving L
+ */
+int mds_loglik(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
+               int32_t y_dtype, int64_t ldy, const double* sigma_dev, double* loglik_dev,
+               void* workspace, size_t workspace_bytes, int32_t tile_rows, int32_t tile_waves,
+               hipStream_t stream);
+
+/*
+ * Gradient of L with respect to X (Eq. 9), fused with L and dL/dsigma.
+ *   scale_dev  optional device double s (NULL = 1): every output is
+ *              multiplied by s (the upstream gradient of a reverse-mode
+ *              caller: grad = s dL/dX, dsigma = s dL/dsigma; loglik is NOT
+ *              scaled)
+ *   grad       N x D FP64, leading dimension ldg >= D: s * dL/dX
+ *   loglik_dev optional device double: L
+ *   dsigma_dev optional device double: s * dL/dsigma
+ */
+int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
+                 int32_t y_dtype, int64_t ldy, const double* sigma_dev, const double* scale_dev,
+                 double* grad, int64_t ldg, double* loglik_dev, double* dsigma_dev,
+                 void* workspace, size_t workspace_bytes, int32_t tile_rows,
+                 int32_t tile_waves, hipStream_t stream);
+
+/*
+ * One leapfrog trajectory of Hamiltonian Monte Carlo (Section 2.3, Eqs. 6-8)
+ * on the target log pi(X) = L(X) - (lambda/2) ||X||_F^2:
+ *     p += (eps/2) grad log pi(x);
+ *     n_steps - 1 times: x += eps M^{-1} p;  p += eps grad log pi(x);
+ *     x += eps M^{-1} p;  p += (eps/2) grad log pi(x).
+ *   x, p           N x D FP64 (leading dimensions ldx, ldp), updated in place
+ *   inv_mass       optional N x D FP64 contiguous diagonal of M^{-1} (NULL = I)
+ *   step_dev       device double eps
+ *   prior_dev      optional device double lambda >= 0 (NULL = 0)
+ *   n_steps        >= 0 (0: nothing moves, the outputs are still written)
+ *   grad_io        N x D FP64 contiguous: grad log pi at x.  If cache_valid
+ *                  is non-zero it must hold grad log pi(x) and loglik_io must
+ *                  hold L(x) on entry, and the first gradient is not
+ *                  recomputed.  On exit both describe the final x.
+ *   loglik_io      device double: L (likelihood only, no prior) at x
+ *   energy_start_dev, energy_end_dev
+ *                  optional device doubles: H = -log pi(x) + p^T M^{-1} p / 2
+ *                  (Eq. 6) before and after the trajectory
+ * The workspace is the one of mds_gradient for the same (n, d, y_dtype, tiling).
+ */
+int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_t ldp,
+                 const void* y, int32_t y_dtype, int64_t ldy, const double* sigma_dev,
+                 const double* inv_mass, const double* step_dev, const double* prior_dev,
+                 int32_t n_steps, double* grad_io, double* loglik_io, int32_t cache_valid,
+                 double* energy_start_dev, double* energy_end_dev, void* workspace,
+                 size_t workspace_bytes, int32_t tile_rows, int32_t tile_waves,
+                 hipStream_t stream);
+
+/*
+ * The device special functions of the sweeps, elementwise: ln Phi(t) and
+ * phi(t)/Phi(t) (Eq. 2 and Eq. 9) for any real t, in the arithmetic of
+ * `precision` (MDS_F64, or MDS_F32: t rounded to FP32 and FP32 arithmetic,
+ * with the far lower tail t < -5 evaluated in FP64 by its log-erfc form).
+ *   t, lnphi, mills   `count` FP64 values each (lnphi or mills may be NULL)
+ */
+int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count,
+                int32_t precision, hipStream_t stream);
+
+/*
+ * Diagnostics for benchmarks: while set (non-NULL), every pair-sweep kernel
+ * launched by this thread is bracketed by hipEventRecord(before, stream) and
+ * hipEventRecord(after, stream), so a caller can time the sweep kernel alone
+ * inside a larger sequence.  The events are the caller's (created with
+ * timing enabled) and are recorded again by every later sweep launch; pass
+ * NULL, NULL to stop.  Thread-local; no effect on results.
+ */
+int mds_set_sweep_events(hipEvent_t before, hipEvent_t after);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MASSIVEMDS_H */

@@ -1,0 +1,291 @@
+"""Thin ctypes binding of libmassivemds (include/massivemds.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  torch supplies device memory and the current stream.
+If the library is missing the binding raises -- there is no CPU fallback.
+
+Low-level functions carry the C names (``mds_loglik``, ``mds_gradient``,
+``mds_leapfrog``, ``mds_prepare_y``, ``mds_log_phi``, ``mds_workspace_bytes``);
+``MDSProblem`` bundles a prepared Y with its workspace.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmassivemds.so")
+
+MDS_OK = 0
+MDS_F64 = 0
+MDS_F32 = 1
+MDS_MAX_DIM = 8
+WORKSPACE_ALIGN = 256
+
+_c_i64 = ctypes.c_int64
+_c_i32 = ctypes.c_int32
+_vp = ctypes.c_void_p
+_lib = None
+
+
+class MDSError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where} failed with {status}: {detail}")
+        self.status = status
+
+
+def lib():
+    """Load libmassivemds.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built: run `python -m paper_1905_04582_amd.build` "
+            "(the MDS path has no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.mds_status_string.restype = ctypes.c_char_p
+    L.mds_status_string.argtypes = [ctypes.c_int]
+    L.mds_last_error.restype = ctypes.c_char_p
+    L.mds_last_error.argtypes = []
+    L.mds_version.restype = ctypes.c_int
+    L.mds_workspace_bytes.restype = ctypes.c_int
+    L.mds_workspace_bytes.argtypes = [_c_i64, _c_i32, _c_i32, _c_i32, _c_i32,
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    L.mds_prepare_y.restype = ctypes.c_int
+    L.mds_prepare_y.argtypes = [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _c_i32, _c_i64, _c_i64,
+                                _vp, _vp]
+    L.mds_loglik.restype = ctypes.c_int
+    L.mds_loglik.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i64, _vp, _vp, _vp,
+                             ctypes.c_size_t, _c_i32, _c_i32, _vp]
+    L.mds_gradient.restype = ctypes.c_int
+    L.mds_gradient.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i64, _vp, _vp, _vp,
+                               _c_i64, _vp, _vp, _vp, ctypes.c_size_t, _c_i32, _c_i32, _vp]
+    L.mds_leapfrog.restype = ctypes.c_int
+    L.mds_leapfrog.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i64, _vp, _c_i32, _c_i64,
+                               _vp, _vp, _vp, _vp, _c_i32, _vp, _vp, _c_i32, _vp, _vp, _vp,
+                               ctypes.c_size_t, _c_i32, _c_i32, _vp]
+    L.mds_log_phi.restype = ctypes.c_int
+    L.mds_log_phi.argtypes = [_vp, _vp, _vp, _c_i64, _c_i32, _vp]
+    L.mds_set_sweep_events.restype = ctypes.c_int
+    L.mds_set_sweep_events.argtypes = [_vp, _vp]
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != MDS_OK:
+        L = lib()
+        raise MDSError(status, where, f"{L.mds_status_string(status).decode()}: "
+                                      f"{L.mds_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype_code(dt: torch.dtype) -> int:
+    if dt == torch.float64:
+        return MDS_F64
+    if dt == torch.float32:
+        return MDS_F32
+    raise TypeError(f"unsupported dtype {dt}: Y is float64 or float32")
+
+
+def _dev_scalar(v, device):
+    if isinstance(v, torch.Tensor):
+        if v.dtype != torch.float64 or v.numel() != 1 or not v.is_cuda:
+            raise TypeError("device scalars are 1-element float64 CUDA tensors")
+        return v
+    return torch.tensor(float(v), dtype=torch.float64, device=device)
+
+
+def _check_mat(t, name, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 2 or (t.numel() > 0 and t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError(f"{name} must be 2-D with unit column stride")
+
+
+def _ld(t) -> int:
+    """Leading dimension of a 2-D tensor; torch reports 0 for empty ones."""
+    if t.shape[0] <= 1:
+        return max(int(t.stride(0)), int(t.shape[1]), 1)
+    return int(t.stride(0))
+
+
+def version() -> int:
+    return lib().mds_version()
+
+
+def mds_workspace_bytes(n: int, d: int, y_dtype: int, tile_rows: int = 0,
+                        tile_waves: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().mds_workspace_bytes(n, d, y_dtype, tile_rows, tile_waves, ctypes.byref(out)),
+           "mds_workspace_bytes")
+    return int(out.value)
+
+
+def alloc_workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), WORKSPACE_ALIGN) + WORKSPACE_ALIGN, dtype=torch.uint8,
+                     device=device)
+    off = (-ws.data_ptr()) % WORKSPACE_ALIGN
+    return ws[off:off + max(int(nbytes), WORKSPACE_ALIGN)]
+
+
+def padded_ld(n: int) -> int:
+    """Leading dimension of prepared Y: N rounded up to 64 elements."""
+    return max(64, (n + 63) // 64 * 64)
+
+
+def mds_prepare_y(y_src: torch.Tensor, out_dtype: torch.dtype = torch.float64, mask=None,
+                  ldy: int | None = None, count: bool = True, stream=None):
+    """Y -> device Y' in out_dtype with missing entries folded into NaN.
+    Returns (y_prepared N x ldy view, m_obs device int64 tensor or None)."""
+    _check_mat(y_src, "y_src", y_src.dtype)
+    n = y_src.shape[0]
+    if y_src.shape[1] < n:
+        raise ValueError("y_src must be N x N")
+    ldy = padded_ld(n) if ldy is None else int(ldy)
+    buf = torch.empty((max(n, 1), ldy), dtype=out_dtype, device=y_src.device)
+    if mask is not None:
+        _check_mat(mask, "mask", torch.uint8)
+    m_obs = torch.zeros((), dtype=torch.int64, device=y_src.device) if count else None
+    _check(lib().mds_prepare_y(_ptr(y_src), _dtype_code(y_src.dtype), _ld(y_src),
+                               _ptr(mask), _ld(mask) if mask is not None else 0,
+                               _ptr(buf), _dtype_code(out_dtype), ldy, n, _ptr(m_obs),
+                               _stream(stream)), "mds_prepare_y")
+    return buf[:n], m_obs
+
+
+def mds_loglik(x, y, sigma, workspace, out=None, tile_rows=0, tile_waves=0, stream=None):
+    _check_mat(x, "x")
+    _check_mat(y, "y", y.dtype)
+    n, d = x.shape
+    sig = _dev_scalar(sigma, x.device)
+    out = torch.empty((), dtype=torch.float64, device=x.device) if out is None else out
+    _check(lib().mds_loglik(n, d, _ptr(x), _ld(x), _ptr(y), _dtype_code(y.dtype),
+                            _ld(y), _ptr(sig), _ptr(out), _ptr(workspace),
+                            workspace.numel(), tile_rows, tile_waves, _stream(stream)),
+           "mds_loglik")
+    return out
+
+
+def mds_gradient(x, y, sigma, workspace, scale=None, grad=None, loglik=None, dsigma=None,
+                 want_loglik=True, want_dsigma=True, tile_rows=0, tile_waves=0, stream=None):
+    """Returns (grad N x D, loglik scalar or None, dsigma scalar or None)."""
+    _check_mat(x, "x")
+    _check_mat(y, "y", y.dtype)
+    n, d = x.shape
+    dev = x.device
+    sig = _dev_scalar(sigma, dev)
+    sc = None if scale is None else _dev_scalar(scale, dev)
+    grad = torch.empty((n, d), dtype=torch.float64, device=dev) if grad is None else grad
+    _check_mat(grad, "grad")
+    if want_loglik and loglik is None:
+        loglik = torch.empty((), dtype=torch.float64, device=dev)
+    if want_dsigma and dsigma is None:
+        dsigma = torch.empty((), dtype=torch.float64, device=dev)
+    _check(lib().mds_gradient(n, d, _ptr(x), _ld(x), _ptr(y), _dtype_code(y.dtype),
+                              _ld(y), _ptr(sig), _ptr(sc), _ptr(grad), _ld(grad),
+                              _ptr(loglik), _ptr(dsigma), _ptr(workspace), workspace.numel(),
+                              tile_rows, tile_waves, _stream(stream)), "mds_gradient")
+    return grad, loglik, dsigma
+
+
+def mds_leapfrog(x, p, y, sigma, step, n_steps, workspace, grad_io, loglik_io,
+                 cache_valid=False, inv_mass=None, prior=None, energy_start=None,
+                 energy_end=None, tile_rows=0, tile_waves=0, stream=None):
+    """In-place leapfrog trajectory on (x, p); grad_io/loglik_io are the
+    gradient/log-likelihood cache at x (read if cache_valid, always written)."""
+    for t, nm in ((x, "x"), (p, "p"), (grad_io, "grad_io")):
+        _check_mat(t, nm)
+    _check_mat(y, "y", y.dtype)
+    n, d = x.shape
+    if grad_io.shape != (n, d) or not grad_io.is_contiguous():
+        raise ValueError("grad_io must be a contiguous N x D float64 tensor")
+    if inv_mass is not None and (inv_mass.shape != (n, d) or not inv_mass.is_contiguous()
+                                 or inv_mass.dtype != torch.float64):
+        raise ValueError("inv_mass must be a contiguous N x D float64 tensor")
+    dev = x.device
+    sig = _dev_scalar(sigma, dev)
+    eps = _dev_scalar(step, dev)
+    lam = None if prior is None else _dev_scalar(prior, dev)
+    _check(lib().mds_leapfrog(n, d, _ptr(x), _ld(x), _ptr(p), _ld(p), _ptr(y),
+                              _dtype_code(y.dtype), _ld(y), _ptr(sig), _ptr(inv_mass),
+                              _ptr(eps), _ptr(lam), int(n_steps), _ptr(grad_io), _ptr(loglik_io),
+                              1 if cache_valid else 0, _ptr(energy_start), _ptr(energy_end),
+                              _ptr(workspace), workspace.numel(), tile_rows, tile_waves,
+                              _stream(stream)), "mds_leapfrog")
+
+
+def mds_log_phi(t: torch.Tensor, precision: int = MDS_F64, stream=None):
+    """(ln Phi(t), phi(t)/Phi(t)) elementwise on the device."""
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("t must be a contiguous float64 device tensor")
+    ln = torch.empty_like(t)
+    mi = torch.empty_like(t)
+    _check(lib().mds_log_phi(_ptr(t), _ptr(ln), _ptr(mi), t.numel(), precision,
+                             _stream(stream)), "mds_log_phi")
+    return ln, mi
+
+
+def mds_set_sweep_events(before, after):
+    """Bracket every later sweep launch of this thread with two raw hipEvent_t
+    handles (ints), or stop with (None, None).  Benchmark diagnostics only."""
+    _check(lib().mds_set_sweep_events(before, after), "mds_set_sweep_events")
+
+
+class MDSProblem:
+    """A prepared dissimilarity matrix on the device plus its workspace.
+
+    y      N x N (numpy or torch, any device), symmetric
+    mask   optional N x N, non-zero = missing
+    dtype  torch.float64 (FP64 form) or torch.float32 (FP32 form)
+    """
+
+    def __init__(self, y, d: int, mask=None, dtype=torch.float64, device="cuda",
+                 tile_rows: int = 0, tile_waves: int = 0):
+        y = torch.as_tensor(y)
+        n = y.shape[0]
+        src = y.to(device=device, dtype=torch.float64 if y.dtype == torch.float64 else
+                   torch.float32).contiguous()
+        m = None
+        if mask is not None:
+            m = (torch.as_tensor(mask) != 0).to(device=device, dtype=torch.uint8).contiguous()
+        self.n, self.d, self.dtype, self.device = n, int(d), dtype, torch.device(device)
+        self.y, self.m_obs = mds_prepare_y(src, dtype, m)
+        del src, m
+        self.tile_rows, self.tile_waves = tile_rows, tile_waves
+        self.ws_bytes = mds_workspace_bytes(n, self.d, _dtype_code(dtype), tile_rows, tile_waves)
+        self.workspace = alloc_workspace(self.ws_bytes, self.device)
+
+    def set_tiling(self, tile_rows: int, tile_waves: int):
+        nb = mds_workspace_bytes(self.n, self.d, _dtype_code(self.dtype), tile_rows, tile_waves)
+        if nb > self.workspace.numel():
+            self.workspace = alloc_workspace(nb, self.device)
+        self.tile_rows, self.tile_waves, self.ws_bytes = tile_rows, tile_waves, nb
+
+    def loglik(self, x, sigma, out=None, stream=None):
+        return mds_loglik(x, self.y, sigma, self.workspace, out, self.tile_rows,
+                          self.tile_waves, stream)
+
+    def gradient(self, x, sigma, scale=None, grad=None, loglik=None, dsigma=None, stream=None):
+        return mds_gradient(x, self.y, sigma, self.workspace, scale, grad, loglik, dsigma,
+                            tile_rows=self.tile_rows, tile_waves=self.tile_waves,
+                            stream=stream)
+
+    def leapfrog(self, x, p, sigma, step, n_steps, grad_io, loglik_io, cache_valid=False,
+                 inv_mass=None, prior=None, energy_start=None, energy_end=None, stream=None):
+        mds_leapfrog(x, p, self.y, sigma, step, n_steps, self.workspace, grad_io, loglik_io,
+                     cache_valid, inv_mass, prior, energy_start, energy_end, self.tile_rows,
+                     self.tile_waves, stream)

@@ -1,0 +1,395 @@
+// mds_api.hip -- host side of the C-ABI declared in include/massivemds.h:
+// argument validation (always before any HIP call), tiling defaults,
+// workspace carving and the launch sequences of each entry point.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "../../include/massivemds.h"
+#include "mds_internal.h"
+
+namespace mds {
+hipError_t launch_kick_drift(int64_t n, int d, double* x, int64_t ldx, double* p, int64_t ldp,
+                             const double* g, const double* inv_mass, const double* step,
+                             double mult, int drift, hipStream_t s);
+hipError_t launch_energy(int64_t n, int d, const double* x, int64_t ldx, const double* p,
+                         int64_t ldp, const double* inv_mass, const double* prior,
+                         const double* loglik, double* out, hipStream_t s);
+hipError_t launch_prepare(const void* src, int sdt, int64_t ld_src, const uint8_t* mask,
+                          int64_t ld_mask, void* out, int odt, int64_t ldy, int64_t n,
+                          int64_t* count, hipStream_t s);
+hipError_t launch_log_phi(const double* t, double* lnphi, double* mills, int64_t count, int prec,
+                          hipStream_t s);
+}  // namespace mds
+
+using namespace mds;
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;
+
+int fail(int status, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(MDS_ERR_HIP, "%s: %s (%s)", what, hipGetErrorName(e), hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+size_t dtype_size(int dt) { return dt == MDS_F64 ? 8 : 4; }
+
+// Largest LDS a sweep work-group may use (row sums of all its waves).
+constexpr size_t kMaxSweepLds = 64 * 1024;
+
+// Tile shape used when the caller passes 0: 64 rows x 256 columns keeps the
+// grid well above the 256 compute units for N >= ~4000 and the partial
+// buffers small; smaller problems use narrower tiles to fill the chip.
+void default_tiling(int64_t n, int d, int dtype, int* br, int* waves)
+{
+    (void)dtype;
+    (void)d;
+    if (n <= 2048) {
+        *br = 32;
+        *waves = 2;
+    } else if (n <= 8192) {
+        *br = 64;
+        *waves = 4;
+    } else {
+        *br = 128;
+        *waves = 4;
+    }
+}
+
+int resolve_tiling(int64_t n, int d, int dtype, int tile_rows, int tile_waves, Tiling* out)
+{
+    int br = tile_rows, waves = tile_waves;
+    if (br == 0 || waves == 0) {
+        int dbr, dw;
+        default_tiling(n, d, dtype, &dbr, &dw);
+        if (br == 0) br = dbr;
+        if (waves == 0) waves = dw;
+    }
+    if (br != 32 && br != 64 && br != 128 && br != 256)
+        return fail(MDS_ERR_UNSUPPORTED, "tile_rows=%d: must be 32, 64, 128 or 256", br);
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8)
+        return fail(MDS_ERR_UNSUPPORTED, "tile_waves=%d: must be 1, 2, 4 or 8", waves);
+    const int cw = kWave * waves;
+    if (!(br % cw == 0 || cw % br == 0))
+        return fail(MDS_ERR_UNSUPPORTED, "tile_rows=%d and 64*tile_waves=%d: neither divides the other",
+                    br, cw);
+    *out = make_tiling(n, br, waves);
+    if (sweep_lds_bytes(*out, d) > kMaxSweepLds)
+        return fail(MDS_ERR_UNSUPPORTED, "tile %dx%d with D=%d needs %zu B of LDS (max %zu)", br,
+                    cw, d, sweep_lds_bytes(*out, d), kMaxSweepLds);
+    return MDS_OK;
+}
+
+int check_problem(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
+                  int32_t y_dtype, int64_t ldy, const double* sigma_dev)
+{
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n=%lld out of [0, %lld]",
+                                            (long long)n, (long long)MDS_MAX_N);
+    if (d < 1 || d > MDS_MAX_DIM)
+        return fail(MDS_ERR_UNSUPPORTED, "d=%d: supported latent dimensions are 1..%d", d,
+                    MDS_MAX_DIM);
+    if (y_dtype != MDS_F64 && y_dtype != MDS_F32)
+        return fail(MDS_ERR_UNSUPPORTED, "y_dtype=%d: must be MDS_F64 or MDS_F32", y_dtype);
+    if (n > 0 && !x) return fail(MDS_ERR_INVALID_ARGUMENT, "x is NULL");
+    if (ldx < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldx=%lld < d=%d", (long long)ldx, d);
+    if (n > 1 && !y) return fail(MDS_ERR_INVALID_ARGUMENT, "y is NULL");
+    if (n > 0 && ldy < n)
+        return fail(MDS_ERR_INVALID_ARGUMENT, "ldy=%lld < n=%lld", (long long)ldy, (long long)n);
+    if (!sigma_dev) return fail(MDS_ERR_INVALID_ARGUMENT, "sigma_dev is NULL");
+    if (!aligned(x, 8) || !aligned(sigma_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "x and sigma_dev must be 8-byte aligned");
+    if (!aligned(y, dtype_size(y_dtype)))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "y is not aligned to its element size");
+    return MDS_OK;
+}
+
+int check_workspace(const Tiling& t, int d, const void* ws, size_t ws_bytes,
+                    WorkspaceLayout* lay)
+{
+    *lay = workspace_layout(t, d);
+    if (ws_bytes < lay->total)
+        return fail(MDS_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu B < %zu B needed", ws_bytes,
+                    lay->total);
+    if (lay->total > 0 && !ws) return fail(MDS_ERR_INVALID_ARGUMENT, "workspace is NULL");
+    if (!aligned(ws, MDS_WORKSPACE_ALIGN))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "workspace must be %d-byte aligned",
+                    MDS_WORKSPACE_ALIGN);
+    return MDS_OK;
+}
+
+// a sweep launch, bracketed by the diagnostic events when they are set
+hipError_t timed_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
+                       hipStream_t s)
+{
+    hipError_t e;
+    if (g_ev_before && (e = hipEventRecord(g_ev_before, s)) != hipSuccess) return e;
+    e = launch_sweep(y_dtype, d, grad, t, a, s);
+    if (e != hipSuccess) return e;
+    if (g_ev_after && (e = hipEventRecord(g_ev_after, s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+SweepArgs sweep_args(const Tiling& t, const WorkspaceLayout& lay, void* ws, int64_t n,
+                     const double* x, int64_t ldx, const void* y, int64_t ldy,
+                     const double* sigma)
+{
+    char* base = static_cast<char*>(ws);
+    SweepArgs a;
+    a.n = n;
+    a.x = x;
+    a.ldx = ldx;
+    a.y = y;
+    a.ldy = ldy;
+    a.sigma = sigma;
+    a.br = t.br;
+    a.cw = t.cw;
+    a.nrb = t.nrb;
+    a.rowpart = reinterpret_cast<double*>(base + lay.rowpart);
+    a.colpart = reinterpret_cast<double*>(base + lay.colpart);
+    a.tscal = reinterpret_cast<double*>(base + lay.tscal);
+    a.tcount = reinterpret_cast<uint32_t*>(base + lay.tcount);
+    return a;
+}
+
+FinalizeArgs finalize_args(const Tiling& t, const SweepArgs& s)
+{
+    FinalizeArgs f = {};
+    f.n = t.n;
+    f.br = t.br;
+    f.cw = t.cw;
+    f.nrb = t.nrb;
+    f.ntiles = t.ntiles;
+    f.rowpart = s.rowpart;
+    f.colpart = s.colpart;
+    f.tscal = s.tscal;
+    f.tcount = s.tcount;
+    f.sigma = s.sigma;
+    return f;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mds_status_string(int status)
+{
+    switch (status) {
+        case MDS_OK: return "MDS_OK";
+        case MDS_ERR_INVALID_ARGUMENT: return "MDS_ERR_INVALID_ARGUMENT";
+        case MDS_ERR_UNSUPPORTED: return "MDS_ERR_UNSUPPORTED";
+        case MDS_ERR_WORKSPACE_TOO_SMALL: return "MDS_ERR_WORKSPACE_TOO_SMALL";
+        case MDS_ERR_HIP: return "MDS_ERR_HIP";
+        default: return "MDS_UNKNOWN_STATUS";
+    }
+}
+
+const char* mds_last_error(void) { return g_last_error; }
+
+int mds_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
+                        int32_t tile_waves, size_t* bytes)
+{
+    if (!bytes) return fail(MDS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if (d < 1 || d > MDS_MAX_DIM) return fail(MDS_ERR_UNSUPPORTED, "d=%d unsupported", d);
+    if (y_dtype != MDS_F64 && y_dtype != MDS_F32)
+        return fail(MDS_ERR_UNSUPPORTED, "y_dtype=%d unsupported", y_dtype);
+    Tiling t;
+    int st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t);
+    if (st) return st;
+    *bytes = workspace_layout(t, d).total;
+    return MDS_OK;
+}
+
+int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src, const uint8_t* missing,
+                  int64_t ld_mask, void* y_out, int32_t out_dtype, int64_t ldy, int64_t n,
+                  int64_t* m_obs_dev, hipStream_t stream)
+{
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if ((src_dtype != MDS_F64 && src_dtype != MDS_F32) ||
+        (out_dtype != MDS_F64 && out_dtype != MDS_F32))
+        return fail(MDS_ERR_UNSUPPORTED, "dtype must be MDS_F64 or MDS_F32");
+    if (n > 0 && (!y_src || !y_out)) return fail(MDS_ERR_INVALID_ARGUMENT, "y_src/y_out NULL");
+    if (ld_src < n || ldy < n) return fail(MDS_ERR_INVALID_ARGUMENT, "leading dimension < n");
+    if (missing && ld_mask < n) return fail(MDS_ERR_INVALID_ARGUMENT, "ld_mask < n");
+    if (!aligned(y_src, dtype_size(src_dtype)) || !aligned(y_out, dtype_size(out_dtype)) ||
+        !aligned(m_obs_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    if (y_src == y_out && n > 0 && (src_dtype != out_dtype || ld_src != ldy))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "in-place prepare needs equal dtype and stride");
+    hipError_t e = launch_prepare(y_src, src_dtype, ld_src, missing, ld_mask, y_out, out_dtype,
+                                  ldy, n, m_obs_dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "prepare launch");
+    return MDS_OK;
+}
+
+int mds_loglik(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
+               int32_t y_dtype, int64_t ldy, const double* sigma_dev, double* loglik_dev,
+               void* workspace, size_t workspace_bytes, int32_t tile_rows, int32_t tile_waves,
+               hipStream_t stream)
+{
+    int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
+    if (st) return st;
+    if (!loglik_dev || !aligned(loglik_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "loglik_dev NULL or misaligned");
+    Tiling t;
+    if ((st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t))) return st;
+    WorkspaceLayout lay;
+    if ((st = check_workspace(t, d, workspace, workspace_bytes, &lay))) return st;
+
+    SweepArgs sa = sweep_args(t, lay, workspace, n, x, ldx, y, ldy, sigma_dev);
+    hipError_t e = timed_sweep(y_dtype, d, false, t, sa, stream);
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    FinalizeArgs fa = finalize_args(t, sa);
+    fa.loglik = loglik_dev;
+    e = launch_finalize(d, fa, stream);
+    if (e != hipSuccess) return hip_fail(e, "finalize launch");
+    return MDS_OK;
+}
+
+int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
+                 int32_t y_dtype, int64_t ldy, const double* sigma_dev, const double* scale_dev,
+                 double* grad, int64_t ldg, double* loglik_dev, double* dsigma_dev,
+                 void* workspace, size_t workspace_bytes, int32_t tile_rows,
+                 int32_t tile_waves, hipStream_t stream)
+{
+    int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
+    if (st) return st;
+    if (n > 0 && !grad) return fail(MDS_ERR_INVALID_ARGUMENT, "grad is NULL");
+    if (ldg < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldg=%lld < d=%d", (long long)ldg, d);
+    if (!aligned(grad, 8) || !aligned(loglik_dev, 8) || !aligned(dsigma_dev, 8) ||
+        !aligned(scale_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned output pointer");
+    Tiling t;
+    if ((st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t))) return st;
+    WorkspaceLayout lay;
+    if ((st = check_workspace(t, d, workspace, workspace_bytes, &lay))) return st;
+
+    SweepArgs sa = sweep_args(t, lay, workspace, n, x, ldx, y, ldy, sigma_dev);
+    hipError_t e = timed_sweep(y_dtype, d, true, t, sa, stream);
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    FinalizeArgs fa = finalize_args(t, sa);
+    fa.scale = scale_dev;
+    fa.grad = grad;
+    fa.ldg = ldg;
+    fa.loglik = loglik_dev;
+    fa.dsigma = dsigma_dev;
+    e = launch_finalize(d, fa, stream);
+    if (e != hipSuccess) return hip_fail(e, "finalize launch");
+    return MDS_OK;
+}
+
+int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_t ldp,
+                 const void* y, int32_t y_dtype, int64_t ldy, const double* sigma_dev,
+                 const double* inv_mass, const double* step_dev, const double* prior_dev,
+                 int32_t n_steps, double* grad_io, double* loglik_io, int32_t cache_valid,
+                 double* energy_start_dev, double* energy_end_dev, void* workspace,
+                 size_t workspace_bytes, int32_t tile_rows, int32_t tile_waves,
+                 hipStream_t stream)
+{
+    int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
+    if (st) return st;
+    if (n > 0 && (!p || !grad_io)) return fail(MDS_ERR_INVALID_ARGUMENT, "p or grad_io is NULL");
+    if (ldp < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldp=%lld < d=%d", (long long)ldp, d);
+    if (!loglik_io || !step_dev) return fail(MDS_ERR_INVALID_ARGUMENT, "loglik_io or step_dev NULL");
+    if (n_steps < 0) return fail(MDS_ERR_INVALID_ARGUMENT, "n_steps=%d < 0", n_steps);
+    if (!aligned(p, 8) || !aligned(grad_io, 8) || !aligned(loglik_io, 8) ||
+        !aligned(step_dev, 8) || !aligned(prior_dev, 8) || !aligned(inv_mass, 8) ||
+        !aligned(energy_start_dev, 8) || !aligned(energy_end_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    if (n > 0 && (x == p || x == grad_io || p == grad_io))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "x, p and grad_io must not alias");
+    Tiling t;
+    if ((st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t))) return st;
+    WorkspaceLayout lay;
+    if ((st = check_workspace(t, d, workspace, workspace_bytes, &lay))) return st;
+
+    SweepArgs sa = sweep_args(t, lay, workspace, n, x, ldx, y, ldy, sigma_dev);
+    hipError_t e;
+
+    // grad log pi and L at a point: sweep + finalize, optionally followed by
+    // a kick of mult*eps and a drift of eps, fused into the finalize
+    auto evaluate = [&](double mult, int kick, int drift) -> int {
+        hipError_t err = timed_sweep(y_dtype, d, true, t, sa, stream);
+        if (err != hipSuccess) return hip_fail(err, "sweep launch");
+        FinalizeArgs fa = finalize_args(t, sa);
+        fa.grad = grad_io;
+        fa.ldg = d;
+        fa.loglik = loglik_io;
+        fa.prior = prior_dev;
+        fa.x = x;
+        fa.ldx = ldx;
+        fa.p = kick ? p : nullptr;
+        fa.ldp = ldp;
+        fa.inv_mass = inv_mass;
+        fa.step = step_dev;
+        fa.kick_mult = mult;
+        fa.drift = drift;
+        err = launch_finalize(d, fa, stream);
+        if (err != hipSuccess) return hip_fail(err, "finalize launch");
+        return MDS_OK;
+    };
+
+    // first half kick (fused into the first evaluation when possible)
+    const bool fuse_first = !cache_valid && !energy_start_dev && n_steps > 0;
+    if (!cache_valid) {
+        if ((st = evaluate(0.5, fuse_first ? 1 : 0, fuse_first ? 1 : 0))) return st;
+    }
+    if (energy_start_dev) {
+        e = launch_energy(n, d, x, ldx, p, ldp, inv_mass, prior_dev, loglik_io, energy_start_dev,
+                          stream);
+        if (e != hipSuccess) return hip_fail(e, "energy launch");
+    }
+    if (n_steps > 0 && !fuse_first) {
+        e = launch_kick_drift(n, d, x, ldx, p, ldp, grad_io, inv_mass, step_dev, 0.5, 1, stream);
+        if (e != hipSuccess) return hip_fail(e, "kick launch");
+    }
+    for (int s = 1; s <= n_steps; ++s) {
+        const bool last = (s == n_steps);
+        if ((st = evaluate(last ? 0.5 : 1.0, 1, last ? 0 : 1))) return st;
+    }
+    if (energy_end_dev) {
+        e = launch_energy(n, d, x, ldx, p, ldp, inv_mass, prior_dev, loglik_io, energy_end_dev,
+                          stream);
+        if (e != hipSuccess) return hip_fail(e, "energy launch");
+    }
+    return MDS_OK;
+}
+
+int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count, int32_t precision,
+                hipStream_t stream)
+{
+    if (count < 0) return fail(MDS_ERR_INVALID_ARGUMENT, "count < 0");
+    if (count > 0 && !t) return fail(MDS_ERR_INVALID_ARGUMENT, "t is NULL");
+    if (precision != MDS_F64 && precision != MDS_F32)
+        return fail(MDS_ERR_UNSUPPORTED, "precision=%d unsupported", precision);
+    if (!aligned(t, 8) || !aligned(lnphi, 8) || !aligned(mills, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    hipError_t e = launch_log_phi(t, lnphi, mills, count, precision, stream);
+    if (e != hipSuccess) return hip_fail(e, "log_phi launch");
+    return MDS_OK;
+}
+
+int mds_set_sweep_events(hipEvent_t before, hipEvent_t after)
+{
+    if ((before == nullptr) != (after == nullptr))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "set both events or neither");
+    g_ev_before = before;
+    g_ev_after = after;
+    return MDS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// mds_internal.h -- tiling arithmetic and kernel launchers shared by the
+// translation units of libmassivemds (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mds {
+
+constexpr int kWave = 64;     // CDNA wavefront width
+constexpr int kRowBatch = 8;  // rows reduced together by the in-wave transpose-reduce
+
+// Tile geometry of the lower-triangle pair sweep.
+//
+// Rows (index i) are cut into blocks of `br`, columns (index j) into blocks
+// of `cw` = 64 * waves; one work-group owns one (row block, column block)
+// tile and each of its waves owns 64 consecutive columns.  A tile exists
+// when it can hold a pair with j < i.  With one of br and cw dividing the
+// other, row block r holds a closed-form number of tiles, so a linear tile
+// index maps back to (r, c) by a short binary search on the prefix count.
+struct Tiling {
+    int64_t n;
+    int br;     // rows per tile
+    int cw;     // columns per tile
+    int waves;  // cw / 64
+    int nrb;    // number of row blocks
+    int64_t ntiles;
+};
+
+__host__ __device__ inline int64_t tiles_in_row_block(int r, int br, int cw)
+{
+    if (br >= cw) return (int64_t)(r + 1) * (br / cw);
+    return (int64_t)(r / (cw / br)) + 1;
+}
+
+// number of tiles in row blocks 0..r-1
+__host__ __device__ inline int64_t tiles_before(int r, int br, int cw)
+{
+    if (br >= cw) {
+        const int64_t k = br / cw;
+        return k * (int64_t)r * (r + 1) / 2;
+    }
+    const int64_t k = cw / br;
+    const int64_t a = r / k, b = r % k;
+    return (int64_t)r + k * a * (a - 1) / 2 + a * b;
+}
+
+// first row block that holds a tile in column block c
+__host__ __device__ inline int first_row_block_of_column(int c, int br, int cw)
+{
+    if (br >= cw) return c / (br / cw);
+    return c * (cw / br);
+}
+
+inline Tiling make_tiling(int64_t n, int br, int waves)
+{
+    Tiling t;
+    t.n = n;
+    t.br = br;
+    t.waves = waves;
+    t.cw = kWave * waves;
+    t.nrb = (int)((n + br - 1) / br);
+    t.ntiles = tiles_before(t.nrb, br, t.cw);
+    return t;
+}
+
+// Workspace layout (each section aligned to 256 bytes).
+struct WorkspaceLayout {
+    size_t rowpart;  // ntiles * br * D doubles: row-side gradient partials
+    size_t colpart;  // ntiles * cw * D doubles: column-side gradient partials
+    size_t tscal;    // ntiles * 2 doubles: per-tile sum r_ij and sum of dsigma terms
+    size_t tcount;   // ntiles uint32: per-tile observed-pair count
+    size_t total;
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+inline WorkspaceLayout workspace_layout(const Tiling& t, int d)
+{
+    WorkspaceLayout w;
+    size_t off = 0;
+    w.rowpart = off;
+    off = align_up(off + (size_t)t.ntiles * t.br * d * sizeof(double), 256);
+    w.colpart = off;
+    off = align_up(off + (size_t)t.ntiles * t.cw * d * sizeof(double), 256);
+    w.tscal = off;
+    off = align_up(off + (size_t)t.ntiles * 2 * sizeof(double), 256);
+    w.tcount = off;
+    off = align_up(off + (size_t)t.ntiles * sizeof(uint32_t), 256);
+    w.total = off;
+    return w;
+}
+
+// LDS bytes used by one sweep work-group
+inline size_t sweep_lds_bytes(const Tiling& t, int d)
+{
+    return (size_t)t.waves * t.br * d * sizeof(double) + (size_t)t.waves * 4 * sizeof(double);
+}
+
+struct SweepArgs {
+    int64_t n;
+    const double* x;
+    int64_t ldx;
+    const void* y;
+    int64_t ldy;
+    const double* sigma;
+    int br, cw, nrb;
+    double* rowpart;
+    double* colpart;
+    double* tscal;
+    uint32_t* tcount;
+};
+
+// What the finalize kernel does with the summed gradient of one element.
+struct FinalizeArgs {
+    int64_t n;
+    int br, cw, nrb;
+    int64_t ntiles;
+    const double* rowpart;
+    const double* colpart;
+    const double* tscal;
+    const uint32_t* tcount;
+    const double* sigma;
+    const double* scale;     // optional upstream scale (NULL = 1)
+    double* grad;            // N x D output (ldg)
+    int64_t ldg;
+    double* loglik;          // optional
+    double* dsigma;          // optional
+    // leapfrog extensions (all optional)
+    const double* prior;     // lambda: grad -= lambda * x
+    double* x;               // positions (ldx), drifted if drift != 0
+    int64_t ldx;
+    double* p;               // momenta (ldp), kicked if p != NULL
+    int64_t ldp;
+    const double* inv_mass;  // N x D contiguous diagonal of M^-1 (NULL = 1)
+    const double* step;      // eps
+    double kick_mult;        // kick coefficient = kick_mult * eps
+    int drift;
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
+                        hipStream_t s);
+hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t s);
+
+}  // namespace mds

@@ -1,0 +1,259 @@
+// mds_kernels.hip -- the kernels around the pair sweep: the deterministic
+// finalize (partials -> gradient rows, L, dL/dsigma, fused leapfrog kick and
+// drift), the Hamiltonian energy, the Y preparation and the elementwise
+// special-function helper.
+#include "mds_internal.h"
+#include "mds_math.h"
+
+namespace mds {
+
+hipError_t launch_sweep_f64(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_f32(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s);
+
+hipError_t launch_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
+                        hipStream_t s)
+{
+    return y_dtype == 0 ? launch_sweep_f64(d, grad, t, a, s) : launch_sweep_f32(d, grad, t, a, s);
+}
+
+constexpr int kFinBlock = 256;
+
+// Fixed-order block reduction of three values over kFinBlock threads.
+__device__ void block_sum3(double& a, double& b, double& c)
+{
+    __shared__ double s[3][kFinBlock];
+    const int t = threadIdx.x;
+    s[0][t] = a;
+    s[1][t] = b;
+    s[2][t] = c;
+    __syncthreads();
+    for (int h = kFinBlock / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            s[0][t] += s[0][t + h];
+            s[1][t] += s[1][t + h];
+            s[2][t] += s[2][t + h];
+        }
+        __syncthreads();
+    }
+    a = s[0][0];
+    b = s[1][0];
+    c = s[2][0];
+}
+
+// Grid: ceil(N*D / 256) element blocks + 1 scalar block (the last one).
+// Element e = (k, d): sums the row-side partials of row k over its row
+// block's tiles, then the column-side partials over the tiles of its column
+// block, always in the same order.
+__global__ void __launch_bounds__(kFinBlock) finalize_kernel(FinalizeArgs a, int D)
+{
+    const double scale = a.scale ? *a.scale : 1.0;
+    if (blockIdx.x == gridDim.x - 1) {
+        double sr = 0.0, ss = 0.0, sm = 0.0;
+        for (int64_t t = threadIdx.x; t < a.ntiles; t += kFinBlock) {
+            sr += a.tscal[2 * t + 0];
+            ss += a.tscal[2 * t + 1];
+            sm += (double)a.tcount[t];
+        }
+        block_sum3(sr, ss, sm);
+        if (threadIdx.x == 0) {
+            const double sigma = *a.sigma;
+            const double m = sm;  // an exact integer below 2^53
+            const double L = (m > 0.0) ? -m * log(sigma) - sr : 0.0;
+            const double ds = (m > 0.0) ? (-m / sigma + ss) * scale : 0.0;
+            if (a.loglik) *a.loglik = L;
+            if (a.dsigma) *a.dsigma = ds;
+        }
+        return;
+    }
+    if (!a.grad) return;
+    const int64_t e = (int64_t)blockIdx.x * kFinBlock + threadIdx.x;
+    if (e >= a.n * D) return;
+    const int64_t k = e / D;
+    const int d = (int)(e - k * D);
+    const int br = a.br, cw = a.cw;
+
+    double s = 0.0;
+    const int r = (int)(k / br);
+    const int64_t roff = k - (int64_t)r * br;
+    const int64_t t0 = tiles_before(r, br, cw);
+    const int64_t nt = tiles_in_row_block(r, br, cw);
+    for (int64_t tt = 0; tt < nt; ++tt) s += a.rowpart[((t0 + tt) * br + roff) * D + d];
+    const int c = (int)(k / cw);
+    const int64_t coff = k - (int64_t)c * cw;
+    for (int rb = first_row_block_of_column(c, br, cw); rb < a.nrb; ++rb)
+        s += a.colpart[((tiles_before(rb, br, cw) + c) * cw + coff) * D + d];
+
+    double g = s * scale;
+    if (a.prior) g -= (*a.prior) * a.x[k * a.ldx + d];
+    a.grad[k * a.ldg + d] = g;
+    if (a.p) {
+        const double eps = *a.step;
+        double* pp = a.p + k * a.ldp + d;
+        const double pn = *pp + a.kick_mult * eps * g;
+        *pp = pn;
+        if (a.drift) {
+            const double im = a.inv_mass ? a.inv_mass[k * D + d] : 1.0;
+            a.x[k * a.ldx + d] += eps * im * pn;
+        }
+    }
+}
+
+hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t s)
+{
+    const int64_t nel = a.grad ? a.n * d : 0;
+    const unsigned nblk = (unsigned)((nel + kFinBlock - 1) / kFinBlock) + 1;
+    hipLaunchKernelGGL(finalize_kernel, dim3(nblk), dim3(kFinBlock), 0, s, a, d);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- leapfrog ----
+
+// p += mult * eps * g; then (drift) x += eps * M^-1 p.  Element-parallel.
+__global__ void __launch_bounds__(256)
+    kick_drift_kernel(int64_t n, int D, double* x, int64_t ldx, double* p, int64_t ldp,
+                      const double* g, const double* inv_mass, const double* step, double mult,
+                      int drift)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * D) return;
+    const int64_t k = e / D;
+    const int d = (int)(e - k * D);
+    const double eps = *step;
+    double* pp = p + k * ldp + d;
+    const double pn = *pp + mult * eps * g[e];
+    *pp = pn;
+    if (drift) x[k * ldx + d] += eps * (inv_mass ? inv_mass[e] : 1.0) * pn;
+}
+
+hipError_t launch_kick_drift(int64_t n, int d, double* x, int64_t ldx, double* p, int64_t ldp,
+                             const double* g, const double* inv_mass, const double* step,
+                             double mult, int drift, hipStream_t s)
+{
+    if (n * d == 0) return hipSuccess;
+    const unsigned nblk = (unsigned)((n * d + 255) / 256);
+    hipLaunchKernelGGL(kick_drift_kernel, dim3(nblk), dim3(256), 0, s, n, d, x, ldx, p, ldp, g,
+                       inv_mass, step, mult, drift);
+    return hipGetLastError();
+}
+
+// H = -(L - lambda/2 ||x||^2) + 1/2 sum p^2 / m  (one work-group, fixed order)
+__global__ void __launch_bounds__(kFinBlock)
+    energy_kernel(int64_t n, int D, const double* x, int64_t ldx, const double* p, int64_t ldp,
+                  const double* inv_mass, const double* prior, const double* loglik, double* out)
+{
+    double kin = 0.0, pri = 0.0, unused = 0.0;
+    const double lam = prior ? *prior : 0.0;
+    for (int64_t e = threadIdx.x; e < n * D; e += kFinBlock) {
+        const int64_t k = e / D;
+        const int d = (int)(e - k * D);
+        const double pv = p[k * ldp + d];
+        const double xv = x[k * ldx + d];
+        kin += 0.5 * pv * pv * (inv_mass ? inv_mass[e] : 1.0);
+        pri += 0.5 * lam * xv * xv;
+    }
+    block_sum3(kin, pri, unused);
+    if (threadIdx.x == 0) *out = -(*loglik - pri) + kin;
+}
+
+hipError_t launch_energy(int64_t n, int d, const double* x, int64_t ldx, const double* p,
+                         int64_t ldp, const double* inv_mass, const double* prior,
+                         const double* loglik, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(kFinBlock), 0, s, n, d, x, ldx, p, ldp,
+                       inv_mass, prior, loglik, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ prepare ---
+
+__global__ void zero_i64_kernel(int64_t* p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// Block b covers row i = b / nchunk, columns (b % nchunk)*256 .. +255.
+// Converts, folds the mask and NaN into NaN, and counts observed pairs i > j
+// (integer atomics: the count does not depend on their order).
+template <typename S, typename O>
+__global__ void __launch_bounds__(256)
+    prepare_kernel(const S* src, int64_t ld_src, const uint8_t* mask, int64_t ld_mask, O* out,
+                   int64_t ldy, int64_t n, int64_t nchunk, unsigned long long* count)
+{
+    const int64_t i = (int64_t)blockIdx.x / nchunk;
+    const int64_t j = ((int64_t)blockIdx.x - i * nchunk) * 256 + threadIdx.x;
+    int obs = 0;
+    if (j < n) {
+        const S v = src[i * ld_src + j];
+        const bool miss = (mask && mask[i * ld_mask + j] != 0) || isnan(v);
+        out[i * ldy + j] = miss ? (O)NAN : (O)v;
+        obs = (!miss && j < i) ? 1 : 0;
+    }
+    if (count) {
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) obs += __shfl_xor(obs, m, kWave);
+        if ((threadIdx.x & 63) == 0 && obs) atomicAdd(count, (unsigned long long)obs);
+    }
+}
+
+hipError_t launch_prepare(const void* src, int sdt, int64_t ld_src, const uint8_t* mask,
+                          int64_t ld_mask, void* out, int odt, int64_t ldy, int64_t n,
+                          int64_t* count, hipStream_t s)
+{
+    if (count) {
+        hipLaunchKernelGGL(zero_i64_kernel, dim3(1), dim3(64), 0, s, count);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n == 0) return hipSuccess;
+    const int64_t nchunk = (n + 255) / 256;
+    const dim3 grid((unsigned)(n * nchunk));
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(count);
+    if (sdt == 0 && odt == 0)
+        hipLaunchKernelGGL((prepare_kernel<double, double>), grid, dim3(256), 0, s,
+                           (const double*)src, ld_src, mask, ld_mask, (double*)out, ldy, n,
+                           nchunk, c);
+    else if (sdt == 0 && odt == 1)
+        hipLaunchKernelGGL((prepare_kernel<double, float>), grid, dim3(256), 0, s,
+                           (const double*)src, ld_src, mask, ld_mask, (float*)out, ldy, n,
+                           nchunk, c);
+    else if (sdt == 1 && odt == 0)
+        hipLaunchKernelGGL((prepare_kernel<float, double>), grid, dim3(256), 0, s,
+                           (const float*)src, ld_src, mask, ld_mask, (double*)out, ldy, n,
+                           nchunk, c);
+    else
+        hipLaunchKernelGGL((prepare_kernel<float, float>), grid, dim3(256), 0, s,
+                           (const float*)src, ld_src, mask, ld_mask, (float*)out, ldy, n,
+                           nchunk, c);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ special funcs ---
+
+__global__ void __launch_bounds__(256)
+    log_phi_kernel(const double* t, double* lnphi, double* mills, int64_t count, int prec)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count) return;
+    double l, m;
+    if (prec == 0) {
+        log_phi_general_f64(t[e], l, m);
+    } else {
+        float lf, mf;
+        log_phi_general_f32((float)t[e], lf, mf);
+        l = lf;
+        m = mf;
+    }
+    if (lnphi) lnphi[e] = l;
+    if (mills) mills[e] = m;
+}
+
+hipError_t launch_log_phi(const double* t, double* lnphi, double* mills, int64_t count, int prec,
+                          hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(log_phi_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, t,
+                       lnphi, mills, count, prec);
+    return hipGetLastError();
+}
+
+}  // namespace mds

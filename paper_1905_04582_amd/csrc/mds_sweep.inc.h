@@ -1,0 +1,294 @@
+// mds_sweep.inc.h -- the fused pair sweep: one pass over the strict lower
+// triangle of Y that produces the per-tile partial sums of the log-likelihood
+// (Eq. 2), of dL/dsigma, and of every gradient row (Eq. 9).
+//
+// Work decomposition (gfx950, 64-wide waves):
+//   * a work-group owns a tile of `br` rows x `cw` = 64*waves columns; wave w
+//     owns columns c*cw + 64w .. +63, one column j per lane;
+//   * the wave walks the tile's rows i (wave-uniform, so x_i comes through
+//     scalar loads) and reads Y[i][j0 .. j0+63]: 64 consecutive elements of
+//     one row, a fully coalesced load of the lower triangle;
+//   * each pair's gradient term goes to row j (+) and row i (-) -- each pair
+//     is evaluated once.  The column side stays in the lane's registers for
+//     the whole tile.  The row side is a sum across the 64 lanes; 8 rows are
+//     reduced together by a butterfly transpose-reduce (exchange halves at
+//     distances 32, 16, 8, then a 3-step reduction), which costs about 1.25
+//     exchanges per row instead of 6;
+//   * the waves' row sums meet in LDS and are added in wave order; column,
+//     row and scalar partials of the tile go to the workspace, and the
+//     finalize kernel adds them in a fixed order.  No atomics: the result is
+//     bitwise reproducible.
+// The paper's GPU design (one thread per pair in 16x16 work-groups for the
+// likelihood, 128 threads per row for the gradient, every pair twice) is
+// replaced by this single fused triangle pass.
+#pragma once
+
+#include "mds_internal.h"
+#include "mds_math.h"
+
+namespace mds {
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor_t(T v, int m)
+{
+    return __shfl_xor(v, m, kWave);
+}
+
+// In-wave transpose-reduce of 8 rows x D values: afterwards lane l holds in
+// v[0][*] the sum over all 64 lanes of row (l >> 3).
+template <typename T, int D>
+__device__ __forceinline__ void rowbatch_reduce(T (&v)[kRowBatch][D], int lane)
+{
+    const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const T lo = v[k][d], hi = v[k + 4][d];
+            const T keep = h32 ? hi : lo, send = h32 ? lo : hi;
+            v[k][d] = keep + shfl_xor_t(send, 32);
+        }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const T lo = v[k][d], hi = v[k + 2][d];
+            const T keep = h16 ? hi : lo, send = h16 ? lo : hi;
+            v[k][d] = keep + shfl_xor_t(send, 16);
+        }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const T lo = v[0][d], hi = v[1][d];
+        const T keep = h8 ? hi : lo, send = h8 ? lo : hi;
+        v[0][d] = keep + shfl_xor_t(send, 8);
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        v[0][d] += shfl_xor_t(v[0][d], 4);
+        v[0][d] += shfl_xor_t(v[0][d], 2);
+        v[0][d] += shfl_xor_t(v[0][d], 1);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+
+// Per-pair arithmetic.  T = double: everything in FP64.  T = float: the
+// difference x_i - x_j is formed in FP64 and rounded once (near-duplicate
+// points would otherwise lose their distance to cancellation), the rest is
+// FP32.
+template <typename T>
+struct PairConsts {
+    T inv_sigma, inv_s2, half_inv_s2, inv_s3;
+};
+
+template <typename T>
+__device__ __forceinline__ PairConsts<T> pair_consts(double sigma)
+{
+    PairConsts<T> c;
+    const double is = 1.0 / sigma;
+    c.inv_sigma = (T)is;
+    c.inv_s2 = (T)(is * is);
+    c.half_inv_s2 = (T)(0.5 * is * is);
+    c.inv_s3 = (T)(is * is * is);
+    return c;
+}
+
+template <typename T>
+__device__ __forceinline__ void trunc_terms(T t, T& lnphi, T& mills);
+template <>
+__device__ __forceinline__ void trunc_terms<double>(double t, double& lnphi, double& mills)
+{
+    trunc_terms_f64(t, lnphi, mills);
+}
+template <>
+__device__ __forceinline__ void trunc_terms<float>(float t, float& lnphi, float& mills)
+{
+    trunc_terms_f32(t, lnphi, mills);
+}
+
+template <typename T, int D, bool GRAD>
+__global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
+{
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int waves = blockDim.x / kWave;
+    const int br = a.br, cw = a.cw;
+
+    // tile -> (row block r, column block c)
+    const int64_t tile = blockIdx.x;
+    int lo = 0, hi = a.nrb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tiles_before(mid, br, cw) <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int r = lo;
+    const int c = (int)(tile - tiles_before(r, br, cw));
+    const int64_t row0 = (int64_t)r * br;
+    const int64_t row1 = min(a.n, row0 + br);
+    const int64_t jw0 = (int64_t)c * cw + (int64_t)w * kWave;
+    const int64_t j = jw0 + lane;
+    const bool colok = j < a.n;
+
+    double* lrows = lds + (size_t)w * br * D;
+    double* lscal = lds + (size_t)waves * br * D;
+    if (GRAD)
+        for (int k = lane; k < br * D; k += kWave) lrows[k] = 0.0;
+
+    double xj[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xj[d] = colok ? a.x[j * a.ldx + d] : 0.0;
+
+    const PairConsts<T> pc = pair_consts<T>(*a.sigma);
+    const T* __restrict__ Y = static_cast<const T*>(a.y);
+
+    double gj[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) gj[d] = 0.0;
+    double acc_r = 0.0, acc_s = 0.0;
+    int cnt = 0;
+
+    // rows i <= jw0 hold no pair (j < i) for any lane of this wave
+    const int64_t istart = max(row0, jw0 + 1);
+    for (int64_t ib = row0 + ((istart - row0) / kRowBatch) * kRowBatch; ib < row1;
+         ib += kRowBatch) {
+        T rb[kRowBatch][D];
+        T gjb[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) gjb[d] = T(0);
+        T br_r = T(0), br_s = T(0);
+
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q) {
+            const int64_t i = ib + q;
+#pragma unroll
+            for (int d = 0; d < D; ++d) rb[q][d] = T(0);
+            if (i < row1) {
+                const bool in_tri = colok && (j < i);
+                T yv = T(0);
+                if (in_tri) yv = Y[i * a.ldy + j];
+                const bool ok = in_tri && !isnan(yv);
+
+                T dl[D];
+                T s2 = T(0);
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    dl[d] = (T)(a.x[i * a.ldx + d] - xj[d]);
+                    s2 += dl[d] * dl[d];
+                }
+                const T delta = sqrt(s2);
+                const T t = delta * pc.inv_sigma;
+                T lnphi, mills;
+                trunc_terms<T>(t, lnphi, mills);
+                const T res = yv - delta;
+                const T rterm = res * res * pc.half_inv_s2 + lnphi;
+                br_r += ok ? rterm : T(0);
+                cnt += ok ? 1 : 0;
+                if (GRAD) {
+                    const T wv = mills * pc.inv_sigma - res * pc.inv_s2;
+                    const T coef = (ok && delta > T(0)) ? wv / delta : T(0);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        const T cd = coef * dl[d];
+                        rb[q][d] = -cd;
+                        gjb[d] += cd;
+                    }
+                    const T sterm = res * res * pc.inv_s3 + delta * pc.inv_s2 * mills;
+                    br_s += ok ? sterm : T(0);
+                }
+            }
+        }
+        acc_r += (double)br_r;
+        if (GRAD) {
+            acc_s += (double)br_s;
+#pragma unroll
+            for (int d = 0; d < D; ++d) gj[d] += (double)gjb[d];
+            rowbatch_reduce<T, D>(rb, lane);
+            if ((lane & 7) == 0) {
+                const int64_t row = ib - row0 + (lane >> 3);
+#pragma unroll
+                for (int d = 0; d < D; ++d) lrows[row * D + d] = (double)rb[0][d];
+            }
+        }
+    }
+
+    if (GRAD) {
+        double* cp = a.colpart + ((size_t)tile * cw + (size_t)w * kWave + lane) * D;
+#pragma unroll
+        for (int d = 0; d < D; ++d) cp[d] = gj[d];
+    }
+    acc_r = wave_sum(acc_r);
+    acc_s = wave_sum(acc_s);
+    cnt = wave_sum(cnt);
+    if (lane == 0) {
+        lscal[w * 4 + 0] = acc_r;
+        lscal[w * 4 + 1] = acc_s;
+        lscal[w * 4 + 2] = (double)cnt;
+    }
+    __syncthreads();
+    if (GRAD) {
+        double* rp = a.rowpart + (size_t)tile * br * D;
+        for (int k = threadIdx.x; k < br * D; k += blockDim.x) {
+            double s = 0.0;
+            for (int ww = 0; ww < waves; ++ww) s += lds[(size_t)ww * br * D + k];
+            rp[k] = s;
+        }
+    }
+    if (threadIdx.x == 0) {
+        double sr = 0.0, ss = 0.0, sc = 0.0;
+        for (int ww = 0; ww < waves; ++ww) {
+            sr += lscal[ww * 4 + 0];
+            ss += lscal[ww * 4 + 1];
+            sc += lscal[ww * 4 + 2];
+        }
+        a.tscal[2 * tile + 0] = sr;
+        a.tscal[2 * tile + 1] = ss;
+        a.tcount[tile] = (uint32_t)sc;
+    }
+}
+
+template <typename T>
+hipError_t launch_sweep_t(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s)
+{
+    if (t.ntiles == 0) return hipSuccess;
+    const dim3 grid((unsigned)t.ntiles), block((unsigned)(t.waves * kWave));
+    const size_t lds = sweep_lds_bytes(t, d);
+#define MDS_SWEEP_CASE(DD)                                                              \
+    case DD:                                                                            \
+        if (grad)                                                                       \
+            hipLaunchKernelGGL((sweep_kernel<T, DD, true>), grid, block, lds, s, a);   \
+        else                                                                            \
+            hipLaunchKernelGGL((sweep_kernel<T, DD, false>), grid, block, lds, s, a);  \
+        break;
+    switch (d) {
+        MDS_SWEEP_CASE(1)
+        MDS_SWEEP_CASE(2)
+        MDS_SWEEP_CASE(3)
+        MDS_SWEEP_CASE(4)
+        MDS_SWEEP_CASE(5)
+        MDS_SWEEP_CASE(6)
+        MDS_SWEEP_CASE(7)
+        MDS_SWEEP_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef MDS_SWEEP_CASE
+    return hipGetLastError();
+}
+
+}  // namespace mds

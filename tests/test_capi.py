@@ -1,0 +1,145 @@
+"""Host-only checks of the C-ABI: the library loads, exports every declared
+entry point, and rejects bad arguments before it makes any HIP call (so all
+of this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch  # noqa: F401  (load torch's HIP runtime first, as the binding does)
+
+from paper_1905_04582_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "massivemds.h")
+
+ERR_ARG, ERR_UNSUP, ERR_WS = -1, -2, -3
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mds_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 8
+    L = api.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_version_and_status_strings():
+    L = api.lib()
+    assert L.mds_version() >= 10000
+    for code, name in [(0, b"MDS_OK"), (-1, b"MDS_ERR_INVALID_ARGUMENT"),
+                       (-2, b"MDS_ERR_UNSUPPORTED"), (-3, b"MDS_ERR_WORKSPACE_TOO_SMALL"),
+                       (-4, b"MDS_ERR_HIP")]:
+        assert L.mds_status_string(code) == name
+
+
+def test_workspace_query():
+    a = api.mds_workspace_bytes(5392, 2, api.MDS_F64)
+    b = api.mds_workspace_bytes(5392, 6, api.MDS_F64)
+    assert 0 < a < b
+    assert api.mds_workspace_bytes(0, 2, api.MDS_F64) == 0
+    # explicit tilings: one of tile_rows and 64*tile_waves must divide the other
+    for br in (32, 64, 128, 256):
+        for w in (1, 2, 4, 8):
+            if (64 * w) % br == 0 or br % (64 * w) == 0:
+                try:
+                    assert api.mds_workspace_bytes(1000, 2, api.MDS_F32, br, w) > 0
+                except api.MDSError as e:   # LDS limit for the largest tiles
+                    assert e.status == ERR_UNSUP
+
+
+@pytest.mark.parametrize("args,code", [
+    ((10, 0, 0, 0, 0), ERR_UNSUP),        # d = 0
+    ((10, 9, 0, 0, 0), ERR_UNSUP),        # d > MDS_MAX_DIM
+    ((10, 2, 7, 0, 0), ERR_UNSUP),        # bad dtype
+    ((-1, 2, 0, 0, 0), ERR_ARG),          # n < 0
+    ((10, 2, 0, 48, 0), ERR_UNSUP),       # tile_rows not in the set
+    ((10, 2, 0, 64, 3), ERR_UNSUP),       # tile_waves not in the set
+])
+def test_workspace_query_rejects(args, code):
+    out = ctypes.c_size_t(0)
+    assert api.lib().mds_workspace_bytes(*args, ctypes.byref(out)) == code
+    assert api.lib().mds_last_error()  # a detail string was set
+
+
+FAKE = 1 << 20  # a non-null, well-aligned address that is never dereferenced
+
+
+def _p(v=FAKE):
+    return ctypes.c_void_p(v)
+
+
+def _loglik(**kw):
+    a = dict(n=100, d=2, x=_p(), ldx=2, y=_p(), dt=0, ldy=128, sigma=_p(), out=_p(), ws=_p(),
+             wsb=1 << 30, br=0, w=0)
+    a.update(kw)
+    return api.lib().mds_loglik(a["n"], a["d"], a["x"], a["ldx"], a["y"], a["dt"], a["ldy"],
+                                a["sigma"], a["out"], a["ws"], a["wsb"], a["br"], a["w"], None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=-5), ERR_ARG), (dict(d=0), ERR_UNSUP), (dict(d=9), ERR_UNSUP),
+    (dict(dt=2), ERR_UNSUP), (dict(x=None), ERR_ARG), (dict(ldx=1), ERR_ARG),
+    (dict(y=None), ERR_ARG), (dict(ldy=99), ERR_ARG), (dict(sigma=None), ERR_ARG),
+    (dict(out=None), ERR_ARG), (dict(x=_p(FAKE + 4)), ERR_ARG), (dict(y=_p(FAKE + 2)), ERR_ARG),
+    (dict(wsb=0), ERR_WS), (dict(ws=None), ERR_ARG), (dict(ws=_p(FAKE + 64)), ERR_ARG),
+    (dict(br=100), ERR_UNSUP), (dict(br=64, w=5), ERR_UNSUP),
+])
+def test_loglik_rejects_before_any_hip_call(kw, code):
+    assert _loglik(**kw) == code
+
+
+def test_gradient_rejects():
+    L = api.lib()
+    args = [100, 2, _p(), 2, _p(), 0, 128, _p(), None, _p(), 2, None, None, _p(), 1 << 30, 0,
+            0, None]
+    ok = list(args)
+    bad = list(ok); bad[9] = None          # grad NULL
+    assert L.mds_gradient(*bad) == ERR_ARG
+    bad = list(ok); bad[10] = 1            # ldg < d
+    assert L.mds_gradient(*bad) == ERR_ARG
+    bad = list(ok); bad[8] = _p(FAKE + 1)  # misaligned scale
+    assert L.mds_gradient(*bad) == ERR_ARG
+    bad = list(ok); bad[14] = 16           # workspace too small
+    assert L.mds_gradient(*bad) == ERR_WS
+
+
+def test_leapfrog_rejects():
+    L = api.lib()
+    ok = [100, 2, _p(FAKE), 2, _p(FAKE + 4096), 2, _p(), 0, 128, _p(), None, _p(), None, 20,
+          _p(FAKE + 8192), _p(), 0, None, None, _p(), 1 << 30, 0, 0, None]
+    bad = list(ok); bad[13] = -1           # n_steps < 0
+    assert L.mds_leapfrog(*bad) == ERR_ARG
+    bad = list(ok); bad[4] = bad[2]        # p aliases x
+    assert L.mds_leapfrog(*bad) == ERR_ARG
+    bad = list(ok); bad[11] = None         # step NULL
+    assert L.mds_leapfrog(*bad) == ERR_ARG
+    bad = list(ok); bad[15] = None         # loglik_io NULL
+    assert L.mds_leapfrog(*bad) == ERR_ARG
+    bad = list(ok); bad[5] = 1             # ldp < d
+    assert L.mds_leapfrog(*bad) == ERR_ARG
+
+
+def test_prepare_and_log_phi_reject():
+    L = api.lib()
+    assert L.mds_prepare_y(_p(), 0, 10, None, 0, _p(), 3, 10, 10, None, None) == ERR_UNSUP
+    assert L.mds_prepare_y(_p(), 0, 9, None, 0, _p(), 0, 10, 10, None, None) == ERR_ARG
+    assert L.mds_prepare_y(_p(), 0, 10, _p(), 5, _p(), 0, 10, 10, None, None) == ERR_ARG
+    # in place with a dtype change
+    assert L.mds_prepare_y(_p(), 0, 10, None, 0, _p(), 1, 10, 10, None, None) == ERR_ARG
+    assert L.mds_log_phi(None, None, None, 5, 0, None) == ERR_ARG
+    assert L.mds_log_phi(_p(), None, None, -1, 0, None) == ERR_ARG
+    assert L.mds_log_phi(_p(), None, None, 5, 4, None) == ERR_UNSUP
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(api, "_lib", None)
+    monkeypatch.setattr(api, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        api.lib()
