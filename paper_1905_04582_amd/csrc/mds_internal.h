@@ -92,10 +92,16 @@ inline WorkspaceLayout workspace_layout(const Tiling& t, int d)
     return w;
 }
 
-// LDS bytes used by one sweep work-group
+// rows staged per reduction step of the sweep (keeps the per-wave staging
+// buffer at <= 16 doubles per lane)
+__host__ __device__ constexpr int sweep_stage_rows(int d) { return d <= 2 ? 8 : (d <= 4 ? 4 : 2); }
+
+// LDS bytes used by one sweep work-group: tile row sums, per-wave scalars
+// and the per-wave row staging buffer
 inline size_t sweep_lds_bytes(const Tiling& t, int d)
 {
-    return (size_t)t.waves * t.br * d * sizeof(double) + (size_t)t.waves * 4 * sizeof(double);
+    return (size_t)t.waves * t.br * d * sizeof(double) + (size_t)t.waves * 4 * sizeof(double) +
+           (size_t)t.waves * sweep_stage_rows(d) * kWave * d * sizeof(double);
 }
 
 struct SweepArgs {

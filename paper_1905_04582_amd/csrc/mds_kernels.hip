@@ -40,52 +40,93 @@ __device__ void block_sum3(double& a, double& b, double& c)
     c = s[2][0];
 }
 
-// Grid: ceil(N*D / 256) element blocks + 1 scalar block (the last one).
-// Element e = (k, d): sums the row-side partials of row k over its row
-// block's tiles, then the column-side partials over the tiles of its column
-// block, always in the same order.
-__global__ void __launch_bounds__(kFinBlock) finalize_kernel(FinalizeArgs a, int D)
+// Finalize: one work-group per 64 consecutive gradient elements e = (k, d),
+// plus one scalar work-group (the last one).  Element e owns a list of
+// partials: the row-side partials of row k over the tiles of its row block,
+// then the column-side partials over the tiles of its column block.  Wave w
+// of kFinChunks adds list items w, w + kFinChunks, ... (64 consecutive
+// elements per wave: coalesced reads), and wave 0 adds the kFinChunks chunk
+// sums in chunk order.  Every order is fixed, so the result is reproducible.
+constexpr int kFinChunks = 8;
+
+__global__ void __launch_bounds__(kWave * kFinChunks) finalize_kernel(FinalizeArgs a, int D)
 {
     const double scale = a.scale ? *a.scale : 1.0;
     if (blockIdx.x == gridDim.x - 1) {
+        // the scalar work-group uses its first kFinBlock threads
+        __shared__ double s[3][kFinBlock];
+        const int t = threadIdx.x;
         double sr = 0.0, ss = 0.0, sm = 0.0;
-        for (int64_t t = threadIdx.x; t < a.ntiles; t += kFinBlock) {
-            sr += a.tscal[2 * t + 0];
-            ss += a.tscal[2 * t + 1];
-            sm += (double)a.tcount[t];
+        if (t < kFinBlock)
+            for (int64_t u = t; u < a.ntiles; u += kFinBlock) {
+                sr += a.tscal[2 * u + 0];
+                ss += a.tscal[2 * u + 1];
+                sm += (double)a.tcount[u];
+            }
+        if (t < kFinBlock) {
+            s[0][t] = sr;
+            s[1][t] = ss;
+            s[2][t] = sm;
         }
-        block_sum3(sr, ss, sm);
-        if (threadIdx.x == 0) {
+        __syncthreads();
+        for (int h = kFinBlock / 2; h > 0; h >>= 1) {
+            if (t < h) {
+                s[0][t] += s[0][t + h];
+                s[1][t] += s[1][t + h];
+                s[2][t] += s[2][t + h];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
             const double sigma = *a.sigma;
-            const double m = sm;  // an exact integer below 2^53
-            const double L = (m > 0.0) ? -m * log(sigma) - sr : 0.0;
-            const double ds = (m > 0.0) ? (-m / sigma + ss) * scale : 0.0;
+            const double m = s[2][0];  // an exact integer below 2^53
+            const double L = (m > 0.0) ? -m * log(sigma) - s[0][0] : 0.0;
+            const double ds = (m > 0.0) ? (-m / sigma + s[1][0]) * scale : 0.0;
             if (a.loglik) *a.loglik = L;
             if (a.dsigma) *a.dsigma = ds;
         }
         return;
     }
-    if (!a.grad) return;
-    const int64_t e = (int64_t)blockIdx.x * kFinBlock + threadIdx.x;
-    if (e >= a.n * D) return;
-    const int64_t k = e / D;
-    const int d = (int)(e - k * D);
+    __shared__ double part[kFinChunks][kWave];
+    const int lane = threadIdx.x % kWave;
+    const int chunk = threadIdx.x / kWave;
+    const int64_t e = (int64_t)blockIdx.x * kWave + lane;
+    const bool live = e < a.n * D;
     const int br = a.br, cw = a.cw;
 
     double s = 0.0;
-    const int r = (int)(k / br);
-    const int64_t roff = k - (int64_t)r * br;
-    const int64_t t0 = tiles_before(r, br, cw);
-    const int64_t nt = tiles_in_row_block(r, br, cw);
-    for (int64_t tt = 0; tt < nt; ++tt) s += a.rowpart[((t0 + tt) * br + roff) * D + d];
-    const int c = (int)(k / cw);
-    const int64_t coff = k - (int64_t)c * cw;
-    for (int rb = first_row_block_of_column(c, br, cw); rb < a.nrb; ++rb)
-        s += a.colpart[((tiles_before(rb, br, cw) + c) * cw + coff) * D + d];
+    int64_t k = 0;
+    int d = 0;
+    if (live) {
+        k = e / D;
+        d = (int)(e - k * D);
+        const int r = (int)(k / br);
+        const int64_t roff = k - (int64_t)r * br;
+        const int64_t t0 = tiles_before(r, br, cw);
+        const int64_t nrow = tiles_in_row_block(r, br, cw);
+        const int c = (int)(k / cw);
+        const int64_t coff = k - (int64_t)c * cw;
+        const int rb0 = first_row_block_of_column(c, br, cw);
+        const int64_t total = nrow + (a.nrb - rb0);
+        for (int64_t it = chunk; it < total; it += kFinChunks) {
+            if (it < nrow) {
+                s += a.rowpart[((t0 + it) * br + roff) * D + d];
+            } else {
+                const int rb = rb0 + (int)(it - nrow);
+                s += a.colpart[((tiles_before(rb, br, cw) + c) * cw + coff) * D + d];
+            }
+        }
+    }
+    part[chunk][lane] = s;
+    __syncthreads();
+    if (chunk != 0 || !live) return;
+    double tot = part[0][lane];
+#pragma unroll
+    for (int q = 1; q < kFinChunks; ++q) tot += part[q][lane];
 
-    double g = s * scale;
+    double g = tot * scale;
     if (a.prior) g -= (*a.prior) * a.x[k * a.ldx + d];
-    a.grad[k * a.ldg + d] = g;
+    if (a.grad) a.grad[k * a.ldg + d] = g;
     if (a.p) {
         const double eps = *a.step;
         double* pp = a.p + k * a.ldp + d;
@@ -101,8 +142,8 @@ __global__ void __launch_bounds__(kFinBlock) finalize_kernel(FinalizeArgs a, int
 hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t s)
 {
     const int64_t nel = a.grad ? a.n * d : 0;
-    const unsigned nblk = (unsigned)((nel + kFinBlock - 1) / kFinBlock) + 1;
-    hipLaunchKernelGGL(finalize_kernel, dim3(nblk), dim3(kFinBlock), 0, s, a, d);
+    const unsigned nblk = (unsigned)((nel + kWave - 1) / kWave) + 1;
+    hipLaunchKernelGGL(finalize_kernel, dim3(nblk), dim3(kWave * kFinChunks), 0, s, a, d);
     return hipGetLastError();
 }
 
@@ -171,27 +212,36 @@ __global__ void zero_i64_kernel(int64_t* p)
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
-// Block b covers row i = b / nchunk, columns (b % nchunk)*256 .. +255.
-// Converts, folds the mask and NaN into NaN, and counts observed pairs i > j
-// (integer atomics: the count does not depend on their order).
+// One work-group per row i: converts, folds the mask and NaN into NaN, and
+// counts the observed pairs i > j of the row; one integer atomic per row
+// (integer addition: the count does not depend on the order).
 template <typename S, typename O>
 __global__ void __launch_bounds__(256)
     prepare_kernel(const S* src, int64_t ld_src, const uint8_t* mask, int64_t ld_mask, O* out,
-                   int64_t ldy, int64_t n, int64_t nchunk, unsigned long long* count)
+                   int64_t ldy, int64_t n, unsigned long long* count)
 {
-    const int64_t i = (int64_t)blockIdx.x / nchunk;
-    const int64_t j = ((int64_t)blockIdx.x - i * nchunk) * 256 + threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const S* srow = src + i * ld_src;
+    const uint8_t* mrow = mask ? mask + i * ld_mask : nullptr;
+    O* orow = out + i * ldy;
     int obs = 0;
-    if (j < n) {
-        const S v = src[i * ld_src + j];
-        const bool miss = (mask && mask[i * ld_mask + j] != 0) || isnan(v);
-        out[i * ldy + j] = miss ? (O)NAN : (O)v;
-        obs = (!miss && j < i) ? 1 : 0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const S v = srow[j];
+        const bool miss = (mrow && mrow[j] != 0) || isnan(v);
+        orow[j] = miss ? (O)NAN : (O)v;
+        obs += (!miss && j < i) ? 1 : 0;
     }
     if (count) {
+        __shared__ int wsum[256 / kWave];
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) obs += __shfl_xor(obs, m, kWave);
-        if ((threadIdx.x & 63) == 0 && obs) atomicAdd(count, (unsigned long long)obs);
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x / kWave] = obs;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int q = 0; q < 256 / kWave; ++q) tot += wsum[q];
+            if (tot) atomicAdd(count, (unsigned long long)tot);
+        }
     }
 }
 
@@ -205,25 +255,20 @@ hipError_t launch_prepare(const void* src, int sdt, int64_t ld_src, const uint8_
         if (e != hipSuccess) return e;
     }
     if (n == 0) return hipSuccess;
-    const int64_t nchunk = (n + 255) / 256;
-    const dim3 grid((unsigned)(n * nchunk));
+    const dim3 grid((unsigned)n);
     unsigned long long* c = reinterpret_cast<unsigned long long*>(count);
     if (sdt == 0 && odt == 0)
         hipLaunchKernelGGL((prepare_kernel<double, double>), grid, dim3(256), 0, s,
-                           (const double*)src, ld_src, mask, ld_mask, (double*)out, ldy, n,
-                           nchunk, c);
+                           (const double*)src, ld_src, mask, ld_mask, (double*)out, ldy, n, c);
     else if (sdt == 0 && odt == 1)
         hipLaunchKernelGGL((prepare_kernel<double, float>), grid, dim3(256), 0, s,
-                           (const double*)src, ld_src, mask, ld_mask, (float*)out, ldy, n,
-                           nchunk, c);
+                           (const double*)src, ld_src, mask, ld_mask, (float*)out, ldy, n, c);
     else if (sdt == 1 && odt == 0)
         hipLaunchKernelGGL((prepare_kernel<float, double>), grid, dim3(256), 0, s,
-                           (const float*)src, ld_src, mask, ld_mask, (double*)out, ldy, n,
-                           nchunk, c);
+                           (const float*)src, ld_src, mask, ld_mask, (double*)out, ldy, n, c);
     else
         hipLaunchKernelGGL((prepare_kernel<float, float>), grid, dim3(256), 0, s,
-                           (const float*)src, ld_src, mask, ld_mask, (float*)out, ldy, n,
-                           nchunk, c);
+                           (const float*)src, ld_src, mask, ld_mask, (float*)out, ldy, n, c);
     return hipGetLastError();
 }
 

@@ -1,12 +1,19 @@
 // mds_math.h -- device special functions of the truncated-normal MDS model.
 //
 // For t = delta/sigma >= 0 every pair needs ln Phi(t) (Eq. 2) and the ratio
-// phi(t)/Phi(t) (Eq. 9).  Both come from q = Phi(-t) = erfc(t/sqrt 2)/2:
-//     ln Phi(t) = log1p(-q)            (keeps relative accuracy as Phi -> 1)
-//     phi(t)/Phi(t) = phi(t) / (1 - q)
-// The general helpers below also cover t < 0 (not reached by the sweeps,
-// where delta >= 0 and sigma > 0), through the scaled complementary error
-// function: Phi(t) = exp(-t^2/2) erfcx(-t/sqrt 2) / 2, so
+// phi(t)/Phi(t) (Eq. 9).  Both are built branch-free from one exponential:
+//     e = exp(-t^2/2),  z = t/sqrt 2,  erfcx(z) ~ P(z)/Q(z),
+//     q = Phi(-t) = e erfcx(z) / 2 = a / (2Q)   with a = e P,
+//     ln Phi(t) = log1p(-q) = -2 s A(s^2),  s = q/(2-q) = a / (4Q - a),
+//     phi(t)/Phi(t) = e / (sqrt(2 pi) (1-q)) = 4 e Q / (sqrt(2 pi) (4Q - 2a)),
+// where A(v) = atanh(sqrt v)/sqrt v.  s <= 1/3 because q <= 1/2, so A is a
+// short polynomial on [0, 1/9], and log1p keeps full relative accuracy as
+// q -> 0.  The two divisions share one reciprocal of (4Q - a)(4Q - 2a).
+// Coefficients come from gen_coeffs.py (mds_coeffs.h).  Every lane runs the
+// same instructions whatever t is: no branches, no lane divergence.
+//
+// The general helpers at the end also cover t < 0 (never reached by the
+// sweeps, where delta >= 0 and sigma > 0) through the log-erfc form
 //     ln Phi(t) = -t^2/2 + ln(erfcx(-t/sqrt 2)/2),
 //     phi(t)/Phi(t) = sqrt(2/pi) / erfcx(-t/sqrt 2),
 // which neither underflows nor cancels however far t goes below 0.
@@ -14,21 +21,118 @@
 
 #include <hip/hip_runtime.h>
 
+#include "mds_coeffs.h"
+
 namespace mds {
 
 constexpr double kInvSqrt2 = 0.70710678118654752440;
 constexpr double kInvSqrt2Pi = 0.39894228040143267794;  // 1/sqrt(2 pi)
 constexpr double kSqrt2OverPi = 0.79788456080286535588;  // sqrt(2/pi)
 
+template <typename T, int N>
+__device__ __forceinline__ T horner(const T (&c)[N], T x)
+{
+    T acc = c[N - 1];
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) acc = fma(acc, x, c[k]);
+    return acc;
+}
+
+// acc * x + c with c in a scalar register: one VOP3 v_fma_f64.  (The
+// compiler otherwise prefers the two-operand v_fmac_f64, whose addend must be
+// a vector register, and copies every coefficient into one first.)
+__device__ __forceinline__ double fma_sc(double acc, double x, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"(x), "s"(c));
+    return r;
+}
+
+// Horner's rule over a coefficient table in constant memory.  The empty asm
+// hides the table's identity from the optimiser, so the coefficients are
+// fetched by uniform scalar loads (s_load) instead of being folded into
+// immediates, which a 64-bit VALU operand cannot encode.
+typedef const __attribute__((address_space(4))) double* const_f64_ptr;
+
+template <int N>
+__device__ __forceinline__ double horner_tab(const double (&tab)[N], double x)
+{
+    const_f64_ptr c = (const_f64_ptr)tab;
+    asm volatile("" : "+s"(c));
+    double acc = fma_sc(c[N - 1], x, c[N - 2]);
+#pragma unroll
+    for (int k = N - 3; k >= 0; --k) acc = fma_sc(acc, x, c[k]);
+    return acc;
+}
+
 // ---------------------------------------------------------------- FP64 --
+
+// 1/d for finite d > 0 (not subnormal): hardware estimate + 2 Newton steps
+__device__ __forceinline__ double rcp_f64(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+// 1/sqrt(x) for finite x >= DBL_MIN: hardware estimate + 2 Newton steps
+__device__ __forceinline__ double rsqrt_f64(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    r = fma(r, fma(-hx, r * r, 0.5), r);
+    r = fma(r, fma(-hx, r * r, 0.5), r);
+    return r;
+}
+
+// exp(-t^2/2) for t >= 0; 0 once the value leaves the FP64 range
+__device__ __forceinline__ double exp_neg_half_sq(double t)
+{
+    const double x = fmax(-0.5 * (t * t), -760.0);
+    const double k = rint(x * kLog2e);
+    double r = fma(k, -kLn2Head, x);
+    r = fma(k, -kLn2Tail, r);
+    return ldexp(horner_tab(kExpC64, r), (int)k);
+}
 
 // ln Phi(t) and phi(t)/Phi(t) for t >= 0 (the sweep's domain)
 __device__ __forceinline__ void trunc_terms_f64(double t, double& lnphi, double& mills)
 {
-    const double q = 0.5 * erfc(t * kInvSqrt2);
-    lnphi = log1p(-q);
-    mills = (exp(-0.5 * t * t) * kInvSqrt2Pi) / (1.0 - q);
+    const double e = exp_neg_half_sq(t);
+    // beyond the fitted range e == 0, so any finite positive erfcx will do
+    const double z = fmin(t * kInvSqrt2, kErfcxZmax64 + 1.0);
+    const double P = horner_tab(kErfcxP64, z);
+    const double Q = horner_tab(kErfcxQ64, z);
+    const double a = e * P;               // 2 q Q
+    const double d1 = fma(4.0, Q, -a);    // 4Q - a   = 2Q (2 - q)
+    const double d2 = d1 - a;             // 4Q - 2a  = 4Q (1 - q)
+    const double rr = rcp_f64(d1 * d2);
+    const double s = a * d2 * rr;         // q / (2 - q)
+    lnphi = -2.0 * s * horner_tab(kAtanhA64, s * s);
+    mills = (4.0 * kInvSqrt2Pi) * (e * Q) * (d1 * rr);
 }
+
+// ---------------------------------------------------------------- FP32 --
+
+// ln Phi(t) and phi(t)/Phi(t) for t >= 0 in FP32 arithmetic
+__device__ __forceinline__ void trunc_terms_f32(float t, float& lnphi, float& mills)
+{
+    const float e = __builtin_amdgcn_exp2f(-0.5f * (t * t) * (float)kLog2e);
+    const float z = fminf(t * (float)kInvSqrt2, kErfcxZmax32 + 1.0f);
+    const float P = horner(kErfcxP32, z);
+    const float Q = horner(kErfcxQ32, z);
+    const float a = e * P;
+    const float d1 = fmaf(4.0f, Q, -a);
+    const float d2 = d1 - a;
+    const float rr = __builtin_amdgcn_rcpf(d1 * d2);
+    const float s = a * d2 * rr;
+    lnphi = -2.0f * s * horner(kAtanhA32, s * s);
+    mills = (float)(4.0 * kInvSqrt2Pi) * (e * Q) * (d1 * rr);
+}
+
+// --------------------------------------------------- general helpers ----
 
 // any real t
 __device__ inline void log_phi_general_f64(double t, double& lnphi, double& mills)
@@ -42,15 +146,6 @@ __device__ inline void log_phi_general_f64(double t, double& lnphi, double& mill
         lnphi = -0.5 * t * t + log(0.5 * ex);
         mills = kSqrt2OverPi / ex;
     }
-}
-
-// ---------------------------------------------------------------- FP32 --
-
-__device__ __forceinline__ void trunc_terms_f32(float t, float& lnphi, float& mills)
-{
-    const float q = 0.5f * erfcf(t * (float)kInvSqrt2);
-    lnphi = log1pf(-q);
-    mills = (expf(-0.5f * t * t) * (float)kInvSqrt2Pi) / (1.0f - q);
 }
 
 // any real t: FP32 arithmetic, except the far lower tail t < -5, which is

@@ -106,6 +106,32 @@ __device__ __forceinline__ PairConsts<T> pair_consts(double sigma)
 }
 
 template <typename T>
+__device__ __forceinline__ T min_normal();
+template <>
+__device__ __forceinline__ double min_normal<double>()
+{
+    return 2.2250738585072014e-308;
+}
+template <>
+__device__ __forceinline__ float min_normal<float>()
+{
+    return 1.17549435e-38f;
+}
+
+template <typename T>
+__device__ __forceinline__ T rsqrt_t(T x);
+template <>
+__device__ __forceinline__ double rsqrt_t<double>(double x)
+{
+    return rsqrt_f64(x);
+}
+template <>
+__device__ __forceinline__ float rsqrt_t<float>(float x)
+{
+    return __builtin_amdgcn_rsqf(x);
+}
+
+template <typename T>
 __device__ __forceinline__ void trunc_terms(T t, T& lnphi, T& mills);
 template <>
 __device__ __forceinline__ void trunc_terms<double>(double t, double& lnphi, double& mills)
@@ -121,9 +147,11 @@ __device__ __forceinline__ void trunc_terms<float>(float t, float& lnphi, float&
 template <typename T, int D, bool GRAD>
 __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
 {
+    constexpr int RB = sweep_stage_rows(D);
+    constexpr int GL = kWave / RB;  // lanes that share one row in the reduction
     extern __shared__ double lds[];
     const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int waves = blockDim.x / kWave;
     const int br = a.br, cw = a.cw;
 
@@ -145,8 +173,10 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
     const int64_t j = jw0 + lane;
     const bool colok = j < a.n;
 
+    // LDS: [waves][br][D] tile row sums | [waves][4] scalars | [waves][RB][64][D] staging
     double* lrows = lds + (size_t)w * br * D;
     double* lscal = lds + (size_t)waves * br * D;
+    T* stage = reinterpret_cast<T*>(lscal + (size_t)waves * 4) + (size_t)w * RB * kWave * D;
     if (GRAD)
         for (int k = lane; k < br * D; k += kWave) lrows[k] = 0.0;
 
@@ -165,52 +195,56 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
 
     // rows i <= jw0 hold no pair (j < i) for any lane of this wave
     const int64_t istart = max(row0, jw0 + 1);
-    for (int64_t ib = row0 + ((istart - row0) / kRowBatch) * kRowBatch; ib < row1;
-         ib += kRowBatch) {
-        T rb[kRowBatch][D];
+    for (int64_t ib = row0 + ((istart - row0) / RB) * RB; ib < row1; ib += RB) {
         T gjb[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) gjb[d] = T(0);
         T br_r = T(0), br_s = T(0);
+        const int nq = (int)min((int64_t)RB, row1 - ib);
 
-#pragma unroll
-        for (int q = 0; q < kRowBatch; ++q) {
+#pragma unroll 1
+        for (int q = 0; q < nq; ++q) {
             const int64_t i = ib + q;
-#pragma unroll
-            for (int d = 0; d < D; ++d) rb[q][d] = T(0);
-            if (i < row1) {
-                const bool in_tri = colok && (j < i);
-                T yv = T(0);
-                if (in_tri) yv = Y[i * a.ldy + j];
-                const bool ok = in_tri && !isnan(yv);
+            const T* __restrict__ yrow = Y + i * a.ldy + jw0;
+            const double* __restrict__ xi = a.x + i * a.ldx;
+            const bool in_tri = colok && (j < i);
+            T yv = T(0);
+            if (in_tri) yv = yrow[lane];
+            const bool ok = in_tri && !isnan(yv);
 
-                T dl[D];
-                T s2 = T(0);
+            T dl[D];
+            T s2 = T(0);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                dl[d] = (T)(xi[d] - xj[d]);
+                s2 = fma(dl[d], dl[d], s2);
+            }
+            // delta and 1/delta from one reciprocal square root; a coincident
+            // pair (s2 below the normal range) has delta = 0 and no direction
+            const bool pos = s2 >= min_normal<T>();
+            const T sg = pos ? s2 : T(1);
+            const T rs = rsqrt_t(sg);
+            const T delta = pos ? sg * rs : T(0);
+            const T rinv = pos ? rs : T(0);
+            const T t = delta * pc.inv_sigma;
+            T lnphi, mills;
+            trunc_terms<T>(t, lnphi, mills);
+            const T res = yv - delta;
+            const T res2 = res * res;
+            br_r += ok ? fma(res2, pc.half_inv_s2, lnphi) : T(0);
+            cnt += ok ? 1 : 0;
+            if (GRAD) {
+                // w = (delta - y)/sigma^2 + m/sigma; the pair's term is w (x_i - x_j)/delta
+                const T wv = fma(mills, pc.inv_sigma, -res * pc.inv_s2);
+                const T coef = ok ? wv * rinv : T(0);
+                T* st = stage + ((size_t)q * kWave + lane) * D;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    dl[d] = (T)(a.x[i * a.ldx + d] - xj[d]);
-                    s2 += dl[d] * dl[d];
+                    const T cd = coef * dl[d];
+                    st[d] = -cd;
+                    gjb[d] += cd;
                 }
-                const T delta = sqrt(s2);
-                const T t = delta * pc.inv_sigma;
-                T lnphi, mills;
-                trunc_terms<T>(t, lnphi, mills);
-                const T res = yv - delta;
-                const T rterm = res * res * pc.half_inv_s2 + lnphi;
-                br_r += ok ? rterm : T(0);
-                cnt += ok ? 1 : 0;
-                if (GRAD) {
-                    const T wv = mills * pc.inv_sigma - res * pc.inv_s2;
-                    const T coef = (ok && delta > T(0)) ? wv / delta : T(0);
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        const T cd = coef * dl[d];
-                        rb[q][d] = -cd;
-                        gjb[d] += cd;
-                    }
-                    const T sterm = res * res * pc.inv_s3 + delta * pc.inv_s2 * mills;
-                    br_s += ok ? sterm : T(0);
-                }
+                br_s += ok ? fma(res2, pc.inv_s3, delta * pc.inv_s2 * mills) : T(0);
             }
         }
         acc_r += (double)br_r;
@@ -218,11 +252,28 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
             acc_s += (double)br_s;
 #pragma unroll
             for (int d = 0; d < D; ++d) gj[d] += (double)gjb[d];
-            rowbatch_reduce<T, D>(rb, lane);
-            if ((lane & 7) == 0) {
-                const int64_t row = ib - row0 + (lane >> 3);
+            // transposed reduction of the staged rows: lane (g, p) adds the
+            // values of lanes p, p+GL, ... of row g, then GL lanes combine
+            const int g = lane / GL, p = lane % GL;
+            T sum[D];
 #pragma unroll
-                for (int d = 0; d < D; ++d) lrows[row * D + d] = (double)rb[0][d];
+            for (int d = 0; d < D; ++d) sum[d] = T(0);
+            if (g < nq) {
+#pragma unroll
+                for (int k = 0; k < RB; ++k) {
+                    const T* src = stage + ((size_t)g * kWave + p + k * GL) * D;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) sum[d] += src[d];
+                }
+            }
+#pragma unroll
+            for (int m = GL / 2; m >= 1; m >>= 1)
+#pragma unroll
+                for (int d = 0; d < D; ++d) sum[d] += shfl_xor_t(sum[d], m);
+            if (p == 0 && g < nq) {
+                const int64_t row = ib - row0 + g;
+#pragma unroll
+                for (int d = 0; d < D; ++d) lrows[row * D + d] = (double)sum[d];
             }
         }
     }
