@@ -139,12 +139,14 @@ int mds_loglik(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y
  *   grad       N x D FP64, leading dimension ldg >= D: s * dL/dX
  *   loglik_dev optional device double: L
  *   dsigma_dev optional device double: s * dL/dsigma
+ *   dlogsigma_dev optional device double: s * dL/d(ln sigma) = s * sigma * dL/dsigma
+ *              (the derivative a caller parametrising sigma by its log needs)
  */
 int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
                  int32_t y_dtype, int64_t ldy, const double* sigma_dev, const double* scale_dev,
                  double* grad, int64_t ldg, double* loglik_dev, double* dsigma_dev,
-                 void* workspace, size_t workspace_bytes, int32_t tile_rows,
-                 int32_t tile_waves, hipStream_t stream);
+                 double* dlogsigma_dev, void* workspace, size_t workspace_bytes,
+                 int32_t tile_rows, int32_t tile_waves, hipStream_t stream);
 
 /*
  * One leapfrog trajectory of Hamiltonian Monte Carlo (Section 2.3, Eqs. 6-8)

@@ -62,7 +62,8 @@ def lib():
                              ctypes.c_size_t, _c_i32, _c_i32, _vp]
     L.mds_gradient.restype = ctypes.c_int
     L.mds_gradient.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i64, _vp, _vp, _vp,
-                               _c_i64, _vp, _vp, _vp, ctypes.c_size_t, _c_i32, _c_i32, _vp]
+                               _c_i64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _c_i32, _c_i32,
+                               _vp]
     L.mds_leapfrog.restype = ctypes.c_int
     L.mds_leapfrog.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i64, _vp, _c_i32, _c_i64,
                                _vp, _vp, _vp, _vp, _c_i32, _vp, _vp, _c_i32, _vp, _vp, _vp,
@@ -181,8 +182,10 @@ def mds_loglik(x, y, sigma, workspace, out=None, tile_rows=0, tile_waves=0, stre
 
 
 def mds_gradient(x, y, sigma, workspace, scale=None, grad=None, loglik=None, dsigma=None,
-                 want_loglik=True, want_dsigma=True, tile_rows=0, tile_waves=0, stream=None):
-    """Returns (grad N x D, loglik scalar or None, dsigma scalar or None)."""
+                 want_loglik=True, want_dsigma=True, dlogsigma=None, tile_rows=0, tile_waves=0,
+                 stream=None):
+    """Returns (grad N x D, loglik scalar or None, dsigma scalar or None); an
+    optional `dlogsigma` device scalar receives scale * sigma * dL/dsigma."""
     _check_mat(x, "x")
     _check_mat(y, "y", y.dtype)
     n, d = x.shape
@@ -197,8 +200,9 @@ def mds_gradient(x, y, sigma, workspace, scale=None, grad=None, loglik=None, dsi
         dsigma = torch.empty((), dtype=torch.float64, device=dev)
     _check(lib().mds_gradient(n, d, _ptr(x), _ld(x), _ptr(y), _dtype_code(y.dtype),
                               _ld(y), _ptr(sig), _ptr(sc), _ptr(grad), _ld(grad),
-                              _ptr(loglik), _ptr(dsigma), _ptr(workspace), workspace.numel(),
-                              tile_rows, tile_waves, _stream(stream)), "mds_gradient")
+                              _ptr(loglik), _ptr(dsigma), _ptr(dlogsigma), _ptr(workspace),
+                              workspace.numel(), tile_rows, tile_waves, _stream(stream)),
+           "mds_gradient")
     return grad, loglik, dsigma
 
 
@@ -279,10 +283,11 @@ class MDSProblem:
         return mds_loglik(x, self.y, sigma, self.workspace, out, self.tile_rows,
                           self.tile_waves, stream)
 
-    def gradient(self, x, sigma, scale=None, grad=None, loglik=None, dsigma=None, stream=None):
+    def gradient(self, x, sigma, scale=None, grad=None, loglik=None, dsigma=None,
+                 want_loglik=True, want_dsigma=True, dlogsigma=None, stream=None):
         return mds_gradient(x, self.y, sigma, self.workspace, scale, grad, loglik, dsigma,
-                            tile_rows=self.tile_rows, tile_waves=self.tile_waves,
-                            stream=stream)
+                            want_loglik, want_dsigma, dlogsigma, tile_rows=self.tile_rows,
+                            tile_waves=self.tile_waves, stream=stream)
 
     def leapfrog(self, x, p, sigma, step, n_steps, grad_io, loglik_io, cache_valid=False,
                  inv_mass=None, prior=None, energy_start=None, energy_end=None, stream=None):

@@ -263,15 +263,15 @@ int mds_loglik(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y
 int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
                  int32_t y_dtype, int64_t ldy, const double* sigma_dev, const double* scale_dev,
                  double* grad, int64_t ldg, double* loglik_dev, double* dsigma_dev,
-                 void* workspace, size_t workspace_bytes, int32_t tile_rows,
-                 int32_t tile_waves, hipStream_t stream)
+                 double* dlogsigma_dev, void* workspace, size_t workspace_bytes,
+                 int32_t tile_rows, int32_t tile_waves, hipStream_t stream)
 {
     int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
     if (st) return st;
     if (n > 0 && !grad) return fail(MDS_ERR_INVALID_ARGUMENT, "grad is NULL");
     if (ldg < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldg=%lld < d=%d", (long long)ldg, d);
     if (!aligned(grad, 8) || !aligned(loglik_dev, 8) || !aligned(dsigma_dev, 8) ||
-        !aligned(scale_dev, 8))
+        !aligned(dlogsigma_dev, 8) || !aligned(scale_dev, 8))
         return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned output pointer");
     Tiling t;
     if ((st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t))) return st;
@@ -287,6 +287,7 @@ int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void*
     fa.ldg = ldg;
     fa.loglik = loglik_dev;
     fa.dsigma = dsigma_dev;
+    fa.dlogsigma = dlogsigma_dev;
     e = launch_finalize(d, fa, stream);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
     return MDS_OK;

@@ -132,7 +132,8 @@ struct FinalizeArgs {
     double* grad;            // N x D output (ldg)
     int64_t ldg;
     double* loglik;          // optional
-    double* dsigma;          // optional
+    double* dsigma;          // optional: scale * dL/dsigma
+    double* dlogsigma;       // optional: scale * sigma * dL/dsigma
     // leapfrog extensions (all optional)
     const double* prior;     // lambda: grad -= lambda * x
     double* x;               // positions (ldx), drifted if drift != 0

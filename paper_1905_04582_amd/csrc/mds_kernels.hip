@@ -84,6 +84,7 @@ __global__ void __launch_bounds__(kWave * kFinChunks) finalize_kernel(FinalizeAr
             const double ds = (m > 0.0) ? (-m / sigma + s[1][0]) * scale : 0.0;
             if (a.loglik) *a.loglik = L;
             if (a.dsigma) *a.dsigma = ds;
+            if (a.dlogsigma) *a.dlogsigma = ds * sigma;
         }
         return;
     }

@@ -97,8 +97,8 @@ def test_loglik_rejects_before_any_hip_call(kw, code):
 
 def test_gradient_rejects():
     L = api.lib()
-    args = [100, 2, _p(), 2, _p(), 0, 128, _p(), None, _p(), 2, None, None, _p(), 1 << 30, 0,
-            0, None]
+    args = [100, 2, _p(), 2, _p(), 0, 128, _p(), None, _p(), 2, None, None, None, _p(),
+            1 << 30, 0, 0, None]
     ok = list(args)
     bad = list(ok); bad[9] = None          # grad NULL
     assert L.mds_gradient(*bad) == ERR_ARG
@@ -106,7 +106,9 @@ def test_gradient_rejects():
     assert L.mds_gradient(*bad) == ERR_ARG
     bad = list(ok); bad[8] = _p(FAKE + 1)  # misaligned scale
     assert L.mds_gradient(*bad) == ERR_ARG
-    bad = list(ok); bad[14] = 16           # workspace too small
+    bad = list(ok); bad[13] = _p(FAKE + 4)  # misaligned dlogsigma
+    assert L.mds_gradient(*bad) == ERR_ARG
+    bad = list(ok); bad[15] = 16           # workspace too small
     assert L.mds_gradient(*bad) == ERR_WS
 
 
