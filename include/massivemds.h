@@ -187,6 +187,62 @@ int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_
 int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count,
                 int32_t precision, hipStream_t stream);
 
+/* ------------------------------------------------------------ batches -- */
+
+/* One independent problem of a batch (every pointer a device pointer). */
+typedef struct mds_problem_desc {
+    int64_t n;             /* locations */
+    int32_t d;             /* latent dimension, 1..MDS_MAX_DIM */
+    int32_t tile_rows;     /* rows per tile (32/64/128/256), 0 = default for (dtype, d, n) */
+    const double* x;       /* N x D FP64, leading dimension ldx */
+    int64_t ldx;
+    const void* y;         /* prepared Y, the batch's y_dtype, leading dimension ldy */
+    int64_t ldy;
+    const double* sigma;   /* device double, > 0 */
+    const double* scale;   /* optional device double: multiplies grad, dsigma, dlogsigma */
+    double* grad;          /* N x D FP64, leading dimension ldg (may be NULL for loglik only) */
+    int64_t ldg;
+    double* loglik;        /* optional device doubles */
+    double* dsigma;
+    double* dlogsigma;
+} mds_problem_desc;
+
+/* What mds_batch_init leaves for mds_batch_eval: plain sizes and the
+ * workspace it was initialised in.  Owned by the caller; no resources. */
+typedef struct mds_batch_plan {
+    int32_t count;
+    int32_t y_dtype;
+    int32_t tile_waves;
+    int32_t grid;            /* persistent work-groups */
+    int64_t total_tiles;
+    int64_t elem_blocks;
+    size_t lds_bytes;
+    void* workspace;
+    size_t workspace_bytes;
+} mds_batch_plan;
+
+/*
+ * Many independent problems (uneven N, D) in one persistent sweep launch and
+ * one finalize launch per evaluation.  Each problem's results equal, bit for
+ * bit, those of mds_gradient with the same tile_rows and tile_waves.
+ *   mds_batch_workspace_bytes: workspace for the batch (tile_waves common to
+ *     the batch, 0 = 4; y_dtype common to the batch).
+ *   mds_batch_init: validates every descriptor, writes the device-side
+ *     problem table into the workspace with one host-to-device copy on
+ *     `stream` and waits for it (not capturable; call once per batch layout),
+ *     and fills *plan.  The descriptors' pointers are baked into the table:
+ *     later calls read and write those same buffers.
+ *   mds_batch_eval: one evaluation of every problem (want_grad = 0: L only)
+ *     on `stream`; asynchronous, allocation-free, capturable.  Calls sharing
+ *     a workspace must not overlap.
+ */
+int mds_batch_workspace_bytes(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
+                              int32_t tile_waves, size_t* bytes);
+int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
+                   int32_t tile_waves, void* workspace, size_t workspace_bytes,
+                   mds_batch_plan* plan, hipStream_t stream);
+int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t stream);
+
 /*
  * Diagnostics for benchmarks: while set (non-NULL), every pair-sweep kernel
  * launched by this thread is bracketed by hipEventRecord(before, stream) and

@@ -30,6 +30,20 @@ _vp = ctypes.c_void_p
 _lib = None
 
 
+class ProblemDesc(ctypes.Structure):
+    """mirror of mds_problem_desc"""
+    _fields_ = [("n", _c_i64), ("d", _c_i32), ("tile_rows", _c_i32), ("x", _vp), ("ldx", _c_i64),
+                ("y", _vp), ("ldy", _c_i64), ("sigma", _vp), ("scale", _vp), ("grad", _vp),
+                ("ldg", _c_i64), ("loglik", _vp), ("dsigma", _vp), ("dlogsigma", _vp)]
+
+
+class BatchPlan(ctypes.Structure):
+    """mirror of mds_batch_plan"""
+    _fields_ = [("count", _c_i32), ("y_dtype", _c_i32), ("tile_waves", _c_i32), ("grid", _c_i32),
+                ("total_tiles", _c_i64), ("elem_blocks", _c_i64), ("lds_bytes", ctypes.c_size_t),
+                ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t)]
+
+
 class MDSError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where} failed with {status}: {detail}")
@@ -72,6 +86,14 @@ def lib():
     L.mds_log_phi.argtypes = [_vp, _vp, _vp, _c_i64, _c_i32, _vp]
     L.mds_set_sweep_events.restype = ctypes.c_int
     L.mds_set_sweep_events.argtypes = [_vp, _vp]
+    L.mds_batch_workspace_bytes.restype = ctypes.c_int
+    L.mds_batch_workspace_bytes.argtypes = [ctypes.POINTER(ProblemDesc), _c_i32, _c_i32, _c_i32,
+                                            ctypes.POINTER(ctypes.c_size_t)]
+    L.mds_batch_init.restype = ctypes.c_int
+    L.mds_batch_init.argtypes = [ctypes.POINTER(ProblemDesc), _c_i32, _c_i32, _c_i32, _vp,
+                                 ctypes.c_size_t, ctypes.POINTER(BatchPlan), _vp]
+    L.mds_batch_eval.restype = ctypes.c_int
+    L.mds_batch_eval.argtypes = [ctypes.POINTER(BatchPlan), _c_i32, _vp]
     _lib = L
     return L
 
@@ -258,9 +280,12 @@ class MDSProblem:
     """
 
     def __init__(self, y, d: int, mask=None, dtype=torch.float64, device="cuda",
-                 tile_rows: int = 0, tile_waves: int = 0):
+                 tile_rows: int = 0, tile_waves: int = 0, autotuned: bool = False):
         y = torch.as_tensor(y)
         n = y.shape[0]
+        if autotuned and tile_rows == 0 and tile_waves == 0:
+            from . import autotune
+            tile_rows, tile_waves = autotune.lookup(dtype, int(d), n, device)
         src = y.to(device=device, dtype=torch.float64 if y.dtype == torch.float64 else
                    torch.float32).contiguous()
         m = None
@@ -294,3 +319,98 @@ class MDSProblem:
         mds_leapfrog(x, p, self.y, sigma, step, n_steps, self.workspace, grad_io, loglik_io,
                      cache_valid, inv_mass, prior, energy_start, energy_end, self.tile_rows,
                      self.tile_waves, stream)
+
+
+class MDSBatch:
+    """Independent problems evaluated together: one persistent sweep launch and
+    one finalize launch per ``eval()``.
+
+    problems  list of dicts {"y": N x N, "d": D, "mask": optional, "tile_rows": 0}
+    dtype     Y storage/arithmetic (float32 or float64), common to the batch
+
+    The batch owns static device buffers that the kernels read and write:
+    ``x[k]`` (N_k x D_k, write your positions there), ``grad[k]``, and the
+    per-problem scalars ``sigma``, ``scale``, ``loglik``, ``dsigma``,
+    ``dlogsigma`` (float64 tensors of length count).
+    """
+
+    def __init__(self, problems, dtype=torch.float32, device="cuda", tile_waves: int = 0,
+                 stream=None, autotuned: bool = False):
+        self.device = torch.device(device)
+        if autotuned:
+            problems, tile_waves = _autotuned_batch(problems, dtype, device, tile_waves)
+        self.dtype = dtype
+        f64 = dict(dtype=torch.float64, device=self.device)
+        count = len(problems)
+        self.count = count
+        self.ys, self.m_obs, self.x, self.grad = [], [], [], []
+        self._scal = torch.zeros((5, count), **f64)
+        self.sigma, self.scale, self.loglik, self.dsigma, self.dlogsigma = self._scal
+        self.sigma.fill_(1.0)
+        self.scale.fill_(1.0)
+        descs = (ProblemDesc * count)()
+        for k, pr in enumerate(problems):
+            y = torch.as_tensor(pr["y"])
+            src = y.to(device=self.device, dtype=torch.float64 if y.dtype == torch.float64
+                       else torch.float32).contiguous()
+            m = pr.get("mask")
+            if m is not None:
+                m = (torch.as_tensor(m) != 0).to(device=self.device, dtype=torch.uint8).contiguous()
+            yp, mo = mds_prepare_y(src, dtype, m, stream=stream)
+            del src, m
+            n, d = y.shape[0], int(pr["d"])
+            xk = torch.zeros((n, d), **f64)
+            gk = torch.zeros((n, d), **f64)
+            self.ys.append(yp)
+            self.m_obs.append(mo)
+            self.x.append(xk)
+            self.grad.append(gk)
+            q = descs[k]
+            q.n, q.d, q.tile_rows = n, d, int(pr.get("tile_rows", 0))
+            q.x, q.ldx = xk.data_ptr(), max(d, 1)
+            q.y, q.ldy = yp.data_ptr(), _ld(yp)
+            q.sigma = self.sigma.data_ptr() + 8 * k
+            q.scale = self.scale.data_ptr() + 8 * k
+            q.grad, q.ldg = gk.data_ptr(), max(d, 1)
+            q.loglik = self.loglik.data_ptr() + 8 * k
+            q.dsigma = self.dsigma.data_ptr() + 8 * k
+            q.dlogsigma = self.dlogsigma.data_ptr() + 8 * k
+        self._descs = descs
+        code = _dtype_code(dtype)
+        nb = ctypes.c_size_t(0)
+        _check(lib().mds_batch_workspace_bytes(descs, count, code, tile_waves, ctypes.byref(nb)),
+               "mds_batch_workspace_bytes")
+        self.workspace = alloc_workspace(int(nb.value), self.device)
+        self.plan = BatchPlan()
+        _check(lib().mds_batch_init(descs, count, code, tile_waves, _ptr(self.workspace),
+                                    self.workspace.numel(), ctypes.byref(self.plan),
+                                    _stream(stream)), "mds_batch_init")
+
+    def set_x(self, k, x):
+        self.x[k].copy_(torch.as_tensor(x, dtype=torch.float64))
+
+    def eval(self, want_grad: bool = True, stream=None):
+        _check(lib().mds_batch_eval(ctypes.byref(self.plan), 1 if want_grad else 0,
+                                    _stream(stream)), "mds_batch_eval")
+
+
+def _autotuned_batch(problems, dtype, device, tile_waves):
+    """Per-problem row tiles from the autotune cache under one common width:
+    the width most problems' entries chose, and each problem's tuned row tile
+    when it is compatible with that width (else the library default)."""
+    from collections import Counter
+
+    from . import autotune
+    picks = [autotune.lookup(dtype, int(p["d"]), int(torch.as_tensor(p["y"]).shape[0]), device)
+             for p in problems]
+    if tile_waves == 0:
+        widths = Counter(w for _, w in picks if w)
+        tile_waves = widths.most_common(1)[0][0] if widths else 0
+    out = []
+    for p, (br, w) in zip(problems, picks):
+        q = dict(p)
+        cw = 64 * (tile_waves or 4)
+        if br and "tile_rows" not in p and (br % cw == 0 or cw % br == 0):
+            q["tile_rows"] = br
+        out.append(q)
+    return out, tile_waves

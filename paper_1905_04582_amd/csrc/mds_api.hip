@@ -4,6 +4,9 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <string>
+#include <vector>
+
 #include "../../include/massivemds.h"
 #include "mds_internal.h"
 
@@ -381,6 +384,165 @@ int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count, in
         return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
     hipError_t e = launch_log_phi(t, lnphi, mills, count, precision, stream);
     if (e != hipSuccess) return hip_fail(e, "log_phi launch");
+    return MDS_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+namespace {
+
+constexpr int kFinElemsPerBlock = 64;  // finalize element block (one wave wide)
+
+struct BatchLayout {
+    size_t table;   // BatchProblem[count]
+    size_t cursor;  // uint64 tile cursor
+    std::vector<size_t> ws;  // per-problem partial buffers
+    std::vector<Tiling> tilings;
+    size_t total;
+};
+
+int batch_layout(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
+                 int32_t tile_waves, BatchLayout* L, size_t* max_lds)
+{
+    if (count < 1) return fail(MDS_ERR_INVALID_ARGUMENT, "count=%d < 1", count);
+    if (!descs) return fail(MDS_ERR_INVALID_ARGUMENT, "descs is NULL");
+    if (y_dtype != MDS_F64 && y_dtype != MDS_F32)
+        return fail(MDS_ERR_UNSUPPORTED, "y_dtype=%d unsupported", y_dtype);
+    const int waves = tile_waves ? tile_waves : 4;
+    size_t off = 0;
+    L->table = off;
+    off = align_up(off + sizeof(BatchProblem) * (size_t)count, 256);
+    L->cursor = off;
+    off = align_up(off + sizeof(unsigned long long), 256);
+    L->ws.resize(count);
+    L->tilings.resize(count);
+    *max_lds = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        const mds_problem_desc& q = descs[k];
+        int st = check_problem(q.n, q.d, q.x, q.ldx, q.y, y_dtype, q.ldy, q.sigma);
+        if (st) return fail(st, "problem %d: %s", k, std::string(g_last_error).c_str());
+        if (q.grad && q.ldg < q.d) return fail(MDS_ERR_INVALID_ARGUMENT, "problem %d: ldg < d", k);
+        if (!aligned(q.grad, 8) || !aligned(q.loglik, 8) || !aligned(q.dsigma, 8) ||
+            !aligned(q.dlogsigma, 8) || !aligned(q.scale, 8))
+            return fail(MDS_ERR_INVALID_ARGUMENT, "problem %d: misaligned pointer", k);
+        Tiling t;
+        if ((st = resolve_tiling(q.n, q.d, y_dtype, q.tile_rows, waves, &t)))
+            return fail(st, "problem %d: %s", k, std::string(g_last_error).c_str());
+        L->tilings[k] = t;
+        L->ws[k] = off;
+        off = align_up(off + workspace_layout(t, q.d).total, 256);
+        const size_t lds = sweep_lds_bytes(t, q.d);
+        if (lds > *max_lds) *max_lds = lds;
+    }
+    L->total = off;
+    return MDS_OK;
+}
+
+int device_cu_count(int* cus)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    return MDS_OK;
+}
+
+}  // namespace
+
+int mds_batch_workspace_bytes(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
+                              int32_t tile_waves, size_t* bytes)
+{
+    if (!bytes) return fail(MDS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    BatchLayout L;
+    size_t lds;
+    int st = batch_layout(descs, count, y_dtype, tile_waves, &L, &lds);
+    if (st) return st;
+    *bytes = L.total;
+    return MDS_OK;
+}
+
+int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
+                   int32_t tile_waves, void* workspace, size_t workspace_bytes,
+                   mds_batch_plan* plan, hipStream_t stream)
+{
+    if (!plan) return fail(MDS_ERR_INVALID_ARGUMENT, "plan is NULL");
+    BatchLayout L;
+    size_t max_lds;
+    int st = batch_layout(descs, count, y_dtype, tile_waves, &L, &max_lds);
+    if (st) return st;
+    if (!workspace) return fail(MDS_ERR_INVALID_ARGUMENT, "workspace is NULL");
+    if (!aligned(workspace, MDS_WORKSPACE_ALIGN))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "workspace must be %d-byte aligned",
+                    MDS_WORKSPACE_ALIGN);
+    if (workspace_bytes < L.total)
+        return fail(MDS_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu B < %zu B needed",
+                    workspace_bytes, L.total);
+    const int waves = tile_waves ? tile_waves : 4;
+
+    // host image of [table | cursor]; copied in one transfer
+    std::vector<unsigned char> img(L.cursor + sizeof(unsigned long long), 0);
+    BatchProblem* tab = reinterpret_cast<BatchProblem*>(img.data());
+    char* base = static_cast<char*>(workspace);
+    int64_t tiles = 0, blocks = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        const mds_problem_desc& q = descs[k];
+        const Tiling& t = L.tilings[k];
+        BatchProblem P = {};
+        P.sweep = sweep_args(t, workspace_layout(t, q.d), base + L.ws[k], q.n, q.x, q.ldx, q.y,
+                             q.ldy, q.sigma);
+        P.d = q.d;
+        P.tile_base = tiles;
+        P.ntiles = t.ntiles;
+        P.blk_base = blocks;
+        P.nblk = q.grad ? (q.n * q.d + kFinElemsPerBlock - 1) / kFinElemsPerBlock : 0;
+        P.scale = q.scale;
+        P.grad = q.grad;
+        P.ldg = q.ldg;
+        P.loglik = q.loglik;
+        P.dsigma = q.dsigma;
+        P.dlogsigma = q.dlogsigma;
+        tab[k] = P;
+        tiles += t.ntiles;
+        blocks += P.nblk;
+    }
+    hipError_t e = hipMemcpyAsync(workspace, img.data(), img.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "batch table upload");
+
+    int cus = 0;
+    if ((st = device_cu_count(&cus))) return st;
+    const int per_cu = batch_sweep_blocks_per_cu(y_dtype, true, waves, max_lds);
+    plan->count = count;
+    plan->y_dtype = y_dtype;
+    plan->tile_waves = waves;
+    plan->grid = cus * per_cu;
+    plan->total_tiles = tiles;
+    plan->elem_blocks = blocks;
+    plan->lds_bytes = max_lds;
+    plan->workspace = workspace;
+    plan->workspace_bytes = workspace_bytes;
+    return MDS_OK;
+}
+
+int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t stream)
+{
+    if (!plan || !plan->workspace || plan->count < 1)
+        return fail(MDS_ERR_INVALID_ARGUMENT, "plan is not initialised");
+    char* base = static_cast<char*>(plan->workspace);
+    const BatchProblem* probs = reinterpret_cast<const BatchProblem*>(base);
+    unsigned long long* cursor = reinterpret_cast<unsigned long long*>(
+        base + align_up(sizeof(BatchProblem) * (size_t)plan->count, 256));
+    hipError_t e = hipSuccess;
+    if (g_ev_before && (e = hipEventRecord(g_ev_before, stream)) != hipSuccess)
+        return hip_fail(e, "event record");
+    e = launch_batch_sweep(plan->y_dtype, want_grad != 0, probs, plan->count, plan->total_tiles,
+                           cursor, plan->tile_waves, plan->lds_bytes, plan->grid, stream);
+    if (e != hipSuccess) return hip_fail(e, "batch sweep launch");
+    if (g_ev_after && (e = hipEventRecord(g_ev_after, stream)) != hipSuccess)
+        return hip_fail(e, "event record");
+    e = launch_batch_finalize(probs, plan->count, want_grad ? plan->elem_blocks : 0, cursor,
+                              stream);
+    if (e != hipSuccess) return hip_fail(e, "batch finalize launch");
     return MDS_OK;
 }
 

@@ -146,9 +146,32 @@ struct FinalizeArgs {
     int drift;
 };
 
+// One problem of a batch, as the persistent kernels see it (device table).
+struct BatchProblem {
+    SweepArgs sweep;      // the problem's sweep arguments and partial buffers
+    int32_t d;
+    int32_t pad_;
+    int64_t tile_base;    // global index of the problem's first tile
+    int64_t ntiles;
+    int64_t blk_base;     // first finalize element block of the problem
+    int64_t nblk;         // finalize element blocks of the problem
+    const double* scale;  // optional upstream scale
+    double* grad;
+    int64_t ldg;
+    double* loglik;
+    double* dsigma;
+    double* dlogsigma;
+};
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
                         hipStream_t s);
 hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_batch_sweep(int y_dtype, bool grad, const BatchProblem* probs, int32_t count,
+                              int64_t total_tiles, unsigned long long* cursor, int waves,
+                              size_t lds, int grid, hipStream_t s);
+int batch_sweep_blocks_per_cu(int y_dtype, bool grad, int waves, size_t lds);
+hipError_t launch_batch_finalize(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
+                                 unsigned long long* cursor, hipStream_t s);
 
 }  // namespace mds

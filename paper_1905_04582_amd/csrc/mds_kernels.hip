@@ -10,10 +10,34 @@ namespace mds {
 hipError_t launch_sweep_f64(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_f32(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s);
 
+hipError_t launch_batch_sweep_f64(bool grad, const BatchProblem* probs, int32_t count,
+                                 int64_t total_tiles, unsigned long long* cursor, int waves,
+                                 size_t lds, int grid, hipStream_t s);
+hipError_t launch_batch_sweep_f32(bool grad, const BatchProblem* probs, int32_t count,
+                                 int64_t total_tiles, unsigned long long* cursor, int waves,
+                                 size_t lds, int grid, hipStream_t s);
+int batch_sweep_blocks_per_cu_f64(bool grad, int waves, size_t lds);
+int batch_sweep_blocks_per_cu_f32(bool grad, int waves, size_t lds);
+
 hipError_t launch_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
                         hipStream_t s)
 {
     return y_dtype == 0 ? launch_sweep_f64(d, grad, t, a, s) : launch_sweep_f32(d, grad, t, a, s);
+}
+
+hipError_t launch_batch_sweep(int y_dtype, bool grad, const BatchProblem* probs, int32_t count,
+                              int64_t total_tiles, unsigned long long* cursor, int waves,
+                              size_t lds, int grid, hipStream_t s)
+{
+    return y_dtype == 0
+               ? launch_batch_sweep_f64(grad, probs, count, total_tiles, cursor, waves, lds, grid, s)
+               : launch_batch_sweep_f32(grad, probs, count, total_tiles, cursor, waves, lds, grid, s);
+}
+
+int batch_sweep_blocks_per_cu(int y_dtype, bool grad, int waves, size_t lds)
+{
+    return y_dtype == 0 ? batch_sweep_blocks_per_cu_f64(grad, waves, lds)
+                        : batch_sweep_blocks_per_cu_f32(grad, waves, lds);
 }
 
 constexpr int kFinBlock = 256;
@@ -49,49 +73,51 @@ __device__ void block_sum3(double& a, double& b, double& c)
 // sums in chunk order.  Every order is fixed, so the result is reproducible.
 constexpr int kFinChunks = 8;
 
-__global__ void __launch_bounds__(kWave * kFinChunks) finalize_kernel(FinalizeArgs a, int D)
+// The scalar part: L, dL/dsigma and dL/d(ln sigma) from the per-tile sums,
+// by the first kFinBlock threads of a work-group, in a fixed tree order.
+__device__ void finalize_scalars(const FinalizeArgs& a, double scale)
 {
-    const double scale = a.scale ? *a.scale : 1.0;
-    if (blockIdx.x == gridDim.x - 1) {
-        // the scalar work-group uses its first kFinBlock threads
-        __shared__ double s[3][kFinBlock];
-        const int t = threadIdx.x;
-        double sr = 0.0, ss = 0.0, sm = 0.0;
-        if (t < kFinBlock)
-            for (int64_t u = t; u < a.ntiles; u += kFinBlock) {
-                sr += a.tscal[2 * u + 0];
-                ss += a.tscal[2 * u + 1];
-                sm += (double)a.tcount[u];
-            }
-        if (t < kFinBlock) {
-            s[0][t] = sr;
-            s[1][t] = ss;
-            s[2][t] = sm;
+    __shared__ double s[3][kFinBlock];
+    const int t = threadIdx.x;
+    double sr = 0.0, ss = 0.0, sm = 0.0;
+    if (t < kFinBlock)
+        for (int64_t u = t; u < a.ntiles; u += kFinBlock) {
+            sr += a.tscal[2 * u + 0];
+            ss += a.tscal[2 * u + 1];
+            sm += (double)a.tcount[u];
+        }
+    if (t < kFinBlock) {
+        s[0][t] = sr;
+        s[1][t] = ss;
+        s[2][t] = sm;
+    }
+    __syncthreads();
+    for (int h = kFinBlock / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            s[0][t] += s[0][t + h];
+            s[1][t] += s[1][t + h];
+            s[2][t] += s[2][t + h];
         }
         __syncthreads();
-        for (int h = kFinBlock / 2; h > 0; h >>= 1) {
-            if (t < h) {
-                s[0][t] += s[0][t + h];
-                s[1][t] += s[1][t + h];
-                s[2][t] += s[2][t + h];
-            }
-            __syncthreads();
-        }
-        if (t == 0) {
-            const double sigma = *a.sigma;
-            const double m = s[2][0];  // an exact integer below 2^53
-            const double L = (m > 0.0) ? -m * log(sigma) - s[0][0] : 0.0;
-            const double ds = (m > 0.0) ? (-m / sigma + s[1][0]) * scale : 0.0;
-            if (a.loglik) *a.loglik = L;
-            if (a.dsigma) *a.dsigma = ds;
-            if (a.dlogsigma) *a.dlogsigma = ds * sigma;
-        }
-        return;
     }
+    if (t == 0) {
+        const double sigma = *a.sigma;
+        const double m = s[2][0];  // an exact integer below 2^53
+        const double L = (m > 0.0) ? -m * log(sigma) - s[0][0] : 0.0;
+        const double ds = (m > 0.0) ? (-m / sigma + s[1][0]) * scale : 0.0;
+        if (a.loglik) *a.loglik = L;
+        if (a.dsigma) *a.dsigma = ds;
+        if (a.dlogsigma) *a.dlogsigma = ds * sigma;
+    }
+}
+
+// The gradient part for element block `blk` (64 consecutive elements).
+__device__ void finalize_elements(const FinalizeArgs& a, int D, int64_t blk, double scale)
+{
     __shared__ double part[kFinChunks][kWave];
     const int lane = threadIdx.x % kWave;
     const int chunk = threadIdx.x / kWave;
-    const int64_t e = (int64_t)blockIdx.x * kWave + lane;
+    const int64_t e = blk * kWave + lane;
     const bool live = e < a.n * D;
     const int br = a.br, cw = a.cw;
 
@@ -138,6 +164,71 @@ __global__ void __launch_bounds__(kWave * kFinChunks) finalize_kernel(FinalizeAr
             a.x[k * a.ldx + d] += eps * im * pn;
         }
     }
+}
+
+__global__ void __launch_bounds__(kWave * kFinChunks) finalize_kernel(FinalizeArgs a, int D)
+{
+    const double scale = a.scale ? *a.scale : 1.0;
+    if (blockIdx.x == gridDim.x - 1)
+        finalize_scalars(a, scale);
+    else
+        finalize_elements(a, D, blockIdx.x, scale);
+}
+
+// Batched finalize: element blocks of every problem, then one scalar block
+// per problem.  Also rewinds the persistent sweep's tile cursor for the next
+// call (this kernel runs after the sweep on the same stream).
+__global__ void __launch_bounds__(kWave * kFinChunks)
+    batch_finalize_kernel(const BatchProblem* __restrict__ probs, int32_t count,
+                          int64_t elem_blocks, unsigned long long* cursor)
+{
+    int64_t b = blockIdx.x;
+    int k;
+    if (b < elem_blocks) {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (probs[mid].blk_base <= b)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        k = lo;
+    } else {
+        k = (int)(b - elem_blocks);
+        if (k == 0 && threadIdx.x == 0) *cursor = 0ull;
+    }
+    const BatchProblem& P = probs[k];
+    FinalizeArgs a = {};
+    a.n = P.sweep.n;
+    a.br = P.sweep.br;
+    a.cw = P.sweep.cw;
+    a.nrb = P.sweep.nrb;
+    a.ntiles = P.ntiles;
+    a.rowpart = P.sweep.rowpart;
+    a.colpart = P.sweep.colpart;
+    a.tscal = P.sweep.tscal;
+    a.tcount = P.sweep.tcount;
+    a.sigma = P.sweep.sigma;
+    a.grad = P.grad;
+    a.ldg = P.ldg;
+    a.loglik = P.loglik;
+    a.dsigma = P.dsigma;
+    a.dlogsigma = P.dlogsigma;
+    const double scale = P.scale ? *P.scale : 1.0;
+    if (b < elem_blocks)
+        finalize_elements(a, P.d, b - P.blk_base, scale);
+    else
+        finalize_scalars(a, scale);
+}
+
+hipError_t launch_batch_finalize(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
+                                 unsigned long long* cursor, hipStream_t s)
+{
+    const unsigned nblk = (unsigned)(elem_blocks + count);
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(nblk), dim3(kWave * kFinChunks), 0, s, probs,
+                       count, elem_blocks, cursor);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t s)

@@ -144,19 +144,20 @@ __device__ __forceinline__ void trunc_terms<float>(float t, float& lnphi, float&
     trunc_terms_f32(t, lnphi, mills);
 }
 
+// One tile of one problem, processed by the whole work-group; `lds` is the
+// work-group's dynamic LDS (sweep_lds_bytes).  Ends with a barrier, so the
+// caller may reuse the LDS for the next tile straight away.
 template <typename T, int D, bool GRAD>
-__global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t tile, double* lds)
 {
     constexpr int RB = sweep_stage_rows(D);
     constexpr int GL = kWave / RB;  // lanes that share one row in the reduction
-    extern __shared__ double lds[];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int waves = blockDim.x / kWave;
     const int br = a.br, cw = a.cw;
 
     // tile -> (row block r, column block c)
-    const int64_t tile = blockIdx.x;
     int lo = 0, hi = a.nrb - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -311,6 +312,87 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
         a.tscal[2 * tile + 1] = ss;
         a.tcount[tile] = (uint32_t)sc;
     }
+    __syncthreads();
+}
+
+template <typename T, int D, bool GRAD>
+__global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
+{
+    extern __shared__ double lds[];
+    sweep_tile<T, D, GRAD>(a, blockIdx.x, lds);
+}
+
+// Persistent sweep over the tiles of a batch of independent problems: each
+// work-group takes the next global tile index from an atomic cursor until
+// the batch is exhausted (every work-group reaches the exit), finds the
+// problem that owns it, and runs that problem's tile with its own D.  Where
+// a tile is processed never changes what it writes, so the results are those
+// of the single-problem sweep, bit for bit.
+template <typename T, bool GRAD>
+__global__ void __launch_bounds__(512) batch_sweep_kernel(const BatchProblem* __restrict__ probs,
+                                                          int32_t count, int64_t total_tiles,
+                                                          unsigned long long* cursor)
+{
+    extern __shared__ double lds[];
+    __shared__ int64_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int64_t)atomicAdd(cursor, 1ull);
+        __syncthreads();
+        const int64_t g = next;
+        __syncthreads();
+        if (g >= total_tiles) break;
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (probs[mid].tile_base <= g)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchProblem& P = probs[lo];
+        const SweepArgs a = P.sweep;
+        const int64_t tile = g - P.tile_base;
+        switch (P.d) {
+            case 1: sweep_tile<T, 1, GRAD>(a, tile, lds); break;
+            case 2: sweep_tile<T, 2, GRAD>(a, tile, lds); break;
+            case 3: sweep_tile<T, 3, GRAD>(a, tile, lds); break;
+            case 4: sweep_tile<T, 4, GRAD>(a, tile, lds); break;
+            case 5: sweep_tile<T, 5, GRAD>(a, tile, lds); break;
+            case 6: sweep_tile<T, 6, GRAD>(a, tile, lds); break;
+            case 7: sweep_tile<T, 7, GRAD>(a, tile, lds); break;
+            default: sweep_tile<T, 8, GRAD>(a, tile, lds); break;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_batch_sweep_t(bool grad, const BatchProblem* probs, int32_t count,
+                                int64_t total_tiles, unsigned long long* cursor, int waves,
+                                size_t lds, int grid, hipStream_t s)
+{
+    if (total_tiles == 0) return hipSuccess;
+    const dim3 g((unsigned)grid), b((unsigned)(waves * kWave));
+    if (grad)
+        hipLaunchKernelGGL((batch_sweep_kernel<T, true>), g, b, lds, s, probs, count,
+                           total_tiles, cursor);
+    else
+        hipLaunchKernelGGL((batch_sweep_kernel<T, false>), g, b, lds, s, probs, count,
+                           total_tiles, cursor);
+    return hipGetLastError();
+}
+
+template <typename T>
+int batch_sweep_blocks_per_cu(bool grad, int waves, size_t lds)
+{
+    int nb = 0;
+    hipError_t e;
+    if (grad)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_sweep_kernel<T, true>,
+                                                         waves * kWave, lds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_sweep_kernel<T, false>,
+                                                         waves * kWave, lds);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 template <typename T>

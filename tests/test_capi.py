@@ -145,3 +145,35 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(api, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         api.lib()
+
+
+def test_batch_rejects():
+    L = api.lib()
+    nb = ctypes.c_size_t(0)
+    d = (api.ProblemDesc * 2)()
+    for q in d:
+        q.n, q.d, q.x, q.ldx, q.y, q.ldy, q.sigma = 100, 2, FAKE, 2, FAKE, 128, FAKE
+        q.grad, q.ldg = FAKE, 2
+    assert L.mds_batch_workspace_bytes(d, 2, 0, 0, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert L.mds_batch_workspace_bytes(d, 0, 0, 0, ctypes.byref(nb)) == ERR_ARG
+    assert L.mds_batch_workspace_bytes(None, 2, 0, 0, ctypes.byref(nb)) == ERR_ARG
+    assert L.mds_batch_workspace_bytes(d, 2, 5, 0, ctypes.byref(nb)) == ERR_UNSUP
+    assert L.mds_batch_workspace_bytes(d, 2, 0, 3, ctypes.byref(nb)) == ERR_UNSUP
+    d[1].d = 9
+    assert L.mds_batch_workspace_bytes(d, 2, 0, 0, ctypes.byref(nb)) == ERR_UNSUP
+    assert b"problem 1" in L.mds_last_error()
+    d[1].d = 2
+    d[1].ldg = 1
+    assert L.mds_batch_workspace_bytes(d, 2, 0, 0, ctypes.byref(nb)) == ERR_ARG
+    d[1].ldg = 2
+    d[0].tile_rows = 48
+    assert L.mds_batch_workspace_bytes(d, 2, 0, 0, ctypes.byref(nb)) == ERR_UNSUP
+    d[0].tile_rows = 0
+    plan = api.BatchPlan()
+    # workspace checks happen before the table upload (no HIP call)
+    assert L.mds_batch_init(d, 2, 0, 0, None, 1 << 30, ctypes.byref(plan), None) == ERR_ARG
+    assert L.mds_batch_init(d, 2, 0, 0, _p(FAKE + 8), 1 << 30, ctypes.byref(plan), None) == ERR_ARG
+    assert L.mds_batch_init(d, 2, 0, 0, _p(), 16, ctypes.byref(plan), None) == ERR_WS
+    assert L.mds_batch_init(d, 2, 0, 0, _p(), 1 << 30, None, None) == ERR_ARG
+    assert L.mds_batch_eval(None, 1, None) == ERR_ARG
+    assert L.mds_batch_eval(ctypes.byref(api.BatchPlan()), 1, None) == ERR_ARG
