@@ -124,7 +124,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-evals", type=int, default=10)
+    ap.add_argument("--only", choices=("fp64", "fp32"), default=None,
+                    help="time one form only (for profiler runs); prints a short JSON line")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run plain device copies of MB megabytes (calibrates the HBM "
+                         "byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": nbytes}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the MDS sweep is built and measured on a "
               "single MI355X (see the sharding design); run with --gpus 1", file=sys.stderr)
@@ -144,6 +159,13 @@ def main():
     m_obs = int(P64.m_obs.item())
     npairs = n * (n - 1) // 2
     events = HipEvents()
+
+    if args.only:
+        P = P64 if args.only == "fp64" else P32
+        wall, sweep, sweep_med, _ = timed_evals(P, x, sigma, args.steps, args.warmup, events)
+        print(json.dumps({"form": args.only, "steps": args.steps, "ms_per_step": wall,
+                          "sweep_ms_mean": sweep, "sweep_ms_median": sweep_med}), flush=True)
+        return
 
     wall64, sweep64, sweep64_med, (g64, L64, ds64) = timed_evals(P64, x, sigma, args.steps,
                                                                  args.warmup, events)

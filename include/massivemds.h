@@ -214,6 +214,8 @@ typedef struct mds_batch_plan {
     int32_t y_dtype;
     int32_t tile_waves;
     int32_t grid;            /* persistent work-groups */
+    int32_t max_d;           /* largest D of the batch */
+    int32_t reserved;
     int64_t total_tiles;
     int64_t elem_blocks;
     size_t lds_bytes;

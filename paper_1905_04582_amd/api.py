@@ -16,7 +16,8 @@ import os
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libmassivemds.so")
+# MDS_LIB_PATH may name another build of the same library (e.g. a variant)
+LIB_PATH = os.environ.get("MDS_LIB_PATH", os.path.join(_PKG, "libmassivemds.so"))
 
 MDS_OK = 0
 MDS_F64 = 0
@@ -40,7 +41,7 @@ class ProblemDesc(ctypes.Structure):
 class BatchPlan(ctypes.Structure):
     """mirror of mds_batch_plan"""
     _fields_ = [("count", _c_i32), ("y_dtype", _c_i32), ("tile_waves", _c_i32), ("grid", _c_i32),
-                ("total_tiles", _c_i64), ("elem_blocks", _c_i64), ("lds_bytes", ctypes.c_size_t),
+                ("max_d", _c_i32), ("reserved", _c_i32), ("total_tiles", _c_i64), ("elem_blocks", _c_i64), ("lds_bytes", ctypes.c_size_t),
                 ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t)]
 
 

@@ -100,6 +100,55 @@ def _random_problem(n, d, dtype, device, seed=0):
     return x, yp
 
 
+class _RawEvents:
+    """hipEvent_t handles for bracketing the sweep kernel alone."""
+
+    def __init__(self):
+        import ctypes
+        self.ct = ctypes
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        e = self.ct.c_void_p()
+        self.hip.hipEventCreate(self.ct.byref(e))
+        return e.value
+
+    def elapsed(self, a, b):
+        out = self.ct.c_float()
+        self.hip.hipEventElapsedTime(self.ct.byref(out), self.ct.c_void_p(a), self.ct.c_void_p(b))
+        return float(out.value)
+
+    def destroy(self, e):
+        self.hip.hipEventDestroy(self.ct.c_void_p(e))
+
+
+def time_sweep_only(x, yp, sigma, br, w, reps=20, warmup=3):
+    """Median duration (ms) of the sweep kernel alone (finalize excluded)."""
+    n, d = x.shape
+    code = api.MDS_F64 if yp.dtype == torch.float64 else api.MDS_F32
+    ws = api.alloc_workspace(api.mds_workspace_bytes(n, d, code, br, w), x.device)
+    g = torch.empty_like(x)
+    sig = torch.tensor(sigma, dtype=torch.float64, device=x.device)
+    for _ in range(warmup):
+        api.mds_gradient(x, yp, sig, ws, grad=g, tile_rows=br, tile_waves=w)
+    ev = _RawEvents()
+    pairs = [(ev.create(), ev.create()) for _ in range(reps)]
+    for a, b in pairs:
+        api.mds_set_sweep_events(a, b)
+        api.mds_gradient(x, yp, sig, ws, grad=g, tile_rows=br, tile_waves=w)
+    api.mds_set_sweep_events(None, None)
+    torch.cuda.synchronize()
+    ts = sorted(ev.elapsed(a, b) for a, b in pairs)
+    for a, b in pairs:
+        ev.destroy(a)
+        ev.destroy(b)
+    return ts[len(ts) // 2]
+
+
 def time_tiling(x, yp, sigma, br, w, reps=20, warmup=3, want_grad=True):
     n, d = x.shape
     code = api.MDS_F64 if yp.dtype == torch.float64 else api.MDS_F32
@@ -133,16 +182,19 @@ def tune(dtype, d: int, n: int, device="cuda", reps: int = 20, path: str | None 
     """Time every candidate tiling at (dtype, D, N) and record the fastest."""
     device = torch.device(device)
     x, yp = _random_problem(n, d, dtype, device)
-    results = {}
+    results, sweeps = {}, {}
     for br, w in candidates(n, d, dtype):
         results[f"{br}x{64 * w}"] = time_tiling(x, yp, 0.5, br, w, reps=reps)
+        sweeps[f"{br}x{64 * w}"] = time_sweep_only(x, yp, 0.5, br, w, reps=reps)
         if verbose:
             print(f"  {dtype} D={d} N={n} tile {br}x{64 * w}: "
-                  f"{results[f'{br}x{64 * w}'] * 1e3:.1f} us", flush=True)
+                  f"{results[f'{br}x{64 * w}'] * 1e3:.1f} us "
+                  f"(sweep {sweeps[f'{br}x{64 * w}'] * 1e3:.1f} us)", flush=True)
     best = min(results, key=results.get)
     br, cols = (int(v) for v in best.split("x"))
     entry = dict(tile_rows=br, tile_waves=cols // 64, ms=results[best], n=n,
-                 candidates_ms=results, tuned_at=time.strftime("%Y-%m-%dT%H:%M:%S"))
+                 candidates_ms=results, sweep_only_ms=sweeps,
+                 tuned_at=time.strftime("%Y-%m-%dT%H:%M:%S"))
     table = load(path)
     table[_key(_arch(device), dtype, d, n)] = entry
     save(table, path)

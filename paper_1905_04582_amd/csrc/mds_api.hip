@@ -62,11 +62,8 @@ void default_tiling(int64_t n, int d, int dtype, int* br, int* waves)
     if (n <= 2048) {
         *br = 32;
         *waves = 2;
-    } else if (n <= 8192) {
-        *br = 64;
-        *waves = 4;
     } else {
-        *br = 128;
+        *br = 64;
         *waves = 4;
     }
 }
@@ -511,8 +508,12 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
 
     int cus = 0;
     if ((st = device_cu_count(&cus))) return st;
-    const int per_cu = batch_sweep_blocks_per_cu(y_dtype, true, waves, max_lds);
+    int max_d = 1;
+    for (int32_t k = 0; k < count; ++k) max_d = descs[k].d > max_d ? descs[k].d : max_d;
+    const int per_cu = batch_sweep_blocks_per_cu(y_dtype, true, max_d, waves, max_lds);
     plan->count = count;
+    plan->max_d = max_d;
+    plan->reserved = 0;
     plan->y_dtype = y_dtype;
     plan->tile_waves = waves;
     plan->grid = cus * per_cu;
@@ -535,8 +536,9 @@ int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t st
     hipError_t e = hipSuccess;
     if (g_ev_before && (e = hipEventRecord(g_ev_before, stream)) != hipSuccess)
         return hip_fail(e, "event record");
-    e = launch_batch_sweep(plan->y_dtype, want_grad != 0, probs, plan->count, plan->total_tiles,
-                           cursor, plan->tile_waves, plan->lds_bytes, plan->grid, stream);
+    e = launch_batch_sweep(plan->y_dtype, want_grad != 0, plan->max_d, probs, plan->count,
+                           plan->total_tiles, cursor, plan->tile_waves, plan->lds_bytes,
+                           plan->grid, stream);
     if (e != hipSuccess) return hip_fail(e, "batch sweep launch");
     if (g_ev_after && (e = hipEventRecord(g_ev_after, stream)) != hipSuccess)
         return hip_fail(e, "event record");

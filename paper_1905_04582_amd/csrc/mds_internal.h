@@ -94,14 +94,28 @@ inline WorkspaceLayout workspace_layout(const Tiling& t, int d)
 
 // rows staged per reduction step of the sweep (keeps the per-wave staging
 // buffer at <= 16 doubles per lane)
-__host__ __device__ constexpr int sweep_stage_rows(int d) { return d <= 2 ? 8 : (d <= 4 ? 4 : 2); }
+#ifndef MDS_STAGE_ROWS_SMALL_D
+#define MDS_STAGE_ROWS_SMALL_D 8
+#endif
+#ifndef MDS_STAGE_ROWS_LARGE_D
+#define MDS_STAGE_ROWS_LARGE_D 2
+#endif
+__host__ __device__ constexpr int sweep_stage_rows(int d)
+{
+    return d <= 2 ? MDS_STAGE_ROWS_SMALL_D : (d <= 4 ? 4 : MDS_STAGE_ROWS_LARGE_D);
+}
+
+#ifndef MDS_STAGE_PAD_BYTES
+#define MDS_STAGE_PAD_BYTES 32
+#endif
+constexpr int kStagePadBytes = MDS_STAGE_PAD_BYTES;
 
 // LDS bytes used by one sweep work-group: tile row sums, per-wave scalars
-// and the per-wave row staging buffer
+// and the per-wave row staging buffer (rows padded by kStagePadBytes)
 inline size_t sweep_lds_bytes(const Tiling& t, int d)
 {
     return (size_t)t.waves * t.br * d * sizeof(double) + (size_t)t.waves * 4 * sizeof(double) +
-           (size_t)t.waves * sweep_stage_rows(d) * kWave * d * sizeof(double);
+           (size_t)t.waves * sweep_stage_rows(d) * (kWave * d * sizeof(double) + kStagePadBytes);
 }
 
 struct SweepArgs {
@@ -167,10 +181,10 @@ struct BatchProblem {
 hipError_t launch_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
                         hipStream_t s);
 hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t s);
-hipError_t launch_batch_sweep(int y_dtype, bool grad, const BatchProblem* probs, int32_t count,
-                              int64_t total_tiles, unsigned long long* cursor, int waves,
-                              size_t lds, int grid, hipStream_t s);
-int batch_sweep_blocks_per_cu(int y_dtype, bool grad, int waves, size_t lds);
+hipError_t launch_batch_sweep(int y_dtype, bool grad, int maxd, const BatchProblem* probs,
+                              int32_t count, int64_t total_tiles, unsigned long long* cursor,
+                              int waves, size_t lds, int grid, hipStream_t s);
+int batch_sweep_blocks_per_cu(int y_dtype, bool grad, int maxd, int waves, size_t lds);
 hipError_t launch_batch_finalize(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
                                  unsigned long long* cursor, hipStream_t s);
 

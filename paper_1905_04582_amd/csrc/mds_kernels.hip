@@ -10,14 +10,14 @@ namespace mds {
 hipError_t launch_sweep_f64(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_f32(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s);
 
-hipError_t launch_batch_sweep_f64(bool grad, const BatchProblem* probs, int32_t count,
+hipError_t launch_batch_sweep_f64(bool grad, int maxd, const BatchProblem* probs, int32_t count,
                                  int64_t total_tiles, unsigned long long* cursor, int waves,
                                  size_t lds, int grid, hipStream_t s);
-hipError_t launch_batch_sweep_f32(bool grad, const BatchProblem* probs, int32_t count,
+hipError_t launch_batch_sweep_f32(bool grad, int maxd, const BatchProblem* probs, int32_t count,
                                  int64_t total_tiles, unsigned long long* cursor, int waves,
                                  size_t lds, int grid, hipStream_t s);
-int batch_sweep_blocks_per_cu_f64(bool grad, int waves, size_t lds);
-int batch_sweep_blocks_per_cu_f32(bool grad, int waves, size_t lds);
+int batch_sweep_blocks_per_cu_f64(bool grad, int maxd, int waves, size_t lds);
+int batch_sweep_blocks_per_cu_f32(bool grad, int maxd, int waves, size_t lds);
 
 hipError_t launch_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
                         hipStream_t s)
@@ -25,19 +25,20 @@ hipError_t launch_sweep(int y_dtype, int d, bool grad, const Tiling& t, const Sw
     return y_dtype == 0 ? launch_sweep_f64(d, grad, t, a, s) : launch_sweep_f32(d, grad, t, a, s);
 }
 
-hipError_t launch_batch_sweep(int y_dtype, bool grad, const BatchProblem* probs, int32_t count,
-                              int64_t total_tiles, unsigned long long* cursor, int waves,
-                              size_t lds, int grid, hipStream_t s)
+hipError_t launch_batch_sweep(int y_dtype, bool grad, int maxd, const BatchProblem* probs,
+                              int32_t count, int64_t total_tiles, unsigned long long* cursor,
+                              int waves, size_t lds, int grid, hipStream_t s)
 {
-    return y_dtype == 0
-               ? launch_batch_sweep_f64(grad, probs, count, total_tiles, cursor, waves, lds, grid, s)
-               : launch_batch_sweep_f32(grad, probs, count, total_tiles, cursor, waves, lds, grid, s);
+    return y_dtype == 0 ? launch_batch_sweep_f64(grad, maxd, probs, count, total_tiles, cursor,
+                                                 waves, lds, grid, s)
+                        : launch_batch_sweep_f32(grad, maxd, probs, count, total_tiles, cursor,
+                                                 waves, lds, grid, s);
 }
 
-int batch_sweep_blocks_per_cu(int y_dtype, bool grad, int waves, size_t lds)
+int batch_sweep_blocks_per_cu(int y_dtype, bool grad, int maxd, int waves, size_t lds)
 {
-    return y_dtype == 0 ? batch_sweep_blocks_per_cu_f64(grad, waves, lds)
-                        : batch_sweep_blocks_per_cu_f32(grad, waves, lds);
+    return y_dtype == 0 ? batch_sweep_blocks_per_cu_f64(grad, maxd, waves, lds)
+                        : batch_sweep_blocks_per_cu_f32(grad, maxd, waves, lds);
 }
 
 constexpr int kFinBlock = 256;

@@ -147,6 +147,10 @@ __device__ __forceinline__ void trunc_terms<float>(float t, float& lnphi, float&
 // One tile of one problem, processed by the whole work-group; `lds` is the
 // work-group's dynamic LDS (sweep_lds_bytes).  Ends with a barrier, so the
 // caller may reuse the LDS for the next tile straight away.
+#ifndef MDS_ROW_UNROLL
+#define MDS_ROW_UNROLL 2
+#endif
+
 template <typename T, int D, bool GRAD>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t tile, double* lds)
 {
@@ -177,7 +181,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     // LDS: [waves][br][D] tile row sums | [waves][4] scalars | [waves][RB][64][D] staging
     double* lrows = lds + (size_t)w * br * D;
     double* lscal = lds + (size_t)waves * br * D;
-    T* stage = reinterpret_cast<T*>(lscal + (size_t)waves * 4) + (size_t)w * RB * kWave * D;
+    // staged rows are padded by 32 bytes so that the RB rows a lane group
+    // reads in the transposed reduction start in different LDS banks
+    constexpr int SROW = kWave * D + kStagePadBytes / (int)sizeof(T);
+    T* stage = reinterpret_cast<T*>(lscal + (size_t)waves * 4) + (size_t)w * RB * SROW;
     if (GRAD)
         for (int k = lane; k < br * D; k += kWave) lrows[k] = 0.0;
 
@@ -196,21 +203,27 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
 
     // rows i <= jw0 hold no pair (j < i) for any lane of this wave
     const int64_t istart = max(row0, jw0 + 1);
-    for (int64_t ib = row0 + ((istart - row0) / RB) * RB; ib < row1; ib += RB) {
+    const int64_t ib0 = row0 + ((istart - row0) / RB) * RB;
+    // Y is prefetched two rows ahead, so each row's load has two iterations
+    // of arithmetic to arrive; a lane loads only its own pairs j < i < row1
+    auto load_y = [&](int64_t i) -> T {
+        T v = T(0);
+        if (i < row1 && colok && j < i) v = Y[i * a.ldy + j];
+        return v;
+    };
+    T ypf0 = load_y(ib0), ypf1 = load_y(ib0 + 1);
+    for (int64_t ib = ib0; ib < row1; ib += RB) {
         T gjb[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) gjb[d] = T(0);
         T br_r = T(0), br_s = T(0);
         const int nq = (int)min((int64_t)RB, row1 - ib);
 
-#pragma unroll 1
-        for (int q = 0; q < nq; ++q) {
+        // the arithmetic of one pair row (row ib + q, this lane's column)
+        auto do_row = [&](const int q, const T yv) {
             const int64_t i = ib + q;
-            const T* __restrict__ yrow = Y + i * a.ldy + jw0;
             const double* __restrict__ xi = a.x + i * a.ldx;
             const bool in_tri = colok && (j < i);
-            T yv = T(0);
-            if (in_tri) yv = yrow[lane];
             const bool ok = in_tri && !isnan(yv);
 
             T dl[D];
@@ -238,7 +251,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 // w = (delta - y)/sigma^2 + m/sigma; the pair's term is w (x_i - x_j)/delta
                 const T wv = fma(mills, pc.inv_sigma, -res * pc.inv_s2);
                 const T coef = ok ? wv * rinv : T(0);
-                T* st = stage + ((size_t)q * kWave + lane) * D;
+                T* st = stage + (size_t)q * SROW + (size_t)lane * D;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
                     const T cd = coef * dl[d];
@@ -247,7 +260,33 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 }
                 br_s += ok ? fma(res2, pc.inv_s3, delta * pc.inv_s2 * mills) : T(0);
             }
+        };
+#if MDS_ROW_UNROLL >= 2
+        // two rows per iteration: independent dependency chains interleave
+        int q = 0;
+#pragma unroll 1
+        for (; q + 1 < nq; q += 2) {
+            const T ya = ypf0, yb = ypf1;
+            ypf0 = load_y(ib + q + 2);
+            ypf1 = load_y(ib + q + 3);
+            do_row(q, ya);
+            do_row(q + 1, yb);
         }
+        if (q < nq) {
+            const T ya = ypf0;
+            ypf0 = ypf1;
+            ypf1 = load_y(ib + q + 2);
+            do_row(q, ya);
+        }
+#else
+#pragma unroll 1
+        for (int q = 0; q < nq; ++q) {
+            const T ya = ypf0;
+            ypf0 = ypf1;
+            ypf1 = load_y(ib + q + 2);
+            do_row(q, ya);
+        }
+#endif
         acc_r += (double)br_r;
         if (GRAD) {
             acc_s += (double)br_s;
@@ -262,7 +301,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             if (g < nq) {
 #pragma unroll
                 for (int k = 0; k < RB; ++k) {
-                    const T* src = stage + ((size_t)g * kWave + p + k * GL) * D;
+                    const T* src = stage + (size_t)g * SROW + (size_t)(p + k * GL) * D;
 #pragma unroll
                     for (int d = 0; d < D; ++d) sum[d] += src[d];
                 }
@@ -327,8 +366,9 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
 // the batch is exhausted (every work-group reaches the exit), finds the
 // problem that owns it, and runs that problem's tile with its own D.  Where
 // a tile is processed never changes what it writes, so the results are those
-// of the single-problem sweep, bit for bit.
-template <typename T, bool GRAD>
+// of the single-problem sweep, bit for bit.  MAXD bounds the D cases compiled
+// in, so the register allocation follows the largest D of the batch.
+template <typename T, bool GRAD, int MAXD>
 __global__ void __launch_bounds__(512) batch_sweep_kernel(const BatchProblem* __restrict__ probs,
                                                           int32_t count, int64_t total_tiles,
                                                           unsigned long long* cursor)
@@ -355,44 +395,76 @@ __global__ void __launch_bounds__(512) batch_sweep_kernel(const BatchProblem* __
         switch (P.d) {
             case 1: sweep_tile<T, 1, GRAD>(a, tile, lds); break;
             case 2: sweep_tile<T, 2, GRAD>(a, tile, lds); break;
-            case 3: sweep_tile<T, 3, GRAD>(a, tile, lds); break;
-            case 4: sweep_tile<T, 4, GRAD>(a, tile, lds); break;
-            case 5: sweep_tile<T, 5, GRAD>(a, tile, lds); break;
-            case 6: sweep_tile<T, 6, GRAD>(a, tile, lds); break;
-            case 7: sweep_tile<T, 7, GRAD>(a, tile, lds); break;
-            default: sweep_tile<T, 8, GRAD>(a, tile, lds); break;
+            case 3: if constexpr (MAXD >= 3) sweep_tile<T, 3, GRAD>(a, tile, lds); break;
+            case 4: if constexpr (MAXD >= 4) sweep_tile<T, 4, GRAD>(a, tile, lds); break;
+            case 5: if constexpr (MAXD >= 5) sweep_tile<T, 5, GRAD>(a, tile, lds); break;
+            case 6: if constexpr (MAXD >= 6) sweep_tile<T, 6, GRAD>(a, tile, lds); break;
+            case 7: if constexpr (MAXD >= 7) sweep_tile<T, 7, GRAD>(a, tile, lds); break;
+            default: if constexpr (MAXD >= 8) sweep_tile<T, 8, GRAD>(a, tile, lds); break;
         }
     }
 }
 
+// smallest compiled bound that covers max_d
+inline int batch_maxd_bucket(int max_d) { return max_d <= 2 ? 2 : (max_d <= 4 ? 4 : (max_d <= 6 ? 6 : 8)); }
+
+template <typename T, bool GRAD>
+hipError_t launch_batch_sweep_g(int maxd, const BatchProblem* probs, int32_t count,
+                                int64_t total_tiles, unsigned long long* cursor, dim3 g, dim3 b,
+                                size_t lds, hipStream_t s)
+{
+    switch (batch_maxd_bucket(maxd)) {
+        case 2:
+            hipLaunchKernelGGL((batch_sweep_kernel<T, GRAD, 2>), g, b, lds, s, probs, count,
+                               total_tiles, cursor);
+            break;
+        case 4:
+            hipLaunchKernelGGL((batch_sweep_kernel<T, GRAD, 4>), g, b, lds, s, probs, count,
+                               total_tiles, cursor);
+            break;
+        case 6:
+            hipLaunchKernelGGL((batch_sweep_kernel<T, GRAD, 6>), g, b, lds, s, probs, count,
+                               total_tiles, cursor);
+            break;
+        default:
+            hipLaunchKernelGGL((batch_sweep_kernel<T, GRAD, 8>), g, b, lds, s, probs, count,
+                               total_tiles, cursor);
+            break;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_batch_sweep_t(bool grad, const BatchProblem* probs, int32_t count,
+hipError_t launch_batch_sweep_t(bool grad, int maxd, const BatchProblem* probs, int32_t count,
                                 int64_t total_tiles, unsigned long long* cursor, int waves,
                                 size_t lds, int grid, hipStream_t s)
 {
     if (total_tiles == 0) return hipSuccess;
     const dim3 g((unsigned)grid), b((unsigned)(waves * kWave));
-    if (grad)
-        hipLaunchKernelGGL((batch_sweep_kernel<T, true>), g, b, lds, s, probs, count,
-                           total_tiles, cursor);
-    else
-        hipLaunchKernelGGL((batch_sweep_kernel<T, false>), g, b, lds, s, probs, count,
-                           total_tiles, cursor);
-    return hipGetLastError();
+    return grad ? launch_batch_sweep_g<T, true>(maxd, probs, count, total_tiles, cursor, g, b,
+                                                lds, s)
+                : launch_batch_sweep_g<T, false>(maxd, probs, count, total_tiles, cursor, g, b,
+                                                 lds, s);
+}
+
+template <typename T, bool GRAD, int MAXD>
+int occupancy_of(int waves, size_t lds)
+{
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, batch_sweep_kernel<T, GRAD, MAXD>, waves * kWave, lds);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 template <typename T>
-int batch_sweep_blocks_per_cu(bool grad, int waves, size_t lds)
+int batch_sweep_blocks_per_cu(bool grad, int maxd, int waves, size_t lds)
 {
-    int nb = 0;
-    hipError_t e;
-    if (grad)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_sweep_kernel<T, true>,
-                                                         waves * kWave, lds);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_sweep_kernel<T, false>,
-                                                         waves * kWave, lds);
-    return (e == hipSuccess && nb > 0) ? nb : 1;
+    switch (batch_maxd_bucket(maxd)) {
+        case 2: return grad ? occupancy_of<T, true, 2>(waves, lds) : occupancy_of<T, false, 2>(waves, lds);
+        case 4: return grad ? occupancy_of<T, true, 4>(waves, lds) : occupancy_of<T, false, 4>(waves, lds);
+        case 6: return grad ? occupancy_of<T, true, 6>(waves, lds) : occupancy_of<T, false, 6>(waves, lds);
+        default: return grad ? occupancy_of<T, true, 8>(waves, lds) : occupancy_of<T, false, 8>(waves, lds);
+    }
 }
 
 template <typename T>

@@ -8,15 +8,16 @@ hipError_t launch_sweep_f32(int d, bool grad, const Tiling& t, const SweepArgs& 
     return launch_sweep_t<float>(d, grad, t, a, s);
 }
 
-hipError_t launch_batch_sweep_f32(bool grad, const BatchProblem* probs, int32_t count,
+hipError_t launch_batch_sweep_f32(bool grad, int maxd, const BatchProblem* probs, int32_t count,
                                  int64_t total_tiles, unsigned long long* cursor, int waves,
                                  size_t lds, int grid, hipStream_t s)
 {
-    return launch_batch_sweep_t<float>(grad, probs, count, total_tiles, cursor, waves, lds, grid, s);
+    return launch_batch_sweep_t<float>(grad, maxd, probs, count, total_tiles, cursor, waves, lds,
+                                     grid, s);
 }
 
-int batch_sweep_blocks_per_cu_f32(bool grad, int waves, size_t lds)
+int batch_sweep_blocks_per_cu_f32(bool grad, int maxd, int waves, size_t lds)
 {
-    return batch_sweep_blocks_per_cu<float>(grad, waves, lds);
+    return batch_sweep_blocks_per_cu<float>(grad, maxd, waves, lds);
 }
 }  // namespace mds
