@@ -109,14 +109,52 @@ int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows
  *   y_out       N x N, dtype out_dtype, leading dimension ldy; receives
  *               y_src converted to out_dtype, with NaN where the mask is set
  *               or y_src is NaN.  y_out may alias y_src only when the two
- *               dtypes and leading dimensions are equal.
+ *               dtypes and leading dimensions are equal and perm is NULL.
+ *   perm        optional device int64[N] (NULL = identity): relabel the
+ *               locations, y_out[k][l] = y_src[perm[k]][perm[l]] (the mask
+ *               likewise).  perm must be a permutation of 0..N-1; an entry
+ *               outside that range makes its pairs missing.
  *   m_obs_dev   optional device int64: the number of observed pairs i > j.
  * Missing data are not part of the paper's model; they are excluded from
  * every sum and from M.
  */
 int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src,
                   const uint8_t* missing, int64_t ld_mask, void* y_out, int32_t out_dtype,
-                  int64_t ldy, int64_t n, int64_t* m_obs_dev, hipStream_t stream);
+                  int64_t ldy, int64_t n, const int64_t* perm, int64_t* m_obs_dev,
+                  hipStream_t stream);
+
+/*
+ * Spatial relabelling of the locations (a set-up step, not part of the
+ * paper's method).  L of Eq. (2) sums over unordered pairs, so relabelling
+ * the locations leaves L and dL/dsigma unchanged and permutes the gradient
+ * rows of Eq. (9).  Under an order that keeps nearby locations at nearby
+ * indices, the sweep skips the truncation terms of whole wavefronts whose
+ * pairs all lie beyond its skip point, which makes every evaluation cheaper.
+ *   x          N x D FP64 (ldx): the locations to order by (typically the
+ *              starting X of a chain)
+ *   perm       device int64[N] receiving the order: position k holds the
+ *              original index of the k-th location along a Hilbert curve
+ *              (D = 2) or in bit-interleaved (Morton) order (other D), over
+ *              the bounding box of x quantised to 32-bit keys; ties keep
+ *              index order.  Use it with mds_prepare_y(perm) for Y and
+ *              mds_permute_rows for X, P and the gradient.
+ *   workspace  device scratch of mds_order_workspace_bytes(n) bytes
+ *              (MDS_WORKSPACE_ALIGN-aligned)
+ */
+int mds_order_workspace_bytes(int64_t n, size_t* bytes);
+int mds_spatial_order(int64_t n, int32_t d, const double* x, int64_t ldx, int64_t* perm,
+                      void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Relabel the rows of an N x D FP64 array by a permutation from
+ * mds_spatial_order:
+ *   inverse == 0: dst[k] = src[perm[k]]   (original labels -> relabelled)
+ *   inverse != 0: dst[perm[k]] = src[k]   (relabelled -> original labels)
+ * src and dst must not overlap.  An out-of-range perm entry writes a NaN row
+ * (inverse == 0) or nothing (inverse != 0).
+ */
+int mds_permute_rows(int64_t n, int32_t d, const double* src, int64_t ld_src, double* dst,
+                     int64_t ld_dst, const int64_t* perm, int32_t inverse, hipStream_t stream);
 
 /*
  * Log-likelihood L of Eq. (2) (see the header comment).

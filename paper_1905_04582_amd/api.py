@@ -5,7 +5,8 @@ kernels of the library.  torch supplies device memory and the current stream.
 If the library is missing the binding raises -- there is no CPU fallback.
 
 Low-level functions carry the C names (``mds_loglik``, ``mds_gradient``,
-``mds_leapfrog``, ``mds_prepare_y``, ``mds_log_phi``, ``mds_workspace_bytes``);
+``mds_leapfrog``, ``mds_prepare_y``, ``mds_spatial_order``, ``mds_permute_rows``,
+``mds_log_phi``, ``mds_workspace_bytes``);
 ``MDSProblem`` bundles a prepared Y with its workspace.
 """
 from __future__ import annotations
@@ -71,7 +72,13 @@ def lib():
                                       ctypes.POINTER(ctypes.c_size_t)]
     L.mds_prepare_y.restype = ctypes.c_int
     L.mds_prepare_y.argtypes = [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _c_i32, _c_i64, _c_i64,
-                                _vp, _vp]
+                                _vp, _vp, _vp]
+    L.mds_order_workspace_bytes.restype = ctypes.c_int
+    L.mds_order_workspace_bytes.argtypes = [_c_i64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mds_spatial_order.restype = ctypes.c_int
+    L.mds_spatial_order.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _vp, ctypes.c_size_t, _vp]
+    L.mds_permute_rows.restype = ctypes.c_int
+    L.mds_permute_rows.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i64, _vp, _c_i32, _vp]
     L.mds_loglik.restype = ctypes.c_int
     L.mds_loglik.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i64, _vp, _vp, _vp,
                              ctypes.c_size_t, _c_i32, _c_i32, _vp]
@@ -172,10 +179,13 @@ def padded_ld(n: int) -> int:
 
 
 def mds_prepare_y(y_src: torch.Tensor, out_dtype: torch.dtype = torch.float64, mask=None,
-                  ldy: int | None = None, count: bool = True, stream=None):
-    """Y -> device Y' in out_dtype with missing entries folded into NaN.
+                  ldy: int | None = None, count: bool = True, perm=None, stream=None):
+    """Y -> device Y' in out_dtype with missing entries folded into NaN,
+    relabelled by ``perm`` (Y'[k, l] = Y[perm[k], perm[l]]) when given.
     Returns (y_prepared N x ldy view, m_obs device int64 tensor or None)."""
     _check_mat(y_src, "y_src", y_src.dtype)
+    if perm is not None:
+        _check_perm(perm, y_src.shape[0], y_src.device)
     n = y_src.shape[0]
     if y_src.shape[1] < n:
         raise ValueError("y_src must be N x N")
@@ -186,9 +196,42 @@ def mds_prepare_y(y_src: torch.Tensor, out_dtype: torch.dtype = torch.float64, m
     m_obs = torch.zeros((), dtype=torch.int64, device=y_src.device) if count else None
     _check(lib().mds_prepare_y(_ptr(y_src), _dtype_code(y_src.dtype), _ld(y_src),
                                _ptr(mask), _ld(mask) if mask is not None else 0,
-                               _ptr(buf), _dtype_code(out_dtype), ldy, n, _ptr(m_obs),
-                               _stream(stream)), "mds_prepare_y")
+                               _ptr(buf), _dtype_code(out_dtype), ldy, n, _ptr(perm),
+                               _ptr(m_obs), _stream(stream)), "mds_prepare_y")
     return buf[:n], m_obs
+
+
+def _check_perm(perm, n, device):
+    if not (isinstance(perm, torch.Tensor) and perm.dtype == torch.int64 and perm.is_contiguous()
+            and perm.dim() == 1 and perm.numel() == n and perm.device == torch.device(device)):
+        raise ValueError("perm must be a contiguous int64 device tensor of length N")
+
+
+def mds_spatial_order(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """Locality-preserving order of the rows of x (Hilbert curve for D = 2,
+    Morton order otherwise): perm[k] = original index of the k-th location."""
+    _check_mat(x, "x")
+    n, d = x.shape
+    nb = ctypes.c_size_t()
+    _check(lib().mds_order_workspace_bytes(n, ctypes.byref(nb)), "mds_order_workspace_bytes")
+    ws = alloc_workspace(nb.value, x.device)
+    perm = torch.empty(max(n, 1), dtype=torch.int64, device=x.device)[:n]
+    _check(lib().mds_spatial_order(n, d, _ptr(x), _ld(x), _ptr(perm), _ptr(ws), nb.value,
+                                   _stream(stream)), "mds_spatial_order")
+    return perm
+
+
+def mds_permute_rows(src: torch.Tensor, perm: torch.Tensor, inverse: bool = False, out=None,
+                     stream=None) -> torch.Tensor:
+    """out[k] = src[perm[k]] (inverse=False) or out[perm[k]] = src[k] (inverse=True)."""
+    _check_mat(src, "src")
+    n, d = src.shape
+    _check_perm(perm, n, src.device)
+    out = torch.empty_like(src) if out is None else out
+    _check_mat(out, "out")
+    _check(lib().mds_permute_rows(n, d, _ptr(src), _ld(src), _ptr(out), _ld(out), _ptr(perm),
+                                  1 if inverse else 0, _stream(stream)), "mds_permute_rows")
+    return out
 
 
 def mds_loglik(x, y, sigma, workspace, out=None, tile_rows=0, tile_waves=0, stream=None):
@@ -278,10 +321,14 @@ class MDSProblem:
     y      N x N (numpy or torch, any device), symmetric
     mask   optional N x N, non-zero = missing
     dtype  torch.float64 (FP64 form) or torch.float32 (FP32 form)
+    order  optional N x D locations (e.g. the chain's starting X): the problem
+           is stored relabelled in their spatial order (``perm``), and every
+           X, P and gradient passed to its methods is in that labelling --
+           ``relabel`` / ``unlabel`` convert N x D arrays to and from it.
     """
 
     def __init__(self, y, d: int, mask=None, dtype=torch.float64, device="cuda",
-                 tile_rows: int = 0, tile_waves: int = 0, autotuned: bool = False):
+                 tile_rows: int = 0, tile_waves: int = 0, autotuned: bool = False, order=None):
         y = torch.as_tensor(y)
         n = y.shape[0]
         if autotuned and tile_rows == 0 and tile_waves == 0:
@@ -293,11 +340,26 @@ class MDSProblem:
         if mask is not None:
             m = (torch.as_tensor(mask) != 0).to(device=device, dtype=torch.uint8).contiguous()
         self.n, self.d, self.dtype, self.device = n, int(d), dtype, torch.device(device)
-        self.y, self.m_obs = mds_prepare_y(src, dtype, m)
+        self.perm = None
+        if order is not None:
+            xo = torch.as_tensor(order).to(device=device, dtype=torch.float64).contiguous()
+            self.perm = mds_spatial_order(xo)
+        self.y, self.m_obs = mds_prepare_y(src, dtype, m, perm=self.perm)
         del src, m
         self.tile_rows, self.tile_waves = tile_rows, tile_waves
         self.ws_bytes = mds_workspace_bytes(n, self.d, _dtype_code(dtype), tile_rows, tile_waves)
         self.workspace = alloc_workspace(self.ws_bytes, self.device)
+
+    def relabel(self, a, out=None, stream=None):
+        """N x D array in the caller's labelling -> the problem's labelling."""
+        a = torch.as_tensor(a).to(device=self.device, dtype=torch.float64).contiguous()
+        return a.clone() if self.perm is None else mds_permute_rows(a, self.perm, False, out,
+                                                                    stream)
+
+    def unlabel(self, a, out=None, stream=None):
+        """N x D array in the problem's labelling -> the caller's labelling."""
+        return a.clone() if self.perm is None else mds_permute_rows(a, self.perm, True, out,
+                                                                    stream)
 
     def set_tiling(self, tile_rows: int, tile_waves: int):
         nb = mds_workspace_bytes(self.n, self.d, _dtype_code(self.dtype), tile_rows, tile_waves)

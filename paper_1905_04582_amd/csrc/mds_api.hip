@@ -19,7 +19,12 @@ hipError_t launch_energy(int64_t n, int d, const double* x, int64_t ldx, const d
                          const double* loglik, double* out, hipStream_t s);
 hipError_t launch_prepare(const void* src, int sdt, int64_t ld_src, const uint8_t* mask,
                           int64_t ld_mask, void* out, int odt, int64_t ldy, int64_t n,
-                          int64_t* count, hipStream_t s);
+                          const int64_t* perm, int64_t* count, hipStream_t s);
+size_t order_workspace_bytes(int64_t n);
+hipError_t launch_order(int64_t n, int d, const double* x, int64_t ldx, int64_t* perm, void* ws,
+                        hipStream_t s);
+hipError_t launch_permute_rows(int64_t n, int d, const double* src, int64_t ld_src, double* dst,
+                               int64_t ld_dst, const int64_t* perm, int inverse, hipStream_t s);
 hipError_t launch_log_phi(const double* t, double* lnphi, double* mills, int64_t count, int prec,
                           hipStream_t s);
 }  // namespace mds
@@ -52,19 +57,23 @@ size_t dtype_size(int dt) { return dt == MDS_F64 ? 8 : 4; }
 // Largest LDS a sweep work-group may use (row sums of all its waves).
 constexpr size_t kMaxSweepLds = 64 * 1024;
 
-// Tile shape used when the caller passes 0: 64 rows x 256 columns keeps the
-// grid well above the 256 compute units for N >= ~4000 and the partial
-// buffers small; smaller problems use narrower tiles to fill the chip.
+// Tile shape used when the caller passes 0.  Many small work-groups keep
+// every SIMD supplied with waves and let the dispatcher balance tiles of
+// uneven cost (tiles whose wavefronts skip the truncation terms are cheap):
+// FP64 uses 32 rows x 256 columns, FP32 64 x 128 (measured at N = 5392 on
+// spatially ordered locations); small problems use 32 x 128.
 void default_tiling(int64_t n, int d, int dtype, int* br, int* waves)
 {
-    (void)dtype;
     (void)d;
     if (n <= 2048) {
         *br = 32;
         *waves = 2;
+    } else if (dtype == MDS_F64) {
+        *br = 32;
+        *waves = 4;
     } else {
         *br = 64;
-        *waves = 4;
+        *waves = 2;
     }
 }
 
@@ -216,7 +225,7 @@ int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows
 
 int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src, const uint8_t* missing,
                   int64_t ld_mask, void* y_out, int32_t out_dtype, int64_t ldy, int64_t n,
-                  int64_t* m_obs_dev, hipStream_t stream)
+                  const int64_t* perm, int64_t* m_obs_dev, hipStream_t stream)
 {
     if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
     if ((src_dtype != MDS_F64 && src_dtype != MDS_F32) ||
@@ -230,9 +239,56 @@ int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src, const ui
         return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
     if (y_src == y_out && n > 0 && (src_dtype != out_dtype || ld_src != ldy))
         return fail(MDS_ERR_INVALID_ARGUMENT, "in-place prepare needs equal dtype and stride");
+    if (y_src == y_out && n > 0 && perm)
+        return fail(MDS_ERR_INVALID_ARGUMENT, "a relabelling prepare cannot run in place");
+    if (!aligned(perm, 8)) return fail(MDS_ERR_INVALID_ARGUMENT, "perm misaligned");
     hipError_t e = launch_prepare(y_src, src_dtype, ld_src, missing, ld_mask, y_out, out_dtype,
-                                  ldy, n, m_obs_dev, stream);
+                                  ldy, n, perm, m_obs_dev, stream);
     if (e != hipSuccess) return hip_fail(e, "prepare launch");
+    return MDS_OK;
+}
+
+int mds_order_workspace_bytes(int64_t n, size_t* bytes)
+{
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if (!bytes) return fail(MDS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    *bytes = order_workspace_bytes(n);
+    return MDS_OK;
+}
+
+int mds_spatial_order(int64_t n, int32_t d, const double* x, int64_t ldx, int64_t* perm,
+                      void* workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if (d < 1 || d > MDS_MAX_DIM)
+        return fail(MDS_ERR_UNSUPPORTED, "d=%d: must be 1..%d", d, MDS_MAX_DIM);
+    if (ldx < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldx < d");
+    if (n > 0 && (!x || !perm || !workspace))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "x, perm and workspace must be non-NULL");
+    if (!aligned(x, 8) || !aligned(perm, 8) || !aligned(workspace, MDS_WORKSPACE_ALIGN))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    if (workspace_bytes < order_workspace_bytes(n))
+        return fail(MDS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed",
+                    workspace_bytes, order_workspace_bytes(n));
+    hipError_t e = launch_order(n, d, x, ldx, perm, workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "order launch");
+    return MDS_OK;
+}
+
+int mds_permute_rows(int64_t n, int32_t d, const double* src, int64_t ld_src, double* dst,
+                     int64_t ld_dst, const int64_t* perm, int32_t inverse, hipStream_t stream)
+{
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if (d < 1 || d > MDS_MAX_DIM)
+        return fail(MDS_ERR_UNSUPPORTED, "d=%d: must be 1..%d", d, MDS_MAX_DIM);
+    if (ld_src < d || ld_dst < d) return fail(MDS_ERR_INVALID_ARGUMENT, "leading dimension < d");
+    if (n > 0 && (!src || !dst || !perm))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "src, dst and perm must be non-NULL");
+    if (n > 0 && src == dst) return fail(MDS_ERR_INVALID_ARGUMENT, "src and dst must differ");
+    if (!aligned(src, 8) || !aligned(dst, 8) || !aligned(perm, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    hipError_t e = launch_permute_rows(n, d, src, ld_src, dst, ld_dst, perm, inverse, stream);
+    if (e != hipSuccess) return hip_fail(e, "permute launch");
     return MDS_OK;
 }
 

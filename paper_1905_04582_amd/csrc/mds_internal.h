@@ -9,7 +9,6 @@
 namespace mds {
 
 constexpr int kWave = 64;     // CDNA wavefront width
-constexpr int kRowBatch = 8;  // rows reduced together by the in-wave transpose-reduce
 
 // Tile geometry of the lower-triangle pair sweep.
 //

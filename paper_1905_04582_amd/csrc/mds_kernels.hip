@@ -73,6 +73,7 @@ __device__ void block_sum3(double& a, double& b, double& c)
 // elements per wave: coalesced reads), and wave 0 adds the kFinChunks chunk
 // sums in chunk order.  Every order is fixed, so the result is reproducible.
 constexpr int kFinChunks = 8;
+constexpr int kFinUnroll = 8;  // partial loads in flight per lane
 
 // The scalar part: L, dL/dsigma and dL/d(ln sigma) from the per-tile sums,
 // by the first kFinBlock threads of a work-group, in a fixed tree order.
@@ -136,14 +137,23 @@ __device__ void finalize_elements(const FinalizeArgs& a, int D, int64_t blk, dou
         const int64_t coff = k - (int64_t)c * cw;
         const int rb0 = first_row_block_of_column(c, br, cw);
         const int64_t total = nrow + (a.nrb - rb0);
-        for (int64_t it = chunk; it < total; it += kFinChunks) {
-            if (it < nrow) {
-                s += a.rowpart[((t0 + it) * br + roff) * D + d];
-            } else {
-                const int rb = rb0 + (int)(it - nrow);
-                s += a.colpart[((tiles_before(rb, br, cw) + c) * cw + coff) * D + d];
-            }
+        // items chunk, chunk + kFinChunks, ... of the list (row-side
+        // partials, then column-side ones), added in list order; the loads
+        // of kFinUnroll items are issued before their adds
+        auto item = [&](int64_t it) -> double {
+            if (it < nrow) return a.rowpart[((t0 + it) * br + roff) * D + d];
+            const int rb = rb0 + (int)(it - nrow);
+            return a.colpart[((tiles_before(rb, br, cw) + c) * cw + coff) * D + d];
+        };
+        int64_t it = chunk;
+        for (; it + (kFinUnroll - 1) * kFinChunks < total; it += kFinUnroll * kFinChunks) {
+            double v[kFinUnroll];
+#pragma unroll
+            for (int u = 0; u < kFinUnroll; ++u) v[u] = item(it + u * kFinChunks);
+#pragma unroll
+            for (int u = 0; u < kFinUnroll; ++u) s += v[u];
         }
+        for (; it < total; it += kFinChunks) s += item(it);
     }
     part[chunk][lane] = s;
     __syncthreads();
@@ -311,18 +321,36 @@ __global__ void zero_i64_kernel(int64_t* p)
 template <typename S, typename O>
 __global__ void __launch_bounds__(256)
     prepare_kernel(const S* src, int64_t ld_src, const uint8_t* mask, int64_t ld_mask, O* out,
-                   int64_t ldy, int64_t n, unsigned long long* count)
+                   int64_t ldy, int64_t n, const int64_t* perm, unsigned long long* count)
 {
     const int64_t i = blockIdx.x;
-    const S* srow = src + i * ld_src;
-    const uint8_t* mrow = mask ? mask + i * ld_mask : nullptr;
     O* orow = out + i * ldy;
     int obs = 0;
-    for (int64_t j = threadIdx.x; j < n; j += 256) {
-        const S v = srow[j];
-        const bool miss = (mrow && mrow[j] != 0) || isnan(v);
-        orow[j] = miss ? (O)NAN : (O)v;
-        obs += (!miss && j < i) ? 1 : 0;
+    if (perm) {
+        // relabelled: out[i][j] = src[perm[i]][perm[j]]; an index out of
+        // range reads as a missing pair
+        const int64_t si = perm[i];
+        const bool rok = si >= 0 && si < n;
+        for (int64_t j = threadIdx.x; j < n; j += 256) {
+            const int64_t sj = perm[j];
+            bool miss = !(rok && sj >= 0 && sj < n);
+            S v = (S)0;
+            if (!miss) {
+                v = src[si * ld_src + sj];
+                miss = (mask && mask[si * ld_mask + sj] != 0) || isnan(v);
+            }
+            orow[j] = miss ? (O)NAN : (O)v;
+            obs += (!miss && j < i) ? 1 : 0;
+        }
+    } else {
+        const S* srow = src + i * ld_src;
+        const uint8_t* mrow = mask ? mask + i * ld_mask : nullptr;
+        for (int64_t j = threadIdx.x; j < n; j += 256) {
+            const S v = srow[j];
+            const bool miss = (mrow && mrow[j] != 0) || isnan(v);
+            orow[j] = miss ? (O)NAN : (O)v;
+            obs += (!miss && j < i) ? 1 : 0;
+        }
     }
     if (count) {
         __shared__ int wsum[256 / kWave];
@@ -340,7 +368,7 @@ __global__ void __launch_bounds__(256)
 
 hipError_t launch_prepare(const void* src, int sdt, int64_t ld_src, const uint8_t* mask,
                           int64_t ld_mask, void* out, int odt, int64_t ldy, int64_t n,
-                          int64_t* count, hipStream_t s)
+                          const int64_t* perm, int64_t* count, hipStream_t s)
 {
     if (count) {
         hipLaunchKernelGGL(zero_i64_kernel, dim3(1), dim3(64), 0, s, count);
@@ -352,16 +380,16 @@ hipError_t launch_prepare(const void* src, int sdt, int64_t ld_src, const uint8_
     unsigned long long* c = reinterpret_cast<unsigned long long*>(count);
     if (sdt == 0 && odt == 0)
         hipLaunchKernelGGL((prepare_kernel<double, double>), grid, dim3(256), 0, s,
-                           (const double*)src, ld_src, mask, ld_mask, (double*)out, ldy, n, c);
+                           (const double*)src, ld_src, mask, ld_mask, (double*)out, ldy, n, perm, c);
     else if (sdt == 0 && odt == 1)
         hipLaunchKernelGGL((prepare_kernel<double, float>), grid, dim3(256), 0, s,
-                           (const double*)src, ld_src, mask, ld_mask, (float*)out, ldy, n, c);
+                           (const double*)src, ld_src, mask, ld_mask, (float*)out, ldy, n, perm, c);
     else if (sdt == 1 && odt == 0)
         hipLaunchKernelGGL((prepare_kernel<float, double>), grid, dim3(256), 0, s,
-                           (const float*)src, ld_src, mask, ld_mask, (double*)out, ldy, n, c);
+                           (const float*)src, ld_src, mask, ld_mask, (double*)out, ldy, n, perm, c);
     else
         hipLaunchKernelGGL((prepare_kernel<float, float>), grid, dim3(256), 0, s,
-                           (const float*)src, ld_src, mask, ld_mask, (float*)out, ldy, n, c);
+                           (const float*)src, ld_src, mask, ld_mask, (float*)out, ldy, n, perm, c);
     return hipGetLastError();
 }
 

@@ -54,15 +54,28 @@ __device__ __forceinline__ double fma_sc(double acc, double x, double c)
 // immediates, which a 64-bit VALU operand cannot encode.
 typedef const __attribute__((address_space(4))) double* const_f64_ptr;
 
+#ifndef MDS_COEF_SMOV
+#define MDS_COEF_SMOV 0
+#endif
+
 template <int N>
 __device__ __forceinline__ double horner_tab(const double (&tab)[N], double x)
 {
+#if MDS_COEF_SMOV
+    // coefficients folded by the compiler and materialised in scalar
+    // registers (scalar moves issue beside the vector FMAs)
+    double acc = fma_sc(tab[N - 1], x, tab[N - 2]);
+#pragma unroll
+    for (int k = N - 3; k >= 0; --k) acc = fma_sc(acc, x, tab[k]);
+    return acc;
+#else
     const_f64_ptr c = (const_f64_ptr)tab;
     asm volatile("" : "+s"(c));
     double acc = fma_sc(c[N - 1], x, c[N - 2]);
 #pragma unroll
     for (int k = N - 3; k >= 0; --k) acc = fma_sc(acc, x, c[k]);
     return acc;
+#endif
 }
 
 // ---------------------------------------------------------------- FP64 --

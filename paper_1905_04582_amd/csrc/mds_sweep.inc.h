@@ -10,10 +10,12 @@
 //     one row, a fully coalesced load of the lower triangle;
 //   * each pair's gradient term goes to row j (+) and row i (-) -- each pair
 //     is evaluated once.  The column side stays in the lane's registers for
-//     the whole tile.  The row side is a sum across the 64 lanes; 8 rows are
-//     reduced together by a butterfly transpose-reduce (exchange halves at
-//     distances 32, 16, 8, then a 3-step reduction), which costs about 1.25
-//     exchanges per row instead of 6;
+//     the whole tile.  The row side is a sum across the 64 lanes: the lanes
+//     stage their terms of a few rows in LDS, then every (row, dimension)
+//     output is summed by a small group of lanes reading the staged values
+//     and finished by log2(group) exchanges;
+//   * a wavefront whose pairs in a row all have delta/sigma beyond a skip
+//     point branches over the special functions as a whole (no divergence);
 //   * the waves' row sums meet in LDS and are added in wave order; column,
 //     row and scalar partials of the tile go to the workspace, and the
 //     finalize kernel adds them in a fixed order.  No atomics: the result is
@@ -32,42 +34,6 @@ template <typename T>
 __device__ __forceinline__ T shfl_xor_t(T v, int m)
 {
     return __shfl_xor(v, m, kWave);
-}
-
-// In-wave transpose-reduce of 8 rows x D values: afterwards lane l holds in
-// v[0][*] the sum over all 64 lanes of row (l >> 3).
-template <typename T, int D>
-__device__ __forceinline__ void rowbatch_reduce(T (&v)[kRowBatch][D], int lane)
-{
-    const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const T lo = v[k][d], hi = v[k + 4][d];
-            const T keep = h32 ? hi : lo, send = h32 ? lo : hi;
-            v[k][d] = keep + shfl_xor_t(send, 32);
-        }
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const T lo = v[k][d], hi = v[k + 2][d];
-            const T keep = h16 ? hi : lo, send = h16 ? lo : hi;
-            v[k][d] = keep + shfl_xor_t(send, 16);
-        }
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const T lo = v[0][d], hi = v[1][d];
-        const T keep = h8 ? hi : lo, send = h8 ? lo : hi;
-        v[0][d] = keep + shfl_xor_t(send, 8);
-    }
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        v[0][d] += shfl_xor_t(v[0][d], 4);
-        v[0][d] += shfl_xor_t(v[0][d], 2);
-        v[0][d] += shfl_xor_t(v[0][d], 1);
-    }
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -144,18 +110,60 @@ __device__ __forceinline__ void trunc_terms<float>(float t, float& lnphi, float&
     trunc_terms_f32(t, lnphi, mills);
 }
 
+// Per-pair quantities computed before the special functions.
+template <typename T, int D>
+struct PairGeom {
+    T dl[D];   // x_i - x_j
+    T delta;   // |x_i - x_j|
+    T rinv;    // 1/delta (0 for a coincident pair)
+    T t;       // delta / sigma
+    T res;     // y - delta
+    bool ok;   // an observed pair of the strict lower triangle
+};
+
+// Skip point of the truncation terms.  For t >= T, 0 <= -ln Phi(t) <=
+// 2 Phi(-T) and phi(t)/Phi(t) <= 2 phi(T): below 2.3e-19 and 2.1e-18 for the
+// FP64 sweep (T = 9), below 8.1e-11 and 5.4e-10 for the FP32 sweep (T = 6.5),
+// each far under the rounding of the pair's other terms in that precision.
+template <typename T>
+__device__ __forceinline__ T skip_t();
+template <>
+__device__ __forceinline__ double skip_t<double>()
+{
+    return 9.0;
+}
+template <>
+__device__ __forceinline__ float skip_t<float>()
+{
+    return 6.5f;
+}
+
 // One tile of one problem, processed by the whole work-group; `lds` is the
 // work-group's dynamic LDS (sweep_lds_bytes).  Ends with a barrier, so the
 // caller may reuse the LDS for the next tile straight away.
 #ifndef MDS_ROW_UNROLL
 #define MDS_ROW_UNROLL 2
 #endif
+#ifndef MDS_REDUCE_PER_OUTPUT
+#define MDS_REDUCE_PER_OUTPUT 1
+#endif
+#ifndef MDS_PREFETCH_X
+#define MDS_PREFETCH_X 0
+#endif
+
+// lanes per output in the row reduction: the largest power of two g with
+// outputs * g <= 64
+__host__ __device__ constexpr int reduce_group(int outputs)
+{
+    int g = 64;
+    while (g > 1 && outputs * g > 64) g >>= 1;
+    return g;
+}
 
 template <typename T, int D, bool GRAD>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t tile, double* lds)
 {
     constexpr int RB = sweep_stage_rows(D);
-    constexpr int GL = kWave / RB;  // lanes that share one row in the reduction
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int waves = blockDim.x / kWave;
@@ -205,13 +213,30 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     const int64_t istart = max(row0, jw0 + 1);
     const int64_t ib0 = row0 + ((istart - row0) / RB) * RB;
     // Y is prefetched two rows ahead, so each row's load has two iterations
-    // of arithmetic to arrive; a lane loads only its own pairs j < i < row1
-    auto load_y = [&](int64_t i) -> T {
-        T v = T(0);
-        if (i < row1 && colok && j < i) v = Y[i * a.ldy + j];
-        return v;
+    // of arithmetic to arrive.  The load itself is unconditional (row clamped
+    // into the tile, column into the matrix; lanes outside the triangle
+    // discard the value through `ok`), so no branch splits the wave and the
+    // wait before a row's first use leaves the two newer loads in flight.
+    // x_i is uniform across the wave and comes through scalar loads (X is
+    // read-only during the sweep, so the constant address space is valid);
+    // with MDS_PREFETCH_X it is fetched together with the row's Y values.
+    const int64_t jc = colok ? j : 0;
+    struct RowIn {
+        T y;
+        double x[D];
     };
-    T ypf0 = load_y(ib0), ypf1 = load_y(ib0 + 1);
+    auto load_y = [&](int64_t i) -> RowIn {
+        RowIn r;
+        const int64_t ic = min(i, row1 - 1);
+        r.y = Y[ic * a.ldy + jc];
+#if MDS_PREFETCH_X
+        const const_f64_ptr xp = (const_f64_ptr)(a.x + ic * a.ldx);
+#pragma unroll
+        for (int d = 0; d < D; ++d) r.x[d] = xp[d];
+#endif
+        return r;
+    };
+    RowIn ypf0 = load_y(ib0), ypf1 = load_y(ib0 + 1);
     for (int64_t ib = ib0; ib < row1; ib += RB) {
         T gjb[D];
 #pragma unroll
@@ -219,72 +244,95 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
         T br_r = T(0), br_s = T(0);
         const int nq = (int)min((int64_t)RB, row1 - ib);
 
-        // the arithmetic of one pair row (row ib + q, this lane's column)
-        auto do_row = [&](const int q, const T yv) {
+        // geometry of one pair row (row ib + q, this lane's column)
+        auto geom = [&](const int q, const RowIn& rin, PairGeom<T, D>& g) {
             const int64_t i = ib + q;
-            const double* __restrict__ xi = a.x + i * a.ldx;
-            const bool in_tri = colok && (j < i);
-            const bool ok = in_tri && !isnan(yv);
-
-            T dl[D];
+            const T yv = rin.y;
+#if MDS_PREFETCH_X
+            const double* xi = rin.x;
+#else
+            const const_f64_ptr xi = (const_f64_ptr)(a.x + i * a.ldx);
+#endif
+            g.ok = colok && (j < i) && !isnan(yv);
             T s2 = T(0);
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                dl[d] = (T)(xi[d] - xj[d]);
-                s2 = fma(dl[d], dl[d], s2);
+                g.dl[d] = (T)(xi[d] - xj[d]);
+                s2 = fma(g.dl[d], g.dl[d], s2);
             }
             // delta and 1/delta from one reciprocal square root; a coincident
             // pair (s2 below the normal range) has delta = 0 and no direction
             const bool pos = s2 >= min_normal<T>();
             const T sg = pos ? s2 : T(1);
             const T rs = rsqrt_t(sg);
-            const T delta = pos ? sg * rs : T(0);
-            const T rinv = pos ? rs : T(0);
-            const T t = delta * pc.inv_sigma;
-            T lnphi, mills;
-            trunc_terms<T>(t, lnphi, mills);
-            const T res = yv - delta;
-            const T res2 = res * res;
-            br_r += ok ? fma(res2, pc.half_inv_s2, lnphi) : T(0);
-            cnt += ok ? 1 : 0;
+            g.delta = pos ? sg * rs : T(0);
+            g.rinv = pos ? rs : T(0);
+            g.t = g.delta * pc.inv_sigma;
+            g.res = yv - g.delta;
+        };
+        // the pair's terms given ln Phi(t) and phi(t)/Phi(t)
+        auto accum = [&](const int q, const PairGeom<T, D>& g, const T lnphi, const T mills) {
+            const T res2 = g.res * g.res;
+            br_r += g.ok ? fma(res2, pc.half_inv_s2, lnphi) : T(0);
+            cnt += g.ok ? 1 : 0;
             if (GRAD) {
                 // w = (delta - y)/sigma^2 + m/sigma; the pair's term is w (x_i - x_j)/delta
-                const T wv = fma(mills, pc.inv_sigma, -res * pc.inv_s2);
-                const T coef = ok ? wv * rinv : T(0);
+                const T wv = fma(mills, pc.inv_sigma, -g.res * pc.inv_s2);
+                const T coef = g.ok ? wv * g.rinv : T(0);
                 T* st = stage + (size_t)q * SROW + (size_t)lane * D;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    const T cd = coef * dl[d];
+                    const T cd = coef * g.dl[d];
                     st[d] = -cd;
                     gjb[d] += cd;
                 }
-                br_s += ok ? fma(res2, pc.inv_s3, delta * pc.inv_s2 * mills) : T(0);
+                br_s += g.ok ? fma(res2, pc.inv_s3, g.delta * pc.inv_s2 * mills) : T(0);
             }
         };
+        // when no observed pair of the row(s) in this wave has t below the
+        // skip point, the wave takes ln Phi = m = 0 and skips the special
+        // functions (a wave-uniform branch; lanes never diverge)
+        auto needs_tail = [&](const PairGeom<T, D>& g) { return g.ok && g.t < skip_t<T>(); };
 #if MDS_ROW_UNROLL >= 2
         // two rows per iteration: independent dependency chains interleave
         int q = 0;
 #pragma unroll 1
         for (; q + 1 < nq; q += 2) {
-            const T ya = ypf0, yb = ypf1;
+            const RowIn ya = ypf0, yb = ypf1;
             ypf0 = load_y(ib + q + 2);
             ypf1 = load_y(ib + q + 3);
-            do_row(q, ya);
-            do_row(q + 1, yb);
+            PairGeom<T, D> ga, gb;
+            geom(q, ya, ga);
+            geom(q + 1, yb, gb);
+            T la = T(0), ma = T(0), lb = T(0), mb = T(0);
+            if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb))) {
+                trunc_terms<T>(ga.t, la, ma);
+                trunc_terms<T>(gb.t, lb, mb);
+            }
+            accum(q, ga, la, ma);
+            accum(q + 1, gb, lb, mb);
         }
         if (q < nq) {
-            const T ya = ypf0;
+            const RowIn ya = ypf0;
             ypf0 = ypf1;
             ypf1 = load_y(ib + q + 2);
-            do_row(q, ya);
+            PairGeom<T, D> ga;
+            geom(q, ya, ga);
+            T la = T(0), ma = T(0);
+            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) trunc_terms<T>(ga.t, la, ma);
+            accum(q, ga, la, ma);
         }
 #else
 #pragma unroll 1
         for (int q = 0; q < nq; ++q) {
-            const T ya = ypf0;
+            const RowIn ya = ypf0;
             ypf0 = ypf1;
             ypf1 = load_y(ib + q + 2);
-            do_row(q, ya);
+            PairGeom<T, D> ga;
+            geom(q, ya, ga);
+            T la = T(0), ma = T(0);
+            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) trunc_terms<T>(ga.t, la, ma);
+            accum(q, ga, la, ma);
         }
 #endif
         acc_r += (double)br_r;
@@ -292,8 +340,29 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             acc_s += (double)br_s;
 #pragma unroll
             for (int d = 0; d < D; ++d) gj[d] += (double)gjb[d];
+#if MDS_REDUCE_PER_OUTPUT
+            // transposed reduction of the staged rows: each (row, dimension)
+            // output of the batch gets RG lanes; lane h of its group adds the
+            // staged values of lanes h, h+RG, ..., then the group combines by
+            // log2(RG) exchanges
+            constexpr int NO = RB * D;
+            constexpr int RG = reduce_group(NO);
+            const int o = lane / RG, h = lane % RG;
+            const int orow = o / D, odim = o % D;
+            const bool live = o < NO && orow < nq;
+            T sum = T(0);
+            if (live) {
+                const T* src = stage + (size_t)orow * SROW + (size_t)h * D + odim;
+#pragma unroll
+                for (int k = 0; k < kWave / RG; ++k) sum += src[(size_t)k * RG * D];
+            }
+#pragma unroll
+            for (int m = RG / 2; m >= 1; m >>= 1) sum += shfl_xor_t(sum, m);
+            if (live && h == 0) lrows[(ib - row0 + orow) * D + odim] = (double)sum;
+#else
             // transposed reduction of the staged rows: lane (g, p) adds the
             // values of lanes p, p+GL, ... of row g, then GL lanes combine
+            constexpr int GL = kWave / RB;
             const int g = lane / GL, p = lane % GL;
             T sum[D];
 #pragma unroll
@@ -315,6 +384,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
 #pragma unroll
                 for (int d = 0; d < D; ++d) lrows[row * D + d] = (double)sum[d];
             }
+#endif
         }
     }
 

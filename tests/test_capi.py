@@ -130,14 +130,40 @@ def test_leapfrog_rejects():
 
 def test_prepare_and_log_phi_reject():
     L = api.lib()
-    assert L.mds_prepare_y(_p(), 0, 10, None, 0, _p(), 3, 10, 10, None, None) == ERR_UNSUP
-    assert L.mds_prepare_y(_p(), 0, 9, None, 0, _p(), 0, 10, 10, None, None) == ERR_ARG
-    assert L.mds_prepare_y(_p(), 0, 10, _p(), 5, _p(), 0, 10, 10, None, None) == ERR_ARG
-    # in place with a dtype change
-    assert L.mds_prepare_y(_p(), 0, 10, None, 0, _p(), 1, 10, 10, None, None) == ERR_ARG
+    assert L.mds_prepare_y(_p(), 0, 10, None, 0, _p(), 3, 10, 10, None, None, None) == ERR_UNSUP
+    assert L.mds_prepare_y(_p(), 0, 9, None, 0, _p(), 0, 10, 10, None, None, None) == ERR_ARG
+    assert L.mds_prepare_y(_p(), 0, 10, _p(), 5, _p(), 0, 10, 10, None, None, None) == ERR_ARG
+    # in place with a dtype change, and in place with a relabelling
+    assert L.mds_prepare_y(_p(), 0, 10, None, 0, _p(), 1, 10, 10, None, None, None) == ERR_ARG
+    assert L.mds_prepare_y(_p(), 0, 10, None, 0, _p(), 0, 10, 10, _p(), None, None) == ERR_ARG
+    # misaligned permutation
+    assert L.mds_prepare_y(_p(), 0, 10, None, 0, _p(FAKE + 4096), 0, 10, 10,
+                           _p(FAKE + 3), None, None) == ERR_ARG
     assert L.mds_log_phi(None, None, None, 5, 0, None) == ERR_ARG
     assert L.mds_log_phi(_p(), None, None, -1, 0, None) == ERR_ARG
     assert L.mds_log_phi(_p(), None, None, 5, 4, None) == ERR_UNSUP
+
+
+def test_order_and_permute_reject():
+    L = api.lib()
+    nb = ctypes.c_size_t()
+    assert L.mds_order_workspace_bytes(-1, ctypes.byref(nb)) == ERR_ARG
+    assert L.mds_order_workspace_bytes(1000, None) == ERR_ARG
+    assert L.mds_order_workspace_bytes(1000, ctypes.byref(nb)) == 0
+    assert nb.value >= 4 * 4 * 1000 and nb.value % 256 == 0
+    assert L.mds_order_workspace_bytes(0, ctypes.byref(nb)) == 0
+    ws = _p(FAKE + 65536)
+    assert L.mds_spatial_order(100, 0, _p(), 2, _p(), ws, 1 << 20, None) == ERR_UNSUP
+    assert L.mds_spatial_order(100, 9, _p(), 9, _p(), ws, 1 << 20, None) == ERR_UNSUP
+    assert L.mds_spatial_order(100, 2, _p(), 1, _p(), ws, 1 << 20, None) == ERR_ARG
+    assert L.mds_spatial_order(100, 2, None, 2, _p(), ws, 1 << 20, None) == ERR_ARG
+    assert L.mds_spatial_order(100, 2, _p(), 2, _p(), _p(FAKE + 8), 1 << 20, None) == ERR_ARG
+    assert L.mds_spatial_order(100, 2, _p(), 2, _p(), ws, 16, None) == ERR_WS
+    assert L.mds_permute_rows(10, 2, _p(), 2, _p(), 2, _p(), 0, None) == ERR_ARG  # src == dst
+    assert L.mds_permute_rows(10, 2, _p(), 1, _p(FAKE + 4096), 2, _p(), 0, None) == ERR_ARG
+    assert L.mds_permute_rows(10, 2, _p(), 2, _p(FAKE + 4096), 2, None, 0, None) == ERR_ARG
+    assert L.mds_permute_rows(10, 9, _p(), 9, _p(FAKE + 4096), 9, _p(), 0, None) == ERR_UNSUP
+    assert L.mds_permute_rows(-1, 2, _p(), 2, _p(FAKE + 4096), 2, _p(), 0, None) == ERR_ARG
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
