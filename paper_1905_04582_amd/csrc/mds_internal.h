@@ -67,7 +67,8 @@ inline Tiling make_tiling(int64_t n, int br, int waves)
 // Workspace layout (each section aligned to 256 bytes).
 struct WorkspaceLayout {
     size_t rowpart;  // ntiles * br * D doubles: row-side gradient partials
-    size_t colpart;  // ntiles * cw * D doubles: column-side gradient partials
+    size_t colpart;  // ncb * nrb * cw * D doubles: column-side gradient partials,
+                     // slot (column block, row block); slots without a tile unused
     size_t tscal;    // ntiles * 2 doubles: per-tile sum r_ij and sum of dsigma terms
     size_t tcount;   // ntiles uint32: per-tile observed-pair count
     size_t total;
@@ -82,7 +83,10 @@ inline WorkspaceLayout workspace_layout(const Tiling& t, int d)
     w.rowpart = off;
     off = align_up(off + (size_t)t.ntiles * t.br * d * sizeof(double), 256);
     w.colpart = off;
-    off = align_up(off + (size_t)t.ntiles * t.cw * d * sizeof(double), 256);
+    // column blocks that hold a tile: those of the last row block (with
+    // br > cw this includes blocks past column n-1, whose tiles still write)
+    const size_t ncb = t.nrb > 0 ? (size_t)tiles_in_row_block(t.nrb - 1, t.br, t.cw) : 0;
+    off = align_up(off + ncb * (size_t)t.nrb * t.cw * d * sizeof(double), 256);
     w.tscal = off;
     off = align_up(off + (size_t)t.ntiles * 2 * sizeof(double), 256);
     w.tcount = off;

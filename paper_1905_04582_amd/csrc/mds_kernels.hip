@@ -72,41 +72,69 @@ __device__ void block_sum3(double& a, double& b, double& c)
 // of kFinChunks adds list items w, w + kFinChunks, ... (64 consecutive
 // elements per wave: coalesced reads), and wave 0 adds the kFinChunks chunk
 // sums in chunk order.  Every order is fixed, so the result is reproducible.
-constexpr int kFinChunks = 8;
-constexpr int kFinUnroll = 8;  // partial loads in flight per lane
+#ifndef MDS_FIN_CHUNKS
+#define MDS_FIN_CHUNKS 8
+#endif
+#ifndef MDS_FIN_UNROLL
+#define MDS_FIN_UNROLL 8
+#endif
+constexpr int kFinChunks = MDS_FIN_CHUNKS;
+constexpr int kFinUnroll = MDS_FIN_UNROLL;  // partial loads in flight per lane
 
 // The scalar part: L, dL/dsigma and dL/d(ln sigma) from the per-tile sums,
-// by the first kFinBlock threads of a work-group, in a fixed tree order.
+// by one work-group of kWave * kFinChunks threads in a fixed order: thread t
+// adds tiles t, t + T, ... (kFinUnroll loads in flight), each wave combines
+// its lanes by a butterfly, and thread 0 adds the waves in order.
 __device__ void finalize_scalars(const FinalizeArgs& a, double scale)
 {
-    __shared__ double s[3][kFinBlock];
-    const int t = threadIdx.x;
+    constexpr int T = kWave * kFinChunks;
+    __shared__ double s[3][kFinChunks];
+    const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
     double sr = 0.0, ss = 0.0, sm = 0.0;
-    if (t < kFinBlock)
-        for (int64_t u = t; u < a.ntiles; u += kFinBlock) {
-            sr += a.tscal[2 * u + 0];
-            ss += a.tscal[2 * u + 1];
-            sm += (double)a.tcount[u];
+    int64_t u = t;
+    for (; u + (kFinUnroll - 1) * T < a.ntiles; u += kFinUnroll * T) {
+        double r[kFinUnroll], q[kFinUnroll], c[kFinUnroll];
+#pragma unroll
+        for (int k = 0; k < kFinUnroll; ++k) {
+            r[k] = a.tscal[2 * (u + k * T) + 0];
+            q[k] = a.tscal[2 * (u + k * T) + 1];
+            c[k] = (double)a.tcount[u + k * T];
         }
-    if (t < kFinBlock) {
-        s[0][t] = sr;
-        s[1][t] = ss;
-        s[2][t] = sm;
+#pragma unroll
+        for (int k = 0; k < kFinUnroll; ++k) {
+            sr += r[k];
+            ss += q[k];
+            sm += c[k];
+        }
+    }
+    for (; u < a.ntiles; u += T) {
+        sr += a.tscal[2 * u + 0];
+        ss += a.tscal[2 * u + 1];
+        sm += (double)a.tcount[u];
+    }
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) {
+        sr += __shfl_xor(sr, m, kWave);
+        ss += __shfl_xor(ss, m, kWave);
+        sm += __shfl_xor(sm, m, kWave);
+    }
+    if (lane == 0) {
+        s[0][w] = sr;
+        s[1][w] = ss;
+        s[2][w] = sm;
     }
     __syncthreads();
-    for (int h = kFinBlock / 2; h > 0; h >>= 1) {
-        if (t < h) {
-            s[0][t] += s[0][t + h];
-            s[1][t] += s[1][t + h];
-            s[2][t] += s[2][t + h];
-        }
-        __syncthreads();
-    }
     if (t == 0) {
+        double r0 = 0.0, q0 = 0.0, m = 0.0;
+        for (int k = 0; k < kFinChunks; ++k) {
+            r0 += s[0][k];
+            q0 += s[1][k];
+            m += s[2][k];
+        }
+        // m is an exact integer below 2^53
         const double sigma = *a.sigma;
-        const double m = s[2][0];  // an exact integer below 2^53
-        const double L = (m > 0.0) ? -m * log(sigma) - s[0][0] : 0.0;
-        const double ds = (m > 0.0) ? (-m / sigma + s[1][0]) * scale : 0.0;
+        const double L = (m > 0.0) ? -m * log(sigma) - r0 : 0.0;
+        const double ds = (m > 0.0) ? (-m / sigma + q0) * scale : 0.0;
         if (a.loglik) *a.loglik = L;
         if (a.dsigma) *a.dsigma = ds;
         if (a.dlogsigma) *a.dlogsigma = ds * sigma;
@@ -138,22 +166,33 @@ __device__ void finalize_elements(const FinalizeArgs& a, int D, int64_t blk, dou
         const int rb0 = first_row_block_of_column(c, br, cw);
         const int64_t total = nrow + (a.nrb - rb0);
         // items chunk, chunk + kFinChunks, ... of the list (row-side
-        // partials, then column-side ones), added in list order; the loads
-        // of kFinUnroll items are issued before their adds
-        auto item = [&](int64_t it) -> double {
-            if (it < nrow) return a.rowpart[((t0 + it) * br + roff) * D + d];
-            const int rb = rb0 + (int)(it - nrow);
-            return a.colpart[((tiles_before(rb, br, cw) + c) * cw + coff) * D + d];
+        // partials of row block r, then column-side partials of column
+        // block c from row block rb0 on), added in list order; kFinUnroll
+        // loads are issued before their adds
+        // Items i0, i0 + kFinChunks, ... < cnt of a strided list, added in
+        // order.  Loads are unconditional (index clamped into the list, an
+        // item past the end replaced by 0), so each batch of kFinUnroll
+        // loads is in flight together.
+        auto add_list = [&](const double* base, int64_t step, int64_t i0, int64_t cnt) {
+            for (; i0 < cnt; i0 += kFinUnroll * kFinChunks) {
+                double v[kFinUnroll];
+#pragma unroll
+                for (int u = 0; u < kFinUnroll; ++u) {
+                    const int64_t q = i0 + u * kFinChunks;
+                    v[u] = base[min(q, cnt - 1) * step];
+                }
+#pragma unroll
+                for (int u = 0; u < kFinUnroll; ++u)
+                    s += (i0 + u * kFinChunks < cnt) ? v[u] : 0.0;
+            }
         };
-        int64_t it = chunk;
-        for (; it + (kFinUnroll - 1) * kFinChunks < total; it += kFinUnroll * kFinChunks) {
-            double v[kFinUnroll];
-#pragma unroll
-            for (int u = 0; u < kFinUnroll; ++u) v[u] = item(it + u * kFinChunks);
-#pragma unroll
-            for (int u = 0; u < kFinUnroll; ++u) s += v[u];
-        }
-        for (; it < total; it += kFinChunks) s += item(it);
+        add_list(a.rowpart + ((t0 * br + roff) * D + d), (int64_t)br * D, chunk, nrow);
+        // the column items continue the list: the first one of this chunk is
+        // the first list index >= nrow congruent to chunk
+        const int64_t jt = (chunk >= nrow) ? chunk - nrow
+                                           : (kFinChunks - (nrow - chunk) % kFinChunks) % kFinChunks;
+        add_list(a.colpart + ((((int64_t)c * a.nrb + rb0) * cw + coff) * D + d), (int64_t)cw * D,
+                 jt, total - nrow);
     }
     part[chunk][lane] = s;
     __syncthreads();

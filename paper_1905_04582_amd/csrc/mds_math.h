@@ -78,6 +78,25 @@ __device__ __forceinline__ double horner_tab(const double (&tab)[N], double x)
 #endif
 }
 
+// Horner's rule for two arguments at once: each coefficient is loaded once
+// and feeds both chains (two independent dependency chains interleave).
+template <int N>
+__device__ __forceinline__ void horner2_tab(const double (&tab)[N], double x1, double x2,
+                                            double& r1, double& r2)
+{
+    const_f64_ptr c = (const_f64_ptr)tab;
+    asm volatile("" : "+s"(c));
+    double a1 = fma_sc(c[N - 1], x1, c[N - 2]);
+    double a2 = fma_sc(c[N - 1], x2, c[N - 2]);
+#pragma unroll
+    for (int k = N - 3; k >= 0; --k) {
+        a1 = fma_sc(a1, x1, c[k]);
+        a2 = fma_sc(a2, x2, c[k]);
+    }
+    r1 = a1;
+    r2 = a2;
+}
+
 // ---------------------------------------------------------------- FP64 --
 
 // 1/d for finite d > 0 (not subnormal): hardware estimate + 2 Newton steps
@@ -125,6 +144,37 @@ __device__ __forceinline__ void trunc_terms_f64(double t, double& lnphi, double&
     const double s = a * d2 * rr;         // q / (2 - q)
     lnphi = -2.0 * s * horner_tab(kAtanhA64, s * s);
     mills = (4.0 * kInvSqrt2Pi) * (e * Q) * (d1 * rr);
+}
+
+// trunc_terms_f64 for two arguments, sharing every coefficient load
+__device__ __forceinline__ void trunc_terms2_f64(double t1, double t2, double& lnphi1,
+                                                 double& mills1, double& lnphi2, double& mills2)
+{
+    const double x1 = fmax(-0.5 * (t1 * t1), -760.0);
+    const double x2 = fmax(-0.5 * (t2 * t2), -760.0);
+    const double k1 = rint(x1 * kLog2e), k2 = rint(x2 * kLog2e);
+    double r1 = fma(k1, -kLn2Head, x1), r2 = fma(k2, -kLn2Head, x2);
+    r1 = fma(k1, -kLn2Tail, r1);
+    r2 = fma(k2, -kLn2Tail, r2);
+    double p1, p2;
+    horner2_tab(kExpC64, r1, r2, p1, p2);
+    const double e1 = ldexp(p1, (int)k1), e2 = ldexp(p2, (int)k2);
+    const double z1 = fmin(t1 * kInvSqrt2, kErfcxZmax64 + 1.0);
+    const double z2 = fmin(t2 * kInvSqrt2, kErfcxZmax64 + 1.0);
+    double P1, P2, Q1, Q2;
+    horner2_tab(kErfcxP64, z1, z2, P1, P2);
+    horner2_tab(kErfcxQ64, z1, z2, Q1, Q2);
+    const double a1 = e1 * P1, a2 = e2 * P2;
+    const double d11 = fma(4.0, Q1, -a1), d12 = fma(4.0, Q2, -a2);
+    const double d21 = d11 - a1, d22 = d12 - a2;
+    const double rr1 = rcp_f64(d11 * d21), rr2 = rcp_f64(d12 * d22);
+    const double s1 = a1 * d21 * rr1, s2 = a2 * d22 * rr2;
+    double A1, A2;
+    horner2_tab(kAtanhA64, s1 * s1, s2 * s2, A1, A2);
+    lnphi1 = -2.0 * s1 * A1;
+    lnphi2 = -2.0 * s2 * A2;
+    mills1 = (4.0 * kInvSqrt2Pi) * (e1 * Q1) * (d11 * rr1);
+    mills2 = (4.0 * kInvSqrt2Pi) * (e2 * Q2) * (d12 * rr2);
 }
 
 // ---------------------------------------------------------------- FP32 --

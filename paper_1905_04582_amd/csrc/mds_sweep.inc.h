@@ -28,6 +28,20 @@
 #include "mds_internal.h"
 #include "mds_math.h"
 
+// build-time variants of the sweep (the defaults are the measured best)
+#ifndef MDS_ROW_UNROLL
+#define MDS_ROW_UNROLL 2
+#endif
+#ifndef MDS_REDUCE_PER_OUTPUT
+#define MDS_REDUCE_PER_OUTPUT 1
+#endif
+#ifndef MDS_PREFETCH_X
+#define MDS_PREFETCH_X 0
+#endif
+#ifndef MDS_SHARED_COEF
+#define MDS_SHARED_COEF 1
+#endif
+
 namespace mds {
 
 template <typename T>
@@ -97,6 +111,25 @@ __device__ __forceinline__ float rsqrt_t<float>(float x)
     return __builtin_amdgcn_rsqf(x);
 }
 
+// both rows of a two-row step
+template <typename T>
+__device__ __forceinline__ void trunc_terms2(T t1, T t2, T& l1, T& m1, T& l2, T& m2)
+{
+    trunc_terms_f32(t1, l1, m1);
+    trunc_terms_f32(t2, l2, m2);
+}
+template <>
+__device__ __forceinline__ void trunc_terms2<double>(double t1, double t2, double& l1,
+                                                     double& m1, double& l2, double& m2)
+{
+#if MDS_SHARED_COEF
+    trunc_terms2_f64(t1, t2, l1, m1, l2, m2);
+#else
+    trunc_terms_f64(t1, l1, m1);
+    trunc_terms_f64(t2, l2, m2);
+#endif
+}
+
 template <typename T>
 __device__ __forceinline__ void trunc_terms(T t, T& lnphi, T& mills);
 template <>
@@ -141,16 +174,6 @@ __device__ __forceinline__ float skip_t<float>()
 // One tile of one problem, processed by the whole work-group; `lds` is the
 // work-group's dynamic LDS (sweep_lds_bytes).  Ends with a barrier, so the
 // caller may reuse the LDS for the next tile straight away.
-#ifndef MDS_ROW_UNROLL
-#define MDS_ROW_UNROLL 2
-#endif
-#ifndef MDS_REDUCE_PER_OUTPUT
-#define MDS_REDUCE_PER_OUTPUT 1
-#endif
-#ifndef MDS_PREFETCH_X
-#define MDS_PREFETCH_X 0
-#endif
-
 // lanes per output in the row reduction: the largest power of two g with
 // outputs * g <= 64
 __host__ __device__ constexpr int reduce_group(int outputs)
@@ -305,10 +328,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             geom(q, ya, ga);
             geom(q + 1, yb, gb);
             T la = T(0), ma = T(0), lb = T(0), mb = T(0);
-            if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb))) {
-                trunc_terms<T>(ga.t, la, ma);
-                trunc_terms<T>(gb.t, lb, mb);
-            }
+            if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb)))
+                trunc_terms2<T>(ga.t, gb.t, la, ma, lb, mb);
             accum(q, ga, la, ma);
             accum(q + 1, gb, lb, mb);
         }
@@ -389,7 +410,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     }
 
     if (GRAD) {
-        double* cp = a.colpart + ((size_t)tile * cw + (size_t)w * kWave + lane) * D;
+        double* cp =
+            a.colpart + (((size_t)c * a.nrb + r) * cw + (size_t)w * kWave + lane) * D;
 #pragma unroll
         for (int d = 0; d < D; ++d) cp[d] = gj[d];
     }
