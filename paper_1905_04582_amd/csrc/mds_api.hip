@@ -60,21 +60,13 @@ constexpr size_t kMaxSweepLds = 64 * 1024;
 // Tile shape used when the caller passes 0.  Many small work-groups keep
 // every SIMD supplied with waves and let the dispatcher balance tiles of
 // uneven cost (tiles whose wavefronts skip the truncation terms are cheap):
-// FP64 uses 32 rows x 256 columns, FP32 64 x 128 (measured at N = 5392 on
-// spatially ordered locations); small problems use 32 x 128.
+// 32 rows x 128 columns in FP64 and 32 x 256 in FP32 (measured at N = 5392
+// on spatially ordered locations).
 void default_tiling(int64_t n, int d, int dtype, int* br, int* waves)
 {
     (void)d;
-    if (n <= 2048) {
-        *br = 32;
-        *waves = 2;
-    } else if (dtype == MDS_F64) {
-        *br = 32;
-        *waves = 4;
-    } else {
-        *br = 64;
-        *waves = 2;
-    }
+    *br = 32;
+    *waves = (dtype == MDS_F64 || n <= 2048) ? 2 : 4;
 }
 
 int resolve_tiling(int64_t n, int d, int dtype, int tile_rows, int tile_waves, Tiling* out)

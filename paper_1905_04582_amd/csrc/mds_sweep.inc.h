@@ -283,25 +283,27 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 g.dl[d] = (T)(xi[d] - xj[d]);
                 s2 = fma(g.dl[d], g.dl[d], s2);
             }
-            // delta and 1/delta from one reciprocal square root; a coincident
-            // pair (s2 below the normal range) has delta = 0 and no direction
-            const bool pos = s2 >= min_normal<T>();
-            const T sg = pos ? s2 : T(1);
-            const T rs = rsqrt_t(sg);
-            g.delta = pos ? sg * rs : T(0);
-            g.rinv = pos ? rs : T(0);
+            // delta and 1/delta from one reciprocal square root.  A coincident
+            // pair (s2 below the normal range) has no direction: 1/delta is
+            // taken as 0, and delta = s2 * rsqrt(DBL_MIN) is 0 for s2 = 0
+            // (below 1.5e-154 otherwise)
+            const T rs = rsqrt_t(fmax(s2, min_normal<T>()));
+            g.delta = s2 * rs;
+            g.rinv = (s2 >= min_normal<T>()) ? rs : T(0);
             g.t = g.delta * pc.inv_sigma;
-            g.res = yv - g.delta;
+            // a pair outside the sums gets y = delta: its residual is 0, and
+            // with ln Phi = m = 0 (set by the caller) all its terms vanish
+            g.res = g.ok ? yv - g.delta : T(0);
         };
-        // the pair's terms given ln Phi(t) and phi(t)/Phi(t)
+        // the pair's terms given ln Phi(t) and phi(t)/Phi(t) (both 0 for a
+        // pair outside the sums)
         auto accum = [&](const int q, const PairGeom<T, D>& g, const T lnphi, const T mills) {
             const T res2 = g.res * g.res;
-            br_r += g.ok ? fma(res2, pc.half_inv_s2, lnphi) : T(0);
-            cnt += g.ok ? 1 : 0;
+            br_r += fma(res2, pc.half_inv_s2, lnphi);
             if (GRAD) {
                 // w = (delta - y)/sigma^2 + m/sigma; the pair's term is w (x_i - x_j)/delta
                 const T wv = fma(mills, pc.inv_sigma, -g.res * pc.inv_s2);
-                const T coef = g.ok ? wv * g.rinv : T(0);
+                const T coef = wv * g.rinv;
                 T* st = stage + (size_t)q * SROW + (size_t)lane * D;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
@@ -309,8 +311,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                     st[d] = -cd;
                     gjb[d] += cd;
                 }
-                br_s += g.ok ? fma(res2, pc.inv_s3, g.delta * pc.inv_s2 * mills) : T(0);
+                br_s += fma(res2, pc.inv_s3, g.delta * pc.inv_s2 * mills);
             }
+        };
+        // observed pairs of a row in this wave (a wave-uniform count)
+        auto count_ok = [&](const PairGeom<T, D>& g) {
+            cnt += (int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(g.ok));
         };
         // when no observed pair of the row(s) in this wave has t below the
         // skip point, the wave takes ln Phi = m = 0 and skips the special
@@ -327,9 +333,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             PairGeom<T, D> ga, gb;
             geom(q, ya, ga);
             geom(q + 1, yb, gb);
+            count_ok(ga);
+            count_ok(gb);
             T la = T(0), ma = T(0), lb = T(0), mb = T(0);
-            if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb)))
+            if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb))) {
                 trunc_terms2<T>(ga.t, gb.t, la, ma, lb, mb);
+                la = ga.ok ? la : T(0);
+                ma = ga.ok ? ma : T(0);
+                lb = gb.ok ? lb : T(0);
+                mb = gb.ok ? mb : T(0);
+            }
             accum(q, ga, la, ma);
             accum(q + 1, gb, lb, mb);
         }
@@ -339,8 +352,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             ypf1 = load_y(ib + q + 2);
             PairGeom<T, D> ga;
             geom(q, ya, ga);
+            count_ok(ga);
             T la = T(0), ma = T(0);
-            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) trunc_terms<T>(ga.t, la, ma);
+            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) {
+                trunc_terms<T>(ga.t, la, ma);
+                la = ga.ok ? la : T(0);
+                ma = ga.ok ? ma : T(0);
+            }
             accum(q, ga, la, ma);
         }
 #else
@@ -351,8 +369,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             ypf1 = load_y(ib + q + 2);
             PairGeom<T, D> ga;
             geom(q, ya, ga);
+            count_ok(ga);
             T la = T(0), ma = T(0);
-            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) trunc_terms<T>(ga.t, la, ma);
+            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) {
+                trunc_terms<T>(ga.t, la, ma);
+                la = ga.ok ? la : T(0);
+                ma = ga.ok ? ma : T(0);
+            }
             accum(q, ga, la, ma);
         }
 #endif
@@ -417,7 +440,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     }
     acc_r = wave_sum(acc_r);
     acc_s = wave_sum(acc_s);
-    cnt = wave_sum(cnt);
+    // cnt is already the wave's total (a popcount of each row's ballot)
     if (lane == 0) {
         lscal[w * 4 + 0] = acc_r;
         lscal[w * 4 + 1] = acc_s;
