@@ -14,9 +14,9 @@ lets most wavefronts skip the truncation terms; the outputs are the same up
 to rounding, with the gradient rows in the new labelling.  Besides the FP64
 figure (the headline `value`) the line carries the FP32 form on the same
 data, both forms in the original labelling, one 20-step leapfrog trajectory,
-the sweep kernel's roofline (its launches bracketed by HIP events inside the
-timed region) and the serial CPU oracle timed on a bounded sample on this
-host.
+the sweep kernel's roofline (each launch timed inside the timed region by
+HIP events attached to the kernel's own start and end) and the serial CPU
+oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -34,8 +34,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_TOPS = 39.3216       # 256 CU x 64 FP64 lanes/clk x 2.4 GHz (lane-ops, FMA = 1)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
-KERNEL_SOURCES = ["mds_sweep.inc.h", "mds_math.h", "mds_internal.h", "mds_sweep_f64.hip",
-                  "mds_sweep_f32.hip"]
+# sources of the sweep kernel: counter figures in profiles/sweep_traffic.json
+# are used only while they and the tiling match
+KERNEL_SOURCES = ["mds_sweep.inc.h", "mds_math.h", "mds_coeffs.h", "mds_internal.h",
+                  "mds_sweep_f64.hip", "mds_sweep_f32.hip"]
 
 
 def kernel_source_hash() -> str:
@@ -176,6 +178,9 @@ def main():
         forms["fp64-plain"] = (api.MDSProblem(prob.y, d, prob.mask, torch.float64, dev), x)
         forms["fp32-plain"] = (api.MDSProblem(prob.y, d, prob.mask, torch.float32, dev), x)
     m_obs = int(P64.m_obs.item())
+    # the tiles the default launch uses, per form
+    tiles = {f: list(api.mds_resolve_tiling(n, d, c)) for f, c in
+             (("fp64", api.MDS_F64), ("fp32", api.MDS_F32))}
 
     if args.only:
         P, xx = forms[args.only]
@@ -215,12 +220,18 @@ def main():
     gbs64 = y_bytes64 / (sweep64 * 1e-3) / 1e9
     gbs32 = y_bytes32 / (sweep32 * 1e-3) / 1e9
 
-    traffic = None
+    # HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated against a
+    # plain copy) and the VALU-busy fraction, from the committed counter runs
+    # of this same kernel source; null once the kernel has changed
+    counters = {}
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        if t.get("kernel_source_sha") == kernel_source_hash() and t.get("n") == n:
-            traffic = t.get("fp64_bytes_per_launch")
+        if (t.get("kernel_source_sha") == kernel_source_hash() and t.get("n") == n
+                and t.get("tiles") == tiles):
+            counters = t
+    c64, c32 = counters.get("fp64", {}), counters.get("fp32", {})
+    traffic = c64.get("traffic_bytes_per_launch")
 
     plain = {}
     for k in ("fp64-plain", "fp32-plain"):
@@ -245,13 +256,15 @@ def main():
                                "loglik+gradient+dL/dsigma evaluation per step; locations "
                                "relabelled once in Hilbert order at set-up",
                    "n": n, "d": d, "sigma": sigma, "pairs": npairs, "observed_pairs": m_obs,
-                   "tile_rows_x_cols": "default", "seed": prob.seed,
+                   "tiles_rows_x_64cols": tiles, "seed": prob.seed,
                    "setup_ms_order_and_prepare": round(setup_ms, 3)},
         "roofline": {
             "bound": "hbm", "kernel": "sweep_kernel<double,2,true>",
             "achieved": round(gbs64, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs64 / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": y_bytes64,
+            "valu_busy_frac": c64.get("valu_busy_frac"),
+            "counters": "profiles/sweep_traffic.json" if counters else None,
             "sweep_ms_mean": round(sweep64, 5), "sweep_ms_median": round(sweep64_med, 5),
             "sweep_ms_cold_median": round(cold64, 5),
         },
@@ -260,6 +273,8 @@ def main():
             "speedup_vs_fp64": round(wall64 / wall32, 3), "sweep_ms_mean": round(sweep32, 5),
             "sweep_ms_cold_median": round(cold32, 5),
             "y_stream_gbs": round(gbs32, 2), "y_stream_frac": round(gbs32 / HBM_PEAK_GBS, 4),
+            "traffic": c32.get("traffic_bytes_per_launch"),
+            "valu_busy_frac": c32.get("valu_busy_frac"),
             "loglik_rel_diff_vs_fp64": abs(L32.item() - L64.item()) / abs(L64.item()),
         },
         "original_labelling": plain,

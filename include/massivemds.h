@@ -102,6 +102,16 @@ int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows
                         int32_t tile_waves, size_t* bytes);
 
 /*
+ * The tiling the sweeps use for these arguments: tile_rows / tile_waves as
+ * passed to mds_loglik and friends (0 = the library's default for n, d and
+ * y_dtype), resolved and validated.  Writes *rows_out (rows per tile) and
+ * *waves_out (64-column groups per tile); returns a status (an unsupported
+ * tiling is MDS_ERR_UNSUPPORTED, as in the evaluation calls).
+ */
+int mds_resolve_tiling(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
+                       int32_t tile_waves, int32_t* rows_out, int32_t* waves_out);
+
+/*
  * Prepare Y for the sweeps (not part of the per-evaluation path).
  *   y_src       N x N, dtype src_dtype, leading dimension ld_src (elements)
  *   missing     optional N x N bytes, leading dimension ld_mask; non-zero
@@ -284,12 +294,13 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
 int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t stream);
 
 /*
- * Diagnostics for benchmarks: while set (non-NULL), every pair-sweep kernel
- * launched by this thread is bracketed by hipEventRecord(before, stream) and
- * hipEventRecord(after, stream), so a caller can time the sweep kernel alone
- * inside a larger sequence.  The events are the caller's (created with
- * timing enabled) and are recorded again by every later sweep launch; pass
- * NULL, NULL to stop.  Thread-local; no effect on results.
+ * Diagnostics for benchmarks: while set (non-NULL), every single-problem
+ * pair-sweep kernel launched by this thread records its own start in
+ * `before` and its end in `after` (hipExtLaunchKernel), so a caller can time
+ * the sweep kernel alone inside a larger sequence.  The events are the
+ * caller's (created with timing enabled) and are recorded again by every
+ * later sweep launch; pass NULL, NULL to stop.  Thread-local; no effect on
+ * results.
  */
 int mds_set_sweep_events(hipEvent_t before, hipEvent_t after);
 

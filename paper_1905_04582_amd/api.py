@@ -73,6 +73,9 @@ def lib():
     L.mds_prepare_y.restype = ctypes.c_int
     L.mds_prepare_y.argtypes = [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _c_i32, _c_i64, _c_i64,
                                 _vp, _vp, _vp]
+    L.mds_resolve_tiling.restype = ctypes.c_int
+    L.mds_resolve_tiling.argtypes = [_c_i64, _c_i32, _c_i32, _c_i32, _c_i32,
+                                     ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]
     L.mds_order_workspace_bytes.restype = ctypes.c_int
     L.mds_order_workspace_bytes.argtypes = [_c_i64, ctypes.POINTER(ctypes.c_size_t)]
     L.mds_spatial_order.restype = ctypes.c_int
@@ -164,6 +167,15 @@ def mds_workspace_bytes(n: int, d: int, y_dtype: int, tile_rows: int = 0,
     _check(lib().mds_workspace_bytes(n, d, y_dtype, tile_rows, tile_waves, ctypes.byref(out)),
            "mds_workspace_bytes")
     return int(out.value)
+
+
+def mds_resolve_tiling(n: int, d: int, y_dtype: int, tile_rows: int = 0,
+                       tile_waves: int = 0):
+    """(rows per tile, 64-column groups per tile) the sweeps use."""
+    r, w = _c_i32(), _c_i32()
+    _check(lib().mds_resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, ctypes.byref(r),
+                                    ctypes.byref(w)), "mds_resolve_tiling")
+    return r.value, w.value
 
 
 def alloc_workspace(nbytes: int, device) -> torch.Tensor:

@@ -5,8 +5,11 @@ For a (Y dtype, D, N bucket) it times every feasible tiling -- rows per tile
 other, within the LDS budget -- on a problem of that size and keeps the
 fastest in a JSON cache keyed by GPU architecture, dtype, D and bucket.
 
-The sweep is branch-free, so its cost does not depend on the values in X and
-Y: the tuning problem is random data generated on the device.
+The tuning problem is generated on the device: locations X ~ N(0, 9 I) in
+spatial order (as ``MDSProblem(order=...)`` stores a problem) and a random
+symmetric Y, evaluated at sigma = 0.5.  The sweep's cost depends on the data
+only through the wavefronts that skip the truncation terms, i.e. on how far
+apart the locations are relative to sigma.
 
     python -m paper_1905_04582_amd.autotune --dtype f64 --d 2 --n 5392
     python -m paper_1905_04582_amd.autotune --grid           # the standard grid
@@ -36,8 +39,12 @@ def cache_path() -> str:
 
 
 def bucket(n: int) -> int:
-    """N bucket: the power of two at or above n (minimum 512)."""
-    return max(512, 1 << max(0, int(math.ceil(math.log2(max(n, 1))))))
+    """N bucket: the smallest 2^k or 3 * 2^(k-1) at or above n (minimum 512),
+    i.e. half-octave buckets: ..., 4096, 6144, 8192, 12288, ..."""
+    b = 512
+    while b < n:
+        b = b * 3 // 2 if (b & (b - 1)) == 0 else b * 4 // 3
+    return b
 
 
 def _arch(device=None) -> str:
@@ -88,10 +95,12 @@ def candidates(n: int, d: int, dtype):
     return out
 
 
-def _random_problem(n, d, dtype, device, seed=0):
+def _random_problem(n, d, dtype, device, seed=0, ordered=True):
     g = torch.Generator(device=device)
     g.manual_seed(seed)
     x = torch.randn((n, d), generator=g, dtype=torch.float64, device=device) * 3.0
+    if ordered:
+        x = api.mds_permute_rows(x, api.mds_spatial_order(x))
     y = (torch.randn((n, n), generator=g, dtype=torch.float64, device=device).abs() * 3.0)
     y = torch.tril(y, -1)
     y = (y + y.T).contiguous()

@@ -57,16 +57,25 @@ size_t dtype_size(int dt) { return dt == MDS_F64 ? 8 : 4; }
 // Largest LDS a sweep work-group may use (row sums of all its waves).
 constexpr size_t kMaxSweepLds = 64 * 1024;
 
-// Tile shape used when the caller passes 0.  Many small work-groups keep
+// Tile shape used when the caller passes 0 (the tuner's choices for D = 2 on
+// spatially ordered locations).  Up to N ~ 6000 many small work-groups keep
 // every SIMD supplied with waves and let the dispatcher balance tiles of
-// uneven cost (tiles whose wavefronts skip the truncation terms are cheap):
-// 32 rows x 128 columns in FP64 and 32 x 256 in FP32 (measured at N = 5392
-// on spatially ordered locations).
+// uneven cost (tiles whose wavefronts skip the truncation terms are cheap);
+// larger problems run long enough for 64 x 256 tiles, which write fewer
+// partial sums.
 void default_tiling(int64_t n, int d, int dtype, int* br, int* waves)
 {
     (void)d;
-    *br = 32;
-    *waves = (dtype == MDS_F64 || n <= 2048) ? 2 : 4;
+    if (n <= 2048) {
+        *br = 32;
+        *waves = 1;
+    } else if (n <= 6144) {
+        *br = 32;
+        *waves = (dtype == MDS_F64) ? 2 : 4;
+    } else {
+        *br = 64;
+        *waves = 4;
+    }
 }
 
 int resolve_tiling(int64_t n, int d, int dtype, int tile_rows, int tile_waves, Tiling* out)
@@ -134,12 +143,7 @@ int check_workspace(const Tiling& t, int d, const void* ws, size_t ws_bytes,
 hipError_t timed_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
                        hipStream_t s)
 {
-    hipError_t e;
-    if (g_ev_before && (e = hipEventRecord(g_ev_before, s)) != hipSuccess) return e;
-    e = launch_sweep(y_dtype, d, grad, t, a, s);
-    if (e != hipSuccess) return e;
-    if (g_ev_after && (e = hipEventRecord(g_ev_after, s)) != hipSuccess) return e;
-    return hipSuccess;
+    return launch_sweep(y_dtype, d, grad, t, a, s, g_ev_before, g_ev_after);
 }
 
 SweepArgs sweep_args(const Tiling& t, const WorkspaceLayout& lay, void* ws, int64_t n,
@@ -212,6 +216,23 @@ int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows
     int st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t);
     if (st) return st;
     *bytes = workspace_layout(t, d).total;
+    return MDS_OK;
+}
+
+int mds_resolve_tiling(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
+                       int32_t tile_waves, int32_t* rows_out, int32_t* waves_out)
+{
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if (d < 1 || d > MDS_MAX_DIM)
+        return fail(MDS_ERR_UNSUPPORTED, "d=%d: must be 1..%d", d, MDS_MAX_DIM);
+    if (y_dtype != MDS_F64 && y_dtype != MDS_F32)
+        return fail(MDS_ERR_UNSUPPORTED, "y_dtype must be MDS_F64 or MDS_F32");
+    if (!rows_out || !waves_out) return fail(MDS_ERR_INVALID_ARGUMENT, "output pointer NULL");
+    Tiling t;
+    const int st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t);
+    if (st) return st;
+    *rows_out = t.br;
+    *waves_out = t.waves;
     return MDS_OK;
 }
 

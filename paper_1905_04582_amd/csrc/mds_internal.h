@@ -181,8 +181,10 @@ struct BatchProblem {
 };
 
 // launchers (return hipError_t of the launch)
+// start/stop (optional): events that record the sweep kernel's own start and
+// end (hipExtLaunchKernel), for timing it alone
 hipError_t launch_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_batch_sweep(int y_dtype, bool grad, int maxd, const BatchProblem* probs,
                               int32_t count, int64_t total_tiles, unsigned long long* cursor,

@@ -7,8 +7,10 @@
 
 namespace mds {
 
-hipError_t launch_sweep_f64(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s);
-hipError_t launch_sweep_f32(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_f64(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s,
+                            hipEvent_t start, hipEvent_t stop);
+hipError_t launch_sweep_f32(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s,
+                            hipEvent_t start, hipEvent_t stop);
 
 hipError_t launch_batch_sweep_f64(bool grad, int maxd, const BatchProblem* probs, int32_t count,
                                  int64_t total_tiles, unsigned long long* cursor, int waves,
@@ -20,9 +22,10 @@ int batch_sweep_blocks_per_cu_f64(bool grad, int maxd, int waves, size_t lds);
 int batch_sweep_blocks_per_cu_f32(bool grad, int maxd, int waves, size_t lds);
 
 hipError_t launch_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
-                        hipStream_t s)
+                        hipStream_t s, hipEvent_t start, hipEvent_t stop)
 {
-    return y_dtype == 0 ? launch_sweep_f64(d, grad, t, a, s) : launch_sweep_f32(d, grad, t, a, s);
+    return y_dtype == 0 ? launch_sweep_f64(d, grad, t, a, s, start, stop)
+                        : launch_sweep_f32(d, grad, t, a, s, start, stop);
 }
 
 hipError_t launch_batch_sweep(int y_dtype, bool grad, int maxd, const BatchProblem* probs,

@@ -25,6 +25,8 @@
 // replaced by this single fused triangle pass.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "mds_internal.h"
 #include "mds_math.h"
 
@@ -583,17 +585,26 @@ int batch_sweep_blocks_per_cu(bool grad, int maxd, int waves, size_t lds)
 }
 
 template <typename T>
-hipError_t launch_sweep_t(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s)
+hipError_t launch_sweep_t(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s,
+                          hipEvent_t start, hipEvent_t stop)
 {
     if (t.ntiles == 0) return hipSuccess;
     const dim3 grid((unsigned)t.ntiles), block((unsigned)(t.waves * kWave));
     const size_t lds = sweep_lds_bytes(t, d);
-#define MDS_SWEEP_CASE(DD)                                                              \
-    case DD:                                                                            \
-        if (grad)                                                                       \
-            hipLaunchKernelGGL((sweep_kernel<T, DD, true>), grid, block, lds, s, a);   \
-        else                                                                            \
-            hipLaunchKernelGGL((sweep_kernel<T, DD, false>), grid, block, lds, s, a);  \
+    const bool timed = start || stop;
+#define MDS_SWEEP_LAUNCH(DD, G)                                                               \
+    if (timed)                                                                                \
+        hipExtLaunchKernelGGL((sweep_kernel<T, DD, G>), grid, block, lds, s, start, stop, 0,  \
+                              a);                                                             \
+    else                                                                                      \
+        hipLaunchKernelGGL((sweep_kernel<T, DD, G>), grid, block, lds, s, a);
+#define MDS_SWEEP_CASE(DD)            \
+    case DD:                          \
+        if (grad) {                   \
+            MDS_SWEEP_LAUNCH(DD, true)  \
+        } else {                      \
+            MDS_SWEEP_LAUNCH(DD, false) \
+        }                             \
         break;
     switch (d) {
         MDS_SWEEP_CASE(1)
@@ -607,6 +618,7 @@ hipError_t launch_sweep_t(int d, bool grad, const Tiling& t, const SweepArgs& a,
         default:
             return hipErrorInvalidValue;
     }
+#undef MDS_SWEEP_LAUNCH
 #undef MDS_SWEEP_CASE
     return hipGetLastError();
 }

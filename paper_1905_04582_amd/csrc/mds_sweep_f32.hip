@@ -3,9 +3,10 @@
 #include "mds_sweep.inc.h"
 
 namespace mds {
-hipError_t launch_sweep_f32(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s)
+hipError_t launch_sweep_f32(int d, bool grad, const Tiling& t, const SweepArgs& a, hipStream_t s,
+                            hipEvent_t start, hipEvent_t stop)
 {
-    return launch_sweep_t<float>(d, grad, t, a, s);
+    return launch_sweep_t<float>(d, grad, t, a, s, start, stop);
 }
 
 hipError_t launch_batch_sweep_f32(bool grad, int maxd, const BatchProblem* probs, int32_t count,

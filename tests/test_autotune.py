@@ -8,8 +8,11 @@ from paper_1905_04582_amd import api, autotune
 
 def test_buckets():
     assert autotune.bucket(1) == 512 and autotune.bucket(512) == 512
-    assert autotune.bucket(513) == 1024 and autotune.bucket(5392) == 8192
-    assert autotune.bucket(20000) == 32768
+    assert autotune.bucket(513) == 768 and autotune.bucket(769) == 1024
+    assert autotune.bucket(5392) == 6144 and autotune.bucket(8000) == 8192
+    assert autotune.bucket(20000) == 24576 and autotune.bucket(24577) == 32768
+    # the standard grid lands in distinct buckets
+    assert len({autotune.bucket(n) for n in autotune.GRID_N}) == len(autotune.GRID_N)
 
 
 def test_candidates_are_valid_tilings():
@@ -35,5 +38,5 @@ def test_cache_round_trip(tmp_path, monkeypatch):
     autotune.save(table)
     assert json.loads(path.read_text())
     assert autotune.lookup(torch.float64, 2, 5000) == (64, 2)      # same bucket
-    assert autotune.lookup(torch.float64, 2, 9000) == (0, 0)       # other bucket
+    assert autotune.lookup(torch.float64, 2, 6500) == (0, 0)       # other bucket
     assert autotune.lookup(torch.float32, 2, 5392) == (0, 0)       # other dtype

@@ -144,6 +144,28 @@ def test_prepare_and_log_phi_reject():
     assert L.mds_log_phi(_p(), None, None, 5, 4, None) == ERR_UNSUP
 
 
+def test_resolve_tiling():
+    L = api.lib()
+    f64, f32 = api.MDS_F64, api.MDS_F32
+    assert api.mds_resolve_tiling(1000, 2, f64) == (32, 1)
+    assert api.mds_resolve_tiling(5392, 2, f64) == (32, 2)
+    assert api.mds_resolve_tiling(5392, 2, f32) == (32, 4)
+    assert api.mds_resolve_tiling(20000, 6, f32) == (64, 4)
+    assert api.mds_resolve_tiling(5392, 2, f64, 128, 2) == (128, 2)
+    r, w = ctypes.c_int32(), ctypes.c_int32()
+    assert L.mds_resolve_tiling(100, 2, 0, 48, 1, ctypes.byref(r), ctypes.byref(w)) == ERR_UNSUP
+    assert L.mds_resolve_tiling(100, 2, 0, 128, 4, ctypes.byref(r), ctypes.byref(w)) == 0
+    assert L.mds_resolve_tiling(100, 9, 0, 0, 0, ctypes.byref(r), ctypes.byref(w)) == ERR_UNSUP
+    assert L.mds_resolve_tiling(100, 2, 2, 0, 0, ctypes.byref(r), ctypes.byref(w)) == ERR_UNSUP
+    assert L.mds_resolve_tiling(-1, 2, 0, 0, 0, ctypes.byref(r), ctypes.byref(w)) == ERR_ARG
+    assert L.mds_resolve_tiling(100, 2, 0, 0, 0, None, ctypes.byref(w)) == ERR_ARG
+    # every tiling the tuner proposes resolves to itself
+    import torch
+    from paper_1905_04582_amd import autotune
+    for br, wv in autotune.candidates(5392, 6, torch.float64):
+        assert api.mds_resolve_tiling(5392, 6, f64, br, wv) == (br, wv)
+
+
 def test_order_and_permute_reject():
     L = api.lib()
     nb = ctypes.c_size_t()
