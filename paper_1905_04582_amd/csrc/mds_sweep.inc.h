@@ -237,8 +237,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     // rows i <= jw0 hold no pair (j < i) for any lane of this wave
     const int64_t istart = max(row0, jw0 + 1);
     const int64_t ib0 = row0 + ((istart - row0) / RB) * RB;
-    // Y is prefetched two rows ahead, so each row's load has two iterations
-    // of arithmetic to arrive.  The load itself is unconditional (row clamped
+    // Y is prefetched one iteration (PF rows) ahead, so each row's load has
+    // an iteration of arithmetic to arrive.  The load itself is unconditional (row clamped
     // into the tile, column into the matrix; lanes outside the triangle
     // discard the value through `ok`), so no branch splits the wave and the
     // wait before a row's first use leaves the two newer loads in flight.
@@ -261,7 +261,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
 #endif
         return r;
     };
-    RowIn ypf0 = load_y(ib0), ypf1 = load_y(ib0 + 1);
+    // rows per iteration (UR) and rows prefetched ahead (PF); a batch of RB
+    // staged rows holds whole iterations
+    constexpr int UR = (MDS_ROW_UNROLL >= 4 && RB % 4 == 0) ? 4 : (MDS_ROW_UNROLL >= 2 ? 2 : 1);
+    constexpr int PF = UR < 2 ? 2 : UR;
+    RowIn pf[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) pf[k] = load_y(ib0 + k);
     for (int64_t ib = ib0; ib < row1; ib += RB) {
         T gjb[D];
 #pragma unroll
@@ -324,63 +330,87 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
         // skip point, the wave takes ln Phi = m = 0 and skips the special
         // functions (a wave-uniform branch; lanes never diverge)
         auto needs_tail = [&](const PairGeom<T, D>& g) { return g.ok && g.t < skip_t<T>(); };
-#if MDS_ROW_UNROLL >= 2
-        // two rows per iteration: independent dependency chains interleave
+        // one row at a time (loop tails)
+        auto one_row = [&](const int q) {
+            const RowIn ya = pf[0];
+#pragma unroll
+            for (int k = 0; k + 1 < PF; ++k) pf[k] = pf[k + 1];
+            pf[PF - 1] = load_y(ib + q + PF);
+            PairGeom<T, D> ga;
+            geom(q, ya, ga);
+            count_ok(ga);
+            T la = T(0), ma = T(0);
+            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) {
+                trunc_terms<T>(ga.t, la, ma);
+                la = ga.ok ? la : T(0);
+                ma = ga.ok ? ma : T(0);
+            }
+            accum(q, ga, la, ma);
+        };
         int q = 0;
+        if constexpr (UR == 4) {
+            // four rows per iteration: two pairs of rows share the special
+            // functions' coefficient loads, four dependency chains interleave
 #pragma unroll 1
-        for (; q + 1 < nq; q += 2) {
-            const RowIn ya = ypf0, yb = ypf1;
-            ypf0 = load_y(ib + q + 2);
-            ypf1 = load_y(ib + q + 3);
-            PairGeom<T, D> ga, gb;
-            geom(q, ya, ga);
-            geom(q + 1, yb, gb);
-            count_ok(ga);
-            count_ok(gb);
-            T la = T(0), ma = T(0), lb = T(0), mb = T(0);
-            if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb))) {
-                trunc_terms2<T>(ga.t, gb.t, la, ma, lb, mb);
-                la = ga.ok ? la : T(0);
-                ma = ga.ok ? ma : T(0);
-                lb = gb.ok ? lb : T(0);
-                mb = gb.ok ? mb : T(0);
+            for (; q + 3 < nq; q += 4) {
+                const RowIn ya = pf[0], yb = pf[1], yc = pf[2], yd = pf[3];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) pf[k] = load_y(ib + q + 4 + k);
+                PairGeom<T, D> ga, gb, gc, gd;
+                geom(q, ya, ga);
+                geom(q + 1, yb, gb);
+                geom(q + 2, yc, gc);
+                geom(q + 3, yd, gd);
+                count_ok(ga);
+                count_ok(gb);
+                count_ok(gc);
+                count_ok(gd);
+                T la = T(0), ma = T(0), lb = T(0), mb = T(0);
+                T lc = T(0), mc = T(0), ld = T(0), md = T(0);
+                if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb) ||
+                                                needs_tail(gc) || needs_tail(gd))) {
+                    trunc_terms2<T>(ga.t, gb.t, la, ma, lb, mb);
+                    trunc_terms2<T>(gc.t, gd.t, lc, mc, ld, md);
+                    la = ga.ok ? la : T(0);
+                    ma = ga.ok ? ma : T(0);
+                    lb = gb.ok ? lb : T(0);
+                    mb = gb.ok ? mb : T(0);
+                    lc = gc.ok ? lc : T(0);
+                    mc = gc.ok ? mc : T(0);
+                    ld = gd.ok ? ld : T(0);
+                    md = gd.ok ? md : T(0);
+                }
+                accum(q, ga, la, ma);
+                accum(q + 1, gb, lb, mb);
+                accum(q + 2, gc, lc, mc);
+                accum(q + 3, gd, ld, md);
             }
-            accum(q, ga, la, ma);
-            accum(q + 1, gb, lb, mb);
-        }
-        if (q < nq) {
-            const RowIn ya = ypf0;
-            ypf0 = ypf1;
-            ypf1 = load_y(ib + q + 2);
-            PairGeom<T, D> ga;
-            geom(q, ya, ga);
-            count_ok(ga);
-            T la = T(0), ma = T(0);
-            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) {
-                trunc_terms<T>(ga.t, la, ma);
-                la = ga.ok ? la : T(0);
-                ma = ga.ok ? ma : T(0);
-            }
-            accum(q, ga, la, ma);
-        }
-#else
+        } else if constexpr (UR == 2) {
+            // two rows per iteration: independent dependency chains interleave
 #pragma unroll 1
-        for (int q = 0; q < nq; ++q) {
-            const RowIn ya = ypf0;
-            ypf0 = ypf1;
-            ypf1 = load_y(ib + q + 2);
-            PairGeom<T, D> ga;
-            geom(q, ya, ga);
-            count_ok(ga);
-            T la = T(0), ma = T(0);
-            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) {
-                trunc_terms<T>(ga.t, la, ma);
-                la = ga.ok ? la : T(0);
-                ma = ga.ok ? ma : T(0);
+            for (; q + 1 < nq; q += 2) {
+                const RowIn ya = pf[0], yb = pf[1];
+                pf[0] = load_y(ib + q + 2);
+                pf[1] = load_y(ib + q + 3);
+                PairGeom<T, D> ga, gb;
+                geom(q, ya, ga);
+                geom(q + 1, yb, gb);
+                count_ok(ga);
+                count_ok(gb);
+                T la = T(0), ma = T(0), lb = T(0), mb = T(0);
+                if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb))) {
+                    trunc_terms2<T>(ga.t, gb.t, la, ma, lb, mb);
+                    la = ga.ok ? la : T(0);
+                    ma = ga.ok ? ma : T(0);
+                    lb = gb.ok ? lb : T(0);
+                    mb = gb.ok ? mb : T(0);
+                }
+                accum(q, ga, la, ma);
+                accum(q + 1, gb, lb, mb);
             }
-            accum(q, ga, la, ma);
         }
-#endif
+#pragma unroll 1
+        for (; q < nq; ++q) one_row(q);
         acc_r += (double)br_r;
         if (GRAD) {
             acc_s += (double)br_s;
