@@ -72,7 +72,9 @@ enum mds_status {
     MDS_ERR_INVALID_ARGUMENT = -1, /* null pointer, bad size, bad stride, misalignment */
     MDS_ERR_UNSUPPORTED = -2,      /* D outside 1..MDS_MAX_DIM, unknown dtype, bad tiling */
     MDS_ERR_WORKSPACE_TOO_SMALL = -3,
-    MDS_ERR_HIP = -4 /* a HIP runtime call failed; mds_last_error() names it */
+    MDS_ERR_HIP = -4, /* a HIP runtime call failed; mds_last_error() names it */
+    MDS_ERR_NOT_SYMMETRIC = -5 /* reported by the bindings when mds_check_symmetric
+                                  finds mismatched pairs */
 };
 
 /* element types */
@@ -132,6 +134,19 @@ int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src,
                   const uint8_t* missing, int64_t ld_mask, void* y_out, int32_t out_dtype,
                   int64_t ldy, int64_t n, const int64_t* perm, int64_t* m_obs_dev,
                   hipStream_t stream);
+
+/*
+ * Symmetry check of a dissimilarity matrix (Eq. 1 defines y_ij for unordered
+ * pairs; the sweeps read only the strict lower triangle, so an asymmetric Y
+ * or mask silently gives the lower triangle's model).  Counts the pairs
+ * i > j with y_ij != y_ji; two NaNs (two missing entries) count as equal, a
+ * NaN against a number does not.  Checking a prepared Y therefore also checks
+ * that the missing-pair mask was symmetric.
+ *   y               N x N, dtype y_dtype, leading dimension ldy
+ *   mismatches_dev  device int64 receiving the count (0 = symmetric)
+ */
+int mds_check_symmetric(const void* y, int32_t y_dtype, int64_t ldy, int64_t n,
+                        int64_t* mismatches_dev, hipStream_t stream);
 
 /*
  * Spatial relabelling of the locations (a set-up step, not part of the

@@ -21,6 +21,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MDS_LIB_PATH", os.path.join(_PKG, "libmassivemds.so"))
 
 MDS_OK = 0
+MDS_ERR_NOT_SYMMETRIC = -5
 MDS_F64 = 0
 MDS_F32 = 1
 MDS_MAX_DIM = 8
@@ -73,6 +74,8 @@ def lib():
     L.mds_prepare_y.restype = ctypes.c_int
     L.mds_prepare_y.argtypes = [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _c_i32, _c_i64, _c_i64,
                                 _vp, _vp, _vp]
+    L.mds_check_symmetric.restype = ctypes.c_int
+    L.mds_check_symmetric.argtypes = [_vp, _c_i32, _c_i64, _c_i64, _vp, _vp]
     L.mds_resolve_tiling.restype = ctypes.c_int
     L.mds_resolve_tiling.argtypes = [_c_i64, _c_i32, _c_i32, _c_i32, _c_i32,
                                      ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]
@@ -213,6 +216,17 @@ def mds_prepare_y(y_src: torch.Tensor, out_dtype: torch.dtype = torch.float64, m
     return buf[:n], m_obs
 
 
+def mds_check_symmetric(y: torch.Tensor, stream=None) -> int:
+    """Number of pairs i > j with y[i, j] != y[j, i] (two NaNs count as equal);
+    synchronises to read the count."""
+    _check_mat(y, "y", y.dtype)
+    n = y.shape[0]
+    cnt = torch.zeros((), dtype=torch.int64, device=y.device)
+    _check(lib().mds_check_symmetric(_ptr(y), _dtype_code(y.dtype), _ld(y), n, _ptr(cnt),
+                                     _stream(stream)), "mds_check_symmetric")
+    return int(cnt.item())
+
+
 def _check_perm(perm, n, device):
     if not (isinstance(perm, torch.Tensor) and perm.dtype == torch.int64 and perm.is_contiguous()
             and perm.dim() == 1 and perm.numel() == n and perm.device == torch.device(device)):
@@ -340,7 +354,8 @@ class MDSProblem:
     """
 
     def __init__(self, y, d: int, mask=None, dtype=torch.float64, device="cuda",
-                 tile_rows: int = 0, tile_waves: int = 0, autotuned: bool = False, order=None):
+                 tile_rows: int = 0, tile_waves: int = 0, autotuned: bool = False, order=None,
+                 check_symmetric: bool = False):
         y = torch.as_tensor(y)
         n = y.shape[0]
         if autotuned and tile_rows == 0 and tile_waves == 0:
@@ -357,6 +372,11 @@ class MDSProblem:
             xo = torch.as_tensor(order).to(device=device, dtype=torch.float64).contiguous()
             self.perm = mds_spatial_order(xo)
         self.y, self.m_obs = mds_prepare_y(src, dtype, m, perm=self.perm)
+        if check_symmetric:
+            bad = mds_check_symmetric(self.y)
+            if bad:
+                raise MDSError(MDS_ERR_NOT_SYMMETRIC, "MDSProblem",
+                               f"{bad} pairs with y[i, j] != y[j, i] (Y or mask not symmetric)")
         del src, m
         self.tile_rows, self.tile_waves = tile_rows, tile_waves
         self.ws_bytes = mds_workspace_bytes(n, self.d, _dtype_code(dtype), tile_rows, tile_waves)

@@ -25,6 +25,8 @@ hipError_t launch_order(int64_t n, int d, const double* x, int64_t ldx, int64_t*
                         hipStream_t s);
 hipError_t launch_permute_rows(int64_t n, int d, const double* src, int64_t ld_src, double* dst,
                                int64_t ld_dst, const int64_t* perm, int inverse, hipStream_t s);
+hipError_t launch_check_symmetric(const void* y, int dt, int64_t ldy, int64_t n, int64_t* count,
+                                 hipStream_t s);
 hipError_t launch_log_phi(const double* t, double* lnphi, double* mills, int64_t count, int prec,
                           hipStream_t s);
 }  // namespace mds
@@ -196,6 +198,7 @@ const char* mds_status_string(int status)
         case MDS_ERR_UNSUPPORTED: return "MDS_ERR_UNSUPPORTED";
         case MDS_ERR_WORKSPACE_TOO_SMALL: return "MDS_ERR_WORKSPACE_TOO_SMALL";
         case MDS_ERR_HIP: return "MDS_ERR_HIP";
+        case MDS_ERR_NOT_SYMMETRIC: return "MDS_ERR_NOT_SYMMETRIC";
         default: return "MDS_UNKNOWN_STATUS";
     }
 }
@@ -258,6 +261,22 @@ int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src, const ui
     hipError_t e = launch_prepare(y_src, src_dtype, ld_src, missing, ld_mask, y_out, out_dtype,
                                   ldy, n, perm, m_obs_dev, stream);
     if (e != hipSuccess) return hip_fail(e, "prepare launch");
+    return MDS_OK;
+}
+
+int mds_check_symmetric(const void* y, int32_t y_dtype, int64_t ldy, int64_t n,
+                        int64_t* mismatches_dev, hipStream_t stream)
+{
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if (y_dtype != MDS_F64 && y_dtype != MDS_F32)
+        return fail(MDS_ERR_UNSUPPORTED, "y_dtype must be MDS_F64 or MDS_F32");
+    if (!mismatches_dev || (n > 0 && !y))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "y and mismatches_dev must be non-NULL");
+    if (ldy < n) return fail(MDS_ERR_INVALID_ARGUMENT, "ldy < n");
+    if (!aligned(y, dtype_size(y_dtype)) || !aligned(mismatches_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    hipError_t e = launch_check_symmetric(y, y_dtype, ldy, n, mismatches_dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "symmetry check launch");
     return MDS_OK;
 }
 

@@ -435,6 +435,50 @@ hipError_t launch_prepare(const void* src, int sdt, int64_t ld_src, const uint8_
     return hipGetLastError();
 }
 
+// ---------------------------------------------------- symmetry check ---
+
+// one work-group per row i: pairs (i, j < i) against (j, i); one integer
+// atomic per row
+template <typename T>
+__global__ void __launch_bounds__(256)
+    check_symmetric_kernel(const T* __restrict__ y, int64_t ldy, int64_t n,
+                           unsigned long long* count)
+{
+    const int64_t i = blockIdx.x;
+    int bad = 0;
+    for (int64_t j = threadIdx.x; j < i; j += 256) {
+        const T a = y[i * ldy + j], b = y[j * ldy + i];
+        const bool same = (a == b) || (isnan(a) && isnan(b));
+        bad += same ? 0 : 1;
+    }
+    __shared__ int wsum[256 / kWave];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) bad += __shfl_xor(bad, m, kWave);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x / kWave] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int q = 0; q < 256 / kWave; ++q) tot += wsum[q];
+        if (tot) atomicAdd(count, (unsigned long long)tot);
+    }
+}
+
+hipError_t launch_check_symmetric(const void* y, int dt, int64_t ldy, int64_t n, int64_t* count,
+                                  hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_i64_kernel, dim3(1), dim3(64), 0, s, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n == 0) return e;
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(count);
+    if (dt == 0)
+        hipLaunchKernelGGL((check_symmetric_kernel<double>), dim3((unsigned)n), dim3(256), 0, s,
+                           (const double*)y, ldy, n, c);
+    else
+        hipLaunchKernelGGL((check_symmetric_kernel<float>), dim3((unsigned)n), dim3(256), 0, s,
+                           (const float*)y, ldy, n, c);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------ special funcs ---
 
 __global__ void __launch_bounds__(256)

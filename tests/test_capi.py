@@ -144,6 +144,16 @@ def test_prepare_and_log_phi_reject():
     assert L.mds_log_phi(_p(), None, None, 5, 4, None) == ERR_UNSUP
 
 
+def test_check_symmetric_rejects():
+    L = api.lib()
+    assert L.mds_check_symmetric(_p(), 2, 10, 10, _p(), None) == ERR_UNSUP
+    assert L.mds_check_symmetric(_p(), 0, 9, 10, _p(), None) == ERR_ARG
+    assert L.mds_check_symmetric(None, 0, 10, 10, _p(), None) == ERR_ARG
+    assert L.mds_check_symmetric(_p(), 0, 10, 10, None, None) == ERR_ARG
+    assert L.mds_check_symmetric(_p(FAKE + 4), 0, 10, 10, _p(), None) == ERR_ARG
+    assert L.mds_status_string(-5) == b"MDS_ERR_NOT_SYMMETRIC"
+
+
 def test_resolve_tiling():
     L = api.lib()
     f64, f32 = api.MDS_F64, api.MDS_F32

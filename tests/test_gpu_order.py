@@ -136,3 +136,25 @@ def test_relabelled_leapfrog_matches_plain():
     assert np.max(np.abs(x0 - x1)) <= 1e-12 * np.max(np.abs(x0))
     assert np.max(np.abs(p0 - p1)) <= 1e-9 * np.max(np.abs(p0))
     assert abs(l0 - l1) <= 1e-12 * abs(l0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_check_symmetric(dtype):
+    rng = np.random.default_rng(12)
+    n = 257
+    y = np.abs(rng.standard_normal((n, n)))
+    y = np.tril(y, -1)
+    y = y + y.T
+    y[3, 7] = y[7, 3] = np.nan                      # a missing pair on both sides: fine
+    yt = torch.as_tensor(y, dtype=dtype, device=DEV)
+    assert api.mds_check_symmetric(yt) == 0
+    yt[10, 2] += 1.0
+    yt[100, 200] = float("nan")                    # missing on one side only
+    assert api.mds_check_symmetric(yt) == 2
+    # an asymmetric mask shows up in the prepared matrix
+    mask = np.zeros((n, n), np.uint8)
+    mask[5, 1] = 1
+    with pytest.raises(api.MDSError) as e:
+        api.MDSProblem(y, 2, mask, dtype, DEV, check_symmetric=True)
+    assert e.value.status == api.MDS_ERR_NOT_SYMMETRIC
+    api.MDSProblem(y, 2, None, dtype, DEV, check_symmetric=True)

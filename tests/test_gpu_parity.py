@@ -390,3 +390,28 @@ def test_leapfrog_reversible_on_gpu():
     bw = _lf_gpu(P, fw["x"], -fw["p"], sigma, 1e-3, 20)
     assert np.abs(bw["x"] - x).max() < 1e-11
     assert np.abs(-bw["p"] - mom).max() < 1e-9
+
+
+def test_leapfrog_paper_scale_parity():
+    """One 20-step trajectory of the paper-scale workload (N = 5392, run in the
+    spatial labelling, mapped back) against the oracle's trajectory."""
+    p = preset("paper_fp64")
+    mom = np.random.default_rng(40).standard_normal((p.n, p.d))
+    ref = oracle.leapfrog(p.x, mom, p.y, p.sigma, eps=1e-3, n_steps=20, mask=p.mask)
+    P = api.MDSProblem(p.y, p.d, p.mask, torch.float64, DEV, order=p.x)
+    x, pm = P.relabel(p.x), P.relabel(mom)
+    g = torch.empty_like(x)
+    f64 = dict(dtype=torch.float64, device=DEV)
+    L, e0, e1 = (torch.empty((), **f64) for _ in range(3))
+    P.leapfrog(x, pm, p.sigma, 1e-3, 20, g, L, energy_start=e0, energy_end=e1)
+    gx, gp, gg = (P.unlabel(t).cpu().numpy() for t in (x, pm, g))
+    ev = oracle.evaluate(ref.x, p.y, p.sigma, p.mask)
+    ptol = TOL64 * 1e-3 * 21 * np.max(ev.condrow)
+    _log(f"paper-scale leapfrog: max |dx| {np.abs(gx - ref.x).max():.2e} max |dp| "
+         f"{np.abs(gp - ref.p).max():.2e} (tol {ptol:.2e})")
+    assert np.abs(gx - ref.x).max() <= 1e-12 * np.abs(ref.x).max()
+    assert np.abs(gp - ref.p).max() <= ptol
+    assert np.all(np.max(np.abs(gg - ref.grad_end), axis=1) <= 1e-10 * ev.condrow)
+    assert abs(L.item() - ref.loglik_end) <= 1e-11 * abs(ref.loglik_end)
+    assert abs(e0.item() - ref.energy_start) <= 1e-11 * abs(ref.energy_start)
+    assert abs(e1.item() - ref.energy_end) <= 1e-11 * abs(ref.energy_end)
