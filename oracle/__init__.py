@@ -28,6 +28,7 @@ _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_ubyte)
 _i64p = ctypes.POINTER(ctypes.c_int64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
 
 
 def build(force: bool = True) -> str:
@@ -65,6 +66,21 @@ def _load():
                                     _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                     _dp, _dp, _dp, _dp, _dp]
     lib.oracle_grad_rows.restype = ctypes.c_int
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    lib.oracle_uniform_open.restype = ctypes.c_double
+    lib.oracle_uniform_open.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    lib.oracle_momentum.restype = None
+    lib.oracle_momentum.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_uint64,
+                                    ctypes.c_uint64, _dp]
+    lib.oracle_accept_uniform.restype = ctypes.c_double
+    lib.oracle_accept_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.oracle_hmc_step.restype = ctypes.c_int
+    lib.oracle_hmc_step.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, _dp, ctypes.c_int64, _u8p,
+                                    ctypes.c_int64, ctypes.c_double, _dp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_uint64,
+                                    ctypes.c_uint64, _dp, _dp, _dp, _dp, _dp, _dp,
+                                    ctypes.POINTER(ctypes.c_int)]
     lib.oracle_grad_rows.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
                                      ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
                                      _i64p, ctypes.c_int64, _dp, _dp, _dp]
@@ -209,3 +225,70 @@ def leapfrog(x, p, y, sigma: float, eps: float, n_steps: int, mask=None,
     if rc != 0:
         raise ValueError("oracle_leapfrog rejected its arguments")
     return Trajectory(x, p, g, out[0], out[1], out[2], out[3])
+
+
+# ------------------------------------------------------ HMC transition ----
+
+def philox4x32_10(ctr, key):
+    """The Philox4x32-10 block for a 4-word counter and a 2-word key."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib.oracle_philox4x32_10(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(out, _u32p))
+    return out
+
+
+def uniform_open(a: int, b: int) -> float:
+    return _load().oracle_uniform_open(int(a), int(b))
+
+
+def momentum(n: int, d: int, seed: int, iteration: int, inv_mass=None) -> np.ndarray:
+    """The momentum draw of HMC transition `iteration` (N x D)."""
+    lib = _load()
+    im = None if inv_mass is None else np.ascontiguousarray(inv_mass, dtype=np.float64)
+    p = np.zeros((n, d), dtype=np.float64)
+    lib.oracle_momentum(n, d, _ptr(im), int(seed), int(iteration), _ptr(p))
+    return p
+
+
+def accept_uniform(seed: int, iteration: int) -> float:
+    return _load().oracle_accept_uniform(int(seed), int(iteration))
+
+
+@dataclass
+class HMCStep:
+    x: np.ndarray
+    p: np.ndarray
+    grad: np.ndarray
+    loglik: float
+    energy_start: float
+    energy_end: float
+    log_u: float
+    accepted: bool
+
+
+def hmc_step(x, y, sigma: float, eps: float, n_steps: int, seed: int, iteration: int,
+             mask=None, inv_mass=None, prior_precision: float = 0.0) -> HMCStep:
+    """One HMC transition (Section 2.3) from state x; inputs untouched."""
+    lib = _load()
+    x = np.array(x, dtype=np.float64, copy=True, order="C")
+    n, d = x.shape
+    y = _as_y(y)
+    m = _as_mask(mask, n)
+    im = None if inv_mass is None else np.ascontiguousarray(inv_mass, dtype=np.float64)
+    p = np.zeros((n, d), dtype=np.float64)
+    g = np.zeros((n, d), dtype=np.float64)
+    out = (ctypes.c_double * 4)()
+    acc = ctypes.c_int(0)
+    rc = lib.oracle_hmc_step(n, d, _ptr(x), _ptr(y), y.shape[1], _ptr(m, _u8p),
+                             n if m is not None else 0, float(sigma), _ptr(im), float(eps),
+                             float(prior_precision), int(n_steps), int(seed), int(iteration),
+                             _ptr(p), _ptr(g), ctypes.cast(ctypes.byref(out, 0), _dp),
+                             ctypes.cast(ctypes.byref(out, 8), _dp),
+                             ctypes.cast(ctypes.byref(out, 16), _dp),
+                             ctypes.cast(ctypes.byref(out, 24), _dp), ctypes.byref(acc))
+    if rc != 0:
+        raise ValueError("oracle_hmc_step rejected its arguments")
+    return HMCStep(x, p, g, out[0], out[1], out[2], out[3], bool(acc.value))
+

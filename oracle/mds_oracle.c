@@ -319,6 +319,130 @@ int oracle_leapfrog(int64_t n, int d, double* x, double* p, const double* y, int
     return 0;
 }
 
+/* ----------------------------------------------------- HMC transition -- */
+
+/*
+ * One Hamiltonian Monte Carlo transition (Section 2.3): draw the momentum
+ * p ~ N(0, M), run one leapfrog trajectory, accept the proposal with
+ * probability min(1, exp(H_start - H_end)) (Eq. 6 gives H), else keep x.
+ *
+ * The random draws come from the counter-based generator Philox4x32-10 of
+ * Salmon, Moraes, Dror and Shaw ("Parallel random numbers: as easy as 1, 2,
+ * 3", SC 2011): ten rounds of two 32x32->64-bit multiplications whose high
+ * and low halves are mixed with the other counter words and the key, the key
+ * advancing by the Weyl constants between rounds.  A block is indexed by a
+ * 64-bit draw index k and the transition index `it`, keyed by the seed:
+ *     block(k, it) = philox(counter = (k_lo, k_hi, it_lo, it_hi),
+ *                           key = (seed_lo, seed_hi))
+ * and a uniform in the open interval (0, 1) is made of 52 bits of two
+ * output words (exact in FP64, so it never rounds to 0 or 1):
+ *     uniform(a, b) = ((a >> 6) * 2^26 + (b >> 6) + 1/2) * 2^-52.
+ * Momentum element e (row-major N x D) uses block k = e / 2 and the
+ * Box-Muller transform: u1 = uniform(r0, r1), u2 = uniform(r2, r3),
+ * z = sqrt(-2 ln u1) cos(2 pi u2) for even e, sin(2 pi u2) for odd e, and
+ * p_e = z / sqrt(inv_mass_e) (variance M_e = 1 / inv_mass_e).  The
+ * acceptance draw is u = uniform(r0, r1) of block k = 2^63; the proposal is
+ * accepted when ln u < H_start - H_end (never when that is NaN).
+ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+double oracle_uniform_open(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 6) * 67108864.0 + (double)(b >> 6) + 0.5) / 4503599627370496.0;
+}
+
+static void draw_block(uint64_t k, uint64_t it, uint64_t seed, uint32_t r[4])
+{
+    const uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), (uint32_t)it, (uint32_t)(it >> 32)};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    oracle_philox4x32_10(ctr, key, r);
+}
+
+void oracle_momentum(int64_t n, int d, const double* inv_mass, uint64_t seed, uint64_t it,
+                     double* p)
+{
+    const double two_pi = 6.28318530717958647692;
+    for (int64_t e = 0; e < n * d; ++e) {
+        uint32_t r[4];
+        draw_block((uint64_t)(e / 2), it, seed, r);
+        const double u1 = oracle_uniform_open(r[0], r[1]), u2 = oracle_uniform_open(r[2], r[3]);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double z = (e % 2 == 0) ? rad * cos(two_pi * u2) : rad * sin(two_pi * u2);
+        p[e] = z / sqrt(inv_mass ? inv_mass[e] : 1.0);
+    }
+}
+
+double oracle_accept_uniform(uint64_t seed, uint64_t it)
+{
+    uint32_t r[4];
+    draw_block((uint64_t)1 << 63, it, seed, r);
+    return oracle_uniform_open(r[0], r[1]);
+}
+
+/*
+ * x (n*d) is the chain's state, replaced by the proposal when it is
+ * accepted.  p_out receives the momentum at the end of the trajectory,
+ * grad_out and loglik_out grad log pi and L at the returned x.  h_start,
+ * h_end, log_u and accepted report the Metropolis test.
+ */
+int oracle_hmc_step(int64_t n, int d, double* x, const double* y, int64_t ldy,
+                    const unsigned char* mask, int64_t ldm, double sigma,
+                    const double* inv_mass, double eps, double lambda, int n_steps,
+                    uint64_t seed, uint64_t it, double* p_out, double* grad_out,
+                    double* loglik_out, double* h_start, double* h_end, double* log_u,
+                    int* accepted)
+{
+    if (n < 0 || d < 1 || n_steps < 0 || !p_out || !grad_out) return -1;
+    const int64_t nd = n * d;
+    double* x0 = (double*)malloc(sizeof(double) * (size_t)(nd > 0 ? nd : 1));
+    if (!x0) return -1;
+    memcpy(x0, x, sizeof(double) * (size_t)nd);
+    oracle_momentum(n, d, inv_mass, seed, it, p_out);
+    double hs = 0.0, he = 0.0, L = 0.0;
+    int rc = oracle_leapfrog(n, d, x, p_out, y, ldy, mask, ldm, sigma, inv_mass, eps, lambda,
+                             n_steps, grad_out, NULL, &L, &hs, &he);
+    if (rc) {
+        free(x0);
+        return rc;
+    }
+    const double lu = log(oracle_accept_uniform(seed, it));
+    const int acc = lu < hs - he;
+    if (!acc) {
+        memcpy(x, x0, sizeof(double) * (size_t)nd);
+        rc = target_grad(n, d, x, y, ldy, mask, ldm, sigma, lambda, grad_out, &L);
+    }
+    free(x0);
+    if (loglik_out) *loglik_out = L;
+    if (h_start) *h_start = hs;
+    if (h_end) *h_end = he;
+    if (log_u) *log_u = lu;
+    if (accepted) *accepted = acc;
+    return rc;
+}
+
 /* ------------------------------------------------------- sampled rows -- */
 
 /*

@@ -68,12 +68,13 @@ constexpr size_t kMaxSweepLds = 64 * 1024;
 void default_tiling(int64_t n, int d, int dtype, int* br, int* waves)
 {
     (void)d;
+    (void)dtype;
     if (n <= 2048) {
         *br = 32;
         *waves = 1;
     } else if (n <= 6144) {
         *br = 32;
-        *waves = (dtype == MDS_F64) ? 2 : 4;
+        *waves = 4;
     } else {
         *br = 64;
         *waves = 4;

@@ -158,7 +158,7 @@ def test_resolve_tiling():
     L = api.lib()
     f64, f32 = api.MDS_F64, api.MDS_F32
     assert api.mds_resolve_tiling(1000, 2, f64) == (32, 1)
-    assert api.mds_resolve_tiling(5392, 2, f64) == (32, 2)
+    assert api.mds_resolve_tiling(5392, 2, f64) == (32, 4)
     assert api.mds_resolve_tiling(5392, 2, f32) == (32, 4)
     assert api.mds_resolve_tiling(20000, 6, f32) == (64, 4)
     assert api.mds_resolve_tiling(5392, 2, f64, 128, 2) == (128, 2)
