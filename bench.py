@@ -213,6 +213,20 @@ def main():
     torch.cuda.synchronize()
     traj_ms = (time.perf_counter() - t0) * 1e3 / reps
 
+    # 100 HMC transitions of 20 leapfrog steps (step 1e-3, unit mass), FP64,
+    # replayed as a captured graph of 10 transitions; the chain starts at the
+    # evaluation point
+    from paper_1905_04582_amd import graphs
+    chain = graphs.HMCChainGraph(P64, xr, n_steps=20, sigma=sigma, step=1e-3, seed=1905,
+                                 transitions_per_graph=10)
+    chain.run(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chain.run(10)
+    torch.cuda.synchronize()
+    hmc_ms = (time.perf_counter() - t0) * 1e3 / 100
+    hmc_acc = chain.accepted.item() / 110
+
     # algorithmic traffic of one sweep: the strict lower triangle of Y once
     # (X in and the partial sums out are under 0.1% of it)
     y_bytes64 = npairs * 8
@@ -280,6 +294,9 @@ def main():
         "original_labelling": plain,
         "leapfrog": {"steps": 20, "step_size": 1e-3, "ms_per_trajectory": round(traj_ms, 4),
                      "gradient_evals": 20},
+        "hmc": {"transitions": 100, "leapfrog_steps": 20, "step_size": 1e-3,
+                "ms_per_transition": round(hmc_ms, 4), "transitions_per_s": round(1e3 / hmc_ms, 2),
+                "acceptance": round(hmc_acc, 3), "graph": "10 transitions per replay"},
         "pair_rate_fp64_gpairs_s": round(npairs / (sweep64 * 1e-3) / 1e9, 3),
         "context_paper": "GP100 OpenCL FP64 at N=5338: 4.5 ms likelihood + 4 ms gradient "
                          "(separate evaluations); context only",

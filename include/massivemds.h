@@ -241,6 +241,54 @@ int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_
                  hipStream_t stream);
 
 /*
+ * One Hamiltonian Monte Carlo transition (Section 2.3, Eqs. 6-8) of the
+ * chain whose state is x, on the target log pi(X) = L(X) - (lambda/2)||X||^2
+ * of mds_leapfrog: draw p ~ N(0, M), run one leapfrog trajectory of n_steps
+ * steps, and accept the proposal with probability min(1, exp(H_start -
+ * H_end)); a rejected proposal leaves x, grad_io and loglik_io as they were.
+ *
+ * Random draws (not part of the paper, which leaves them unspecified):
+ * Philox4x32-10 (Salmon et al., SC 2011) with key (seed_lo, seed_hi) and
+ * counter (k_lo, k_hi, it_lo, it_hi), where `it` = *iteration_dev is the
+ * transition's index and k the draw's index; uniform(a, b) = ((a >> 6) 2^26
+ * + (b >> 6) + 1/2) 2^-52 lies in (0, 1).  Momentum element e of the
+ * row-major N x D array uses block k = e / 2: u1 = uniform(r0, r1), u2 =
+ * uniform(r2, r3), z = sqrt(-2 ln u1) cos(2 pi u2) for even e and sin(2 pi
+ * u2) for odd e, p_e = z / sqrt(inv_mass_e).  The test uses u = uniform(r0,
+ * r1) of block k = 2^63 and accepts when ln u < H_start - H_end (never when
+ * that difference is NaN).
+ *
+ *   x              N x D FP64 (ldx), the chain's state, updated in place
+ *   iteration_dev  device uint64: the transition index; incremented by one
+ *   p              N x D FP64 (ldp): the momentum at the trajectory's end
+ *   grad_io, loglik_io, cache_valid
+ *                  as in mds_leapfrog; on exit they describe the returned x
+ *   stats_dev      optional device double[4]: H_start, H_end, ln u, accepted
+ *                  (1.0 or 0.0)
+ *   accepted_total_dev  optional device int64, incremented on acceptance
+ *   workspace      mds_hmc_workspace_bytes() bytes (the gradient workspace
+ *                  plus room to save the state)
+ * Every step runs on the device and reads its scalars from device memory, so
+ * transitions can be captured in a graph and replayed as a chain.
+ */
+int mds_hmc_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
+                            int32_t tile_waves, size_t* bytes);
+int mds_hmc_step(int64_t n, int32_t d, double* x, int64_t ldx, const void* y, int32_t y_dtype,
+                 int64_t ldy, const double* sigma_dev, const double* inv_mass,
+                 const double* step_dev, const double* prior_dev, int32_t n_steps,
+                 uint64_t seed, uint64_t* iteration_dev, double* p, int64_t ldp,
+                 double* grad_io, double* loglik_io, int32_t cache_valid, double* stats_dev,
+                 int64_t* accepted_total_dev, void* workspace, size_t workspace_bytes,
+                 int32_t tile_rows, int32_t tile_waves, hipStream_t stream);
+
+/*
+ * The momentum draw of mds_hmc_step alone: p (N x D, ldp) = the momentum of
+ * transition *iteration_dev under seed (iteration_dev is not incremented).
+ */
+int mds_hmc_momentum(int64_t n, int32_t d, const double* inv_mass, uint64_t seed,
+                     const uint64_t* iteration_dev, double* p, int64_t ldp, hipStream_t stream);
+
+/*
  * The device special functions of the sweeps, elementwise: ln Phi(t) and
  * phi(t)/Phi(t) (Eq. 2 and Eq. 9) for any real t, in the arithmetic of
  * `precision` (MDS_F64, or MDS_F32: t rounded to FP32 and FP32 arithmetic,

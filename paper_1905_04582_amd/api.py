@@ -74,6 +74,15 @@ def lib():
     L.mds_prepare_y.restype = ctypes.c_int
     L.mds_prepare_y.argtypes = [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _c_i32, _c_i64, _c_i64,
                                 _vp, _vp, _vp]
+    L.mds_hmc_workspace_bytes.restype = ctypes.c_int
+    L.mds_hmc_workspace_bytes.argtypes = [_c_i64, _c_i32, _c_i32, _c_i32, _c_i32,
+                                          ctypes.POINTER(ctypes.c_size_t)]
+    L.mds_hmc_momentum.restype = ctypes.c_int
+    L.mds_hmc_momentum.argtypes = [_c_i64, _c_i32, _vp, ctypes.c_uint64, _vp, _vp, _c_i64, _vp]
+    L.mds_hmc_step.restype = ctypes.c_int
+    L.mds_hmc_step.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i64, _vp, _vp, _vp,
+                               _vp, _c_i32, ctypes.c_uint64, _vp, _vp, _c_i64, _vp, _vp, _c_i32,
+                               _vp, _vp, _vp, ctypes.c_size_t, _c_i32, _c_i32, _vp]
     L.mds_check_symmetric.restype = ctypes.c_int
     L.mds_check_symmetric.argtypes = [_vp, _c_i32, _c_i64, _c_i64, _vp, _vp]
     L.mds_resolve_tiling.restype = ctypes.c_int
@@ -324,6 +333,67 @@ def mds_leapfrog(x, p, y, sigma, step, n_steps, workspace, grad_io, loglik_io,
                               _stream(stream)), "mds_leapfrog")
 
 
+def mds_hmc_workspace_bytes(n: int, d: int, y_dtype: int, tile_rows: int = 0,
+                            tile_waves: int = 0) -> int:
+    nb = ctypes.c_size_t()
+    _check(lib().mds_hmc_workspace_bytes(n, d, y_dtype, tile_rows, tile_waves, ctypes.byref(nb)),
+           "mds_hmc_workspace_bytes")
+    return int(nb.value)
+
+
+def _check_counter(t, device):
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.int64 and t.numel() == 1
+            and t.device == torch.device(device)):
+        raise ValueError("the transition counter must be a one-element int64 device tensor")
+
+
+def mds_hmc_momentum(n: int, d: int, seed: int, iteration: torch.Tensor, inv_mass=None,
+                     out=None, stream=None) -> torch.Tensor:
+    """The momentum draw of HMC transition *iteration (an int64 device scalar
+    read as uint64) under `seed`."""
+    dev = iteration.device
+    _check_counter(iteration, dev)
+    out = torch.empty((n, d), dtype=torch.float64, device=dev) if out is None else out
+    _check_mat(out, "out")
+    if inv_mass is not None:
+        _check_mat(inv_mass, "inv_mass")
+    _check(lib().mds_hmc_momentum(n, d, _ptr(inv_mass), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                  _ptr(iteration), _ptr(out), _ld(out), _stream(stream)),
+           "mds_hmc_momentum")
+    return out
+
+
+def mds_hmc_step(x, p, y, sigma, step, n_steps, seed, iteration, workspace, grad_io, loglik_io,
+                 cache_valid=False, inv_mass=None, prior=None, stats=None, accepted_total=None,
+                 tile_rows=0, tile_waves=0, stream=None):
+    """One HMC transition of the chain at x (in place); see include/massivemds.h."""
+    for t, nm in ((x, "x"), (p, "p"), (grad_io, "grad_io")):
+        _check_mat(t, nm)
+    _check_mat(y, "y", y.dtype)
+    n, d = x.shape
+    dev = x.device
+    _check_counter(iteration, dev)
+    if grad_io.shape != (n, d) or not grad_io.is_contiguous():
+        raise ValueError("grad_io must be a contiguous N x D float64 tensor")
+    if inv_mass is not None and (inv_mass.shape != (n, d) or not inv_mass.is_contiguous()
+                                 or inv_mass.dtype != torch.float64):
+        raise ValueError("inv_mass must be a contiguous N x D float64 tensor")
+    if stats is not None and (stats.dtype != torch.float64 or stats.numel() < 4):
+        raise ValueError("stats must hold four float64 values")
+    if accepted_total is not None:
+        _check_counter(accepted_total, dev)
+    sig = _dev_scalar(sigma, dev)
+    eps = _dev_scalar(step, dev)
+    lam = None if prior is None else _dev_scalar(prior, dev)
+    _check(lib().mds_hmc_step(n, d, _ptr(x), _ld(x), _ptr(y), _dtype_code(y.dtype), _ld(y),
+                              _ptr(sig), _ptr(inv_mass), _ptr(eps), _ptr(lam), int(n_steps),
+                              int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(iteration), _ptr(p), _ld(p),
+                              _ptr(grad_io), _ptr(loglik_io), 1 if cache_valid else 0,
+                              _ptr(stats), _ptr(accepted_total), _ptr(workspace),
+                              workspace.numel(), tile_rows, tile_waves, _stream(stream)),
+           "mds_hmc_step")
+
+
 def mds_log_phi(t: torch.Tensor, precision: int = MDS_F64, stream=None):
     """(ln Phi(t), phi(t)/Phi(t)) elementwise on the device."""
     if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
@@ -392,6 +462,19 @@ class MDSProblem:
         """N x D array in the problem's labelling -> the caller's labelling."""
         return a.clone() if self.perm is None else mds_permute_rows(a, self.perm, True, out,
                                                                     stream)
+
+    def hmc_step(self, x, p, sigma, step, n_steps, seed, iteration, grad_io, loglik_io,
+                 cache_valid=False, inv_mass=None, prior=None, stats=None, accepted_total=None,
+                 stream=None):
+        """One HMC transition (see ``mds_hmc_step``); x, p, grad_io in this
+        problem's labelling."""
+        nb = mds_hmc_workspace_bytes(self.n, self.d, _dtype_code(self.dtype), self.tile_rows,
+                                     self.tile_waves)
+        if getattr(self, "_hmc_ws", None) is None or self._hmc_ws.numel() < nb:
+            self._hmc_ws = alloc_workspace(nb, self.device)
+        mds_hmc_step(x, p, self.y, sigma, step, n_steps, seed, iteration, self._hmc_ws, grad_io,
+                     loglik_io, cache_valid, inv_mass, prior, stats, accepted_total,
+                     self.tile_rows, self.tile_waves, stream)
 
     def set_tiling(self, tile_rows: int, tile_waves: int):
         nb = mds_workspace_bytes(self.n, self.d, _dtype_code(self.dtype), tile_rows, tile_waves)

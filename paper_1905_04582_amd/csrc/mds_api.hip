@@ -27,6 +27,15 @@ hipError_t launch_permute_rows(int64_t n, int d, const double* src, int64_t ld_s
                                int64_t ld_dst, const int64_t* perm, int inverse, hipStream_t s);
 hipError_t launch_check_symmetric(const void* y, int dt, int64_t ldy, int64_t n, int64_t* count,
                                  hipStream_t s);
+hipError_t launch_hmc_begin(int64_t n, int d, const double* inv_mass, uint64_t seed,
+                            const uint64_t* iteration, double* p, int64_t ldp, const double* x,
+                            int64_t ldx, const double* grad, const double* loglik, double* x_save,
+                            double* g_save, double* l_save, hipStream_t s);
+hipError_t launch_hmc_decide(uint64_t seed, uint64_t* iteration, const double* energies,
+                             double* flag, double* stats, int64_t* accepted_total, hipStream_t s);
+hipError_t launch_hmc_finish(int64_t n, int d, const double* flag, double* x, int64_t ldx,
+                             double* grad, double* loglik, const double* x_save,
+                             const double* g_save, const double* l_save, hipStream_t s);
 hipError_t launch_log_phi(const double* t, double* lnphi, double* mills, int64_t count, int prec,
                           hipStream_t s);
 }  // namespace mds
@@ -459,6 +468,108 @@ int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_
     return MDS_OK;
 }
 
+// HMC workspace: the gradient workspace, then the saved x and gradient
+// (n*d doubles each) and four scalars (saved L, H_start, H_end, decision)
+struct HmcLayout {
+    size_t x_save, g_save, scal, total;
+};
+
+static HmcLayout hmc_layout(const WorkspaceLayout& lay, int64_t n, int d)
+{
+    HmcLayout h;
+    const size_t nd = (size_t)n * d * sizeof(double);
+    h.x_save = align_up(lay.total, 256);
+    h.g_save = align_up(h.x_save + nd, 256);
+    h.scal = align_up(h.g_save + nd, 256);
+    h.total = align_up(h.scal + 4 * sizeof(double), 256);
+    return h;
+}
+
+int mds_hmc_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
+                            int32_t tile_waves, size_t* bytes)
+{
+    if (!bytes) return fail(MDS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if (d < 1 || d > MDS_MAX_DIM)
+        return fail(MDS_ERR_UNSUPPORTED, "d=%d: must be 1..%d", d, MDS_MAX_DIM);
+    if (y_dtype != MDS_F64 && y_dtype != MDS_F32)
+        return fail(MDS_ERR_UNSUPPORTED, "y_dtype must be MDS_F64 or MDS_F32");
+    Tiling t;
+    const int st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t);
+    if (st) return st;
+    *bytes = hmc_layout(workspace_layout(t, d), n, d).total;
+    return MDS_OK;
+}
+
+int mds_hmc_momentum(int64_t n, int32_t d, const double* inv_mass, uint64_t seed,
+                     const uint64_t* iteration_dev, double* p, int64_t ldp, hipStream_t stream)
+{
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if (d < 1 || d > MDS_MAX_DIM)
+        return fail(MDS_ERR_UNSUPPORTED, "d=%d: must be 1..%d", d, MDS_MAX_DIM);
+    if (!iteration_dev || (n > 0 && !p))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "iteration_dev and p must be non-NULL");
+    if (ldp < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldp < d");
+    if (!aligned(iteration_dev, 8) || !aligned(p, 8) || !aligned(inv_mass, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    hipError_t e = launch_hmc_begin(n, d, inv_mass, seed, iteration_dev, p, ldp, nullptr, 0,
+                                    nullptr, nullptr, nullptr, nullptr, nullptr, stream);
+    if (e != hipSuccess) return hip_fail(e, "momentum launch");
+    return MDS_OK;
+}
+
+int mds_hmc_step(int64_t n, int32_t d, double* x, int64_t ldx, const void* y, int32_t y_dtype,
+                 int64_t ldy, const double* sigma_dev, const double* inv_mass,
+                 const double* step_dev, const double* prior_dev, int32_t n_steps,
+                 uint64_t seed, uint64_t* iteration_dev, double* p, int64_t ldp,
+                 double* grad_io, double* loglik_io, int32_t cache_valid, double* stats_dev,
+                 int64_t* accepted_total_dev, void* workspace, size_t workspace_bytes,
+                 int32_t tile_rows, int32_t tile_waves, hipStream_t stream)
+{
+    int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
+    if (st) return st;
+    if (!iteration_dev || !aligned(iteration_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "iteration_dev NULL or misaligned");
+    if (!aligned(stats_dev, 8) || !aligned(accepted_total_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    Tiling t;
+    if ((st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t))) return st;
+    const WorkspaceLayout lay = workspace_layout(t, d);
+    const HmcLayout h = hmc_layout(lay, n, d);
+    if (!workspace || !aligned(workspace, MDS_WORKSPACE_ALIGN))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "workspace NULL or not %d-byte aligned",
+                    MDS_WORKSPACE_ALIGN);
+    if (workspace_bytes < h.total)
+        return fail(MDS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed",
+                    workspace_bytes, h.total);
+    char* base = static_cast<char*>(workspace);
+    double* x_save = reinterpret_cast<double*>(base + h.x_save);
+    double* g_save = reinterpret_cast<double*>(base + h.g_save);
+    double* scal = reinterpret_cast<double*>(base + h.scal);  // L_save, H0, H1, decision
+
+    // grad log pi and L at x, when the caller has no cached values
+    if (!cache_valid) {
+        st = mds_leapfrog(n, d, x, ldx, p, ldp, y, y_dtype, ldy, sigma_dev, inv_mass, step_dev,
+                          prior_dev, 0, grad_io, loglik_io, 0, nullptr, nullptr, workspace,
+                          lay.total, tile_rows, tile_waves, stream);
+        if (st) return st;
+    }
+    hipError_t e = launch_hmc_begin(n, d, inv_mass, seed, iteration_dev, p, ldp, x, ldx, grad_io,
+                                    loglik_io, x_save, g_save, scal, stream);
+    if (e != hipSuccess) return hip_fail(e, "momentum launch");
+    st = mds_leapfrog(n, d, x, ldx, p, ldp, y, y_dtype, ldy, sigma_dev, inv_mass, step_dev,
+                      prior_dev, n_steps, grad_io, loglik_io, 1, scal + 1, scal + 2, workspace,
+                      lay.total, tile_rows, tile_waves, stream);
+    if (st) return st;
+    e = launch_hmc_decide(seed, iteration_dev, scal + 1, scal + 3, stats_dev, accepted_total_dev,
+                          stream);
+    if (e != hipSuccess) return hip_fail(e, "decision launch");
+    e = launch_hmc_finish(n, d, scal + 3, x, ldx, grad_io, loglik_io, x_save, g_save, scal,
+                          stream);
+    if (e != hipSuccess) return hip_fail(e, "restore launch");
+    return MDS_OK;
+}
+
 int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count, int32_t precision,
                 hipStream_t stream)
 {
@@ -487,7 +598,7 @@ struct BatchLayout {
     size_t total;
 };
 
-int batch_layout(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
+static int batch_layout(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
                  int32_t tile_waves, BatchLayout* L, size_t* max_lds)
 {
     if (count < 1) return fail(MDS_ERR_INVALID_ARGUMENT, "count=%d < 1", count);
@@ -524,7 +635,7 @@ int batch_layout(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
     return MDS_OK;
 }
 
-int device_cu_count(int* cus)
+static int device_cu_count(int* cus)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);

@@ -154,6 +154,38 @@ def test_check_symmetric_rejects():
     assert L.mds_status_string(-5) == b"MDS_ERR_NOT_SYMMETRIC"
 
 
+def test_hmc_rejects():
+    L = api.lib()
+    nb = ctypes.c_size_t()
+    assert L.mds_hmc_workspace_bytes(1000, 2, 0, 0, 0, None) == ERR_ARG
+    assert L.mds_hmc_workspace_bytes(1000, 9, 0, 0, 0, ctypes.byref(nb)) == ERR_UNSUP
+    assert L.mds_hmc_workspace_bytes(1000, 2, 0, 0, 0, ctypes.byref(nb)) == 0
+    g = ctypes.c_size_t()
+    assert L.mds_workspace_bytes(1000, 2, 0, 0, 0, ctypes.byref(g)) == 0
+    assert nb.value >= g.value + 2 * 1000 * 2 * 8
+    assert L.mds_hmc_momentum(10, 2, None, 1, None, _p(), 2, None) == ERR_ARG
+    assert L.mds_hmc_momentum(10, 2, None, 1, _p(), None, 2, None) == ERR_ARG
+    assert L.mds_hmc_momentum(10, 2, None, 1, _p(), _p(), 1, None) == ERR_ARG
+    assert L.mds_hmc_momentum(10, 0, None, 1, _p(), _p(), 2, None) == ERR_UNSUP
+    assert L.mds_hmc_momentum(10, 2, None, 1, _p(FAKE + 4), _p(), 2, None) == ERR_ARG
+    ws = _p(FAKE + 65536)
+    ok = [100, 2, _p(), 2, _p(FAKE + 4096), 0, 128, _p(), None, _p(), None, 20, 7,
+          _p(FAKE + 8192), _p(FAKE + 12288), 2, _p(FAKE + 16384), _p(), 0, None, None, ws,
+          1 << 30, 0, 0, None]
+    bad = list(ok)
+    bad[13] = None                                   # no transition counter
+    assert L.mds_hmc_step(*bad) == ERR_ARG
+    bad = list(ok)
+    bad[22] = 16                                     # workspace too small
+    assert L.mds_hmc_step(*bad) == ERR_WS
+    bad = list(ok)
+    bad[21] = _p(FAKE + 65536 + 8)                   # misaligned workspace
+    assert L.mds_hmc_step(*bad) == ERR_ARG
+    bad = list(ok)
+    bad[19] = _p(FAKE + 3)                           # misaligned stats
+    assert L.mds_hmc_step(*bad) == ERR_ARG
+
+
 def test_resolve_tiling():
     L = api.lib()
     f64, f32 = api.MDS_F64, api.MDS_F32
