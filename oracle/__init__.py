@@ -60,6 +60,8 @@ def _load():
     lib.oracle_eval.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
                                 ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
                                 _dp, _dp, _dp, _dp, _dp, _dp, _dp, _i64p]
+    lib.oracle_eval_normal.restype = ctypes.c_int
+    lib.oracle_eval_normal.argtypes = lib.oracle_eval.argtypes
     lib.oracle_leapfrog.restype = ctypes.c_int
     lib.oracle_leapfrog.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, _dp, _dp,
                                     ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
@@ -144,8 +146,9 @@ class Evaluation:
     m_obs: int
 
 
-def evaluate(x, y, sigma: float, mask=None) -> Evaluation:
-    """L, dL/dX and dL/dsigma of Eq. (2)/(9) at X for dissimilarities Y."""
+def evaluate(x, y, sigma: float, mask=None, truncated: bool = True) -> Evaluation:
+    """L, dL/dX and dL/dsigma of Eq. (2)/(9) at X for dissimilarities Y
+    (truncated=False: the same model without the truncation to y > 0)."""
     lib = _load()
     x = np.ascontiguousarray(x, dtype=np.float64)
     if x.ndim == 1:
@@ -159,12 +162,12 @@ def evaluate(x, y, sigma: float, mask=None) -> Evaluation:
     condrow = np.zeros(n, dtype=np.float64)
     out = (ctypes.c_double * 5)()
     mobs = ctypes.c_int64(0)
-    rc = lib.oracle_eval(n, d, _ptr(x), d, _ptr(y), y.shape[1], _ptr(m, _u8p),
-                         n if m is not None else 0, float(sigma),
-                         ctypes.cast(ctypes.byref(out, 0), _dp), _ptr(grad),
-                         ctypes.cast(ctypes.byref(out, 8), _dp), _ptr(absrow), _ptr(condrow),
-                         ctypes.cast(ctypes.byref(out, 16), _dp),
-                         ctypes.cast(ctypes.byref(out, 24), _dp), ctypes.byref(mobs))
+    fn = lib.oracle_eval if truncated else lib.oracle_eval_normal
+    rc = fn(n, d, _ptr(x), d, _ptr(y), y.shape[1], _ptr(m, _u8p), n if m is not None else 0,
+            float(sigma), ctypes.cast(ctypes.byref(out, 0), _dp), _ptr(grad),
+            ctypes.cast(ctypes.byref(out, 8), _dp), _ptr(absrow), _ptr(condrow),
+            ctypes.cast(ctypes.byref(out, 16), _dp), ctypes.cast(ctypes.byref(out, 24), _dp),
+            ctypes.byref(mobs))
     if rc != 0:
         raise ValueError("oracle_eval rejected its arguments")
     return Evaluation(out[0], grad, out[1], absrow, condrow, out[2], out[3], int(mobs.value))

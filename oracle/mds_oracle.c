@@ -135,11 +135,17 @@ int64_t oracle_count_observed(int64_t n, const double* y, int64_t ldy,
  *   abs_ds    sum |dsigma terms| + M / sigma, the scale of dL/dsigma's sum
  *   m_obs     number of observed pairs
  * Returns 0, or -1 on bad arguments or allocation failure.
+ *
+ * With truncated = 0 the same pass evaluates the model without the
+ * truncation to y > 0, i.e. plain normal errors y_ij ~ N(delta_ij, sigma^2)
+ * (the comparison the paper draws in its scaling appendix): the ln Phi term
+ * of Eq. (2) and the phi/Phi term of Eq. (9) are left out.
  */
-int oracle_eval(int64_t n, int d, const double* x, int64_t ldx, const double* y,
-                int64_t ldy, const unsigned char* mask, int64_t ldm, double sigma,
-                double* loglik, double* grad, double* dsigma, double* absrow,
-                double* condrow, double* abs_l, double* abs_ds, int64_t* m_obs)
+static int eval_pairs(int64_t n, int d, const double* x, int64_t ldx, const double* y,
+                      int64_t ldy, const unsigned char* mask, int64_t ldm, double sigma,
+                      int truncated, double* loglik, double* grad, double* dsigma,
+                      double* absrow, double* condrow, double* abs_l, double* abs_ds,
+                      int64_t* m_obs)
 {
     if (n < 0 || d < 1 || ldx < d || (n > 0 && ldy < n)) return -1;
     if (mask && n > 0 && ldm < n) return -1;
@@ -185,9 +191,9 @@ int oracle_eval(int64_t n, int d, const double* x, int64_t ldx, const double* y,
             const double t = delta / sigma;
             /* truncation terms of Eq. (2) and Eq. (9) */
             const double q = 0.5 * erfc(t / ORACLE_SQRT2); /* Phi(-t) */
-            const double lnphi = log1p(-q);                /* ln Phi(t) */
+            const double lnphi = truncated ? log1p(-q) : 0.0; /* ln Phi(t) */
             const double phi = exp(-0.5 * t * t) * ORACLE_INV_SQRT_2PI;
-            const double mills = phi / (1.0 - q); /* phi(t)/Phi(t) */
+            const double mills = truncated ? phi / (1.0 - q) : 0.0; /* phi(t)/Phi(t) */
             const double resid = yij - delta;
             /* r_ij of Eq. (2) */
             const double r = resid * resid / (2.0 * s2) + lnphi;
@@ -236,6 +242,25 @@ int oracle_eval(int64_t n, int d, const double* x, int64_t ldx, const double* y,
     free(a);
     free(b);
     return 0;
+}
+
+int oracle_eval(int64_t n, int d, const double* x, int64_t ldx, const double* y,
+                int64_t ldy, const unsigned char* mask, int64_t ldm, double sigma,
+                double* loglik, double* grad, double* dsigma, double* absrow,
+                double* condrow, double* abs_l, double* abs_ds, int64_t* m_obs)
+{
+    return eval_pairs(n, d, x, ldx, y, ldy, mask, ldm, sigma, 1, loglik, grad, dsigma, absrow,
+                      condrow, abs_l, abs_ds, m_obs);
+}
+
+/* The same outputs for the untruncated model (plain normal errors). */
+int oracle_eval_normal(int64_t n, int d, const double* x, int64_t ldx, const double* y,
+                       int64_t ldy, const unsigned char* mask, int64_t ldm, double sigma,
+                       double* loglik, double* grad, double* dsigma, double* absrow,
+                       double* condrow, double* abs_l, double* abs_ds, int64_t* m_obs)
+{
+    return eval_pairs(n, d, x, ldx, y, ldy, mask, ldm, sigma, 0, loglik, grad, dsigma, absrow,
+                      condrow, abs_l, abs_ds, m_obs);
 }
 
 /* ----------------------------------------------------------- leapfrog -- */

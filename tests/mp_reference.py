@@ -67,3 +67,37 @@ def mills(t, dps=50):
     with mp.workdps(dps):
         t = mp.mpf(t)
         return mp.npdf(t) / mp.ncdf(t)
+
+
+def brute_force_normal(x, y, sigma, mask=None, dps=40):
+    """The untruncated model (plain normal errors) from mpmath's normal
+    density: L = sum_{observed i>j} [ln N(y_ij; delta_ij, sigma^2) + ln sqrt(2 pi)]
+    (the same 2*pi constant dropped as in Eq. 2); its gradient and
+    sigma-derivative by mpmath's numerical differentiation of that L."""
+    with mp.workdps(dps):
+        n = len(x)
+        d = len(x[0])
+        pairs = [(i, j, mp.mpf(float(y[i][j]))) for i in range(n) for j in range(i)
+                 if _observed(y, mask, i, j)]
+
+        def loglik(flat, s):
+            tot = mp.mpf(0)
+            for i, j, yij in pairs:
+                delta = mp.sqrt(mp.fsum((flat[i * d + k] - flat[j * d + k]) ** 2
+                                        for k in range(d)))
+                tot += mp.log(mp.npdf(yij, delta, s)) + mp.log(mp.sqrt(2 * mp.pi))
+            return tot
+
+        flat = [mp.mpf(float(v)) for row in x for v in row]
+        s = mp.mpf(sigma)
+        L = loglik(flat, s)
+        G = []
+        for c in range(n * d):
+            def f(v, c=c):
+                g = list(flat)
+                g[c] = v
+                return loglik(g, s)
+            G.append(mp.diff(f, flat[c]))
+        dS = mp.diff(lambda v: loglik(flat, v), s)
+        return dict(loglik=L, grad=[G[i * d:(i + 1) * d] for i in range(n)], dsigma=dS,
+                    m_obs=len(pairs))

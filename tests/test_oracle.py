@@ -373,3 +373,45 @@ def test_row_rounding_scale_bounds_the_row():
     x, y, mask = _rand_problem(40, 2, 0.3, 26, missing=0.1)
     ev = oracle.evaluate(x, y, 0.3, mask)
     assert np.all(ev.condrow >= ev.absrow) and np.all(ev.absrow >= np.abs(ev.grad).max(axis=1))
+
+
+# ------------------------------------------- model without truncation ----
+
+def test_untruncated_against_normal_density():
+    """The ablation model (no truncation to y > 0) against mpmath's normal
+    density, with the gradient and sigma-derivative by numerical
+    differentiation of that density."""
+    rng = np.random.default_rng(77)
+    n, d = 6, 2
+    x = rng.standard_normal((n, d)) * 1.5
+    y = np.abs(rng.standard_normal((n, n))) * 2 + 0.1
+    y = np.tril(y, -1)
+    y = y + y.T
+    mask = np.zeros((n, n), np.uint8)
+    mask[4, 1] = mask[1, 4] = 1
+    y[5, 2] = y[2, 5] = np.nan
+    ref = mpr.brute_force_normal(x, y, 0.8, mask)
+    got = oracle.evaluate(x, y, 0.8, mask, truncated=False)
+    assert got.m_obs == ref["m_obs"] == 13
+    assert abs(got.loglik - float(ref["loglik"])) <= 1e-14 * abs(float(ref["loglik"]))
+    g = np.array([[float(v) for v in row] for row in ref["grad"]])
+    assert np.abs(got.grad - g).max() <= 1e-12 * np.abs(g).max()
+    assert abs(got.dsigma - float(ref["dsigma"])) <= 1e-12 * abs(float(ref["dsigma"]))
+
+
+def test_truncation_term_is_the_only_difference():
+    rng = np.random.default_rng(78)
+    n, d, sigma = 40, 3, 0.9
+    x = rng.standard_normal((n, d)) * 2
+    y = np.abs(rng.standard_normal((n, n))) * 3
+    y = np.tril(y, -1)
+    y = y + y.T
+    a = oracle.evaluate(x, y, sigma)
+    b = oracle.evaluate(x, y, sigma, truncated=False)
+    i, j = np.tril_indices(n, -1)
+    delta = np.sqrt(((x[i] - x[j]) ** 2).sum(1))
+    lnphi = oracle.log_phi(delta / sigma)
+    assert abs((b.loglik - a.loglik) - lnphi.sum()) <= 1e-12 * abs(a.loglik)
+    assert a.m_obs == b.m_obs
+    # the untruncated gradient has no phi/Phi term: its rows sum to zero too
+    assert np.abs(b.grad.sum(0)).max() <= 1e-12 * np.abs(b.grad).max()
