@@ -227,6 +227,16 @@ def main():
     hmc_ms = (time.perf_counter() - t0) * 1e3 / 100
     hmc_acc = chain.accepted.item() / 110
 
+    # the model without truncation (the paper's comparison of the two): the
+    # same sweep with the special functions left out, and the oracle's time
+    # for it on one core
+    abl = {}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        Pu = api.MDSProblem(prob.y, d, prob.mask, dt, dev, order=prob.x, truncated=False)
+        w, sw, _, _ = timed_evals(Pu, xr, sigma, args.steps, args.warmup, events)
+        abl[name] = {"ms_per_step": round(w, 5), "sweep_ms_mean": round(sw, 5)}
+        del Pu
+
     # algorithmic traffic of one sweep: the strict lower triangle of Y once
     # (X in and the partial sums out are under 0.1% of it)
     y_bytes64 = npairs * 8
@@ -292,6 +302,7 @@ def main():
             "loglik_rel_diff_vs_fp64": abs(L32.item() - L64.item()) / abs(L64.item()),
         },
         "original_labelling": plain,
+        "untruncated_model": abl,
         "leapfrog": {"steps": 20, "step_size": 1e-3, "ms_per_trajectory": round(traj_ms, 4),
                      "gradient_evals": 20},
         "hmc": {"transitions": 100, "leapfrog_steps": 20, "step_size": 1e-3,
@@ -315,6 +326,14 @@ def main():
                       "FP64 oracle (one thread)",
             "s_per_eval": round(cpu_s, 4),
         }
+        t0 = time.perf_counter()
+        k_u = max(1, k // 2)
+        for _ in range(k_u):
+            oracle.evaluate(prob.x, prob.y, sigma, prob.mask, truncated=False)
+        cpu_u = (time.perf_counter() - t0) / k_u
+        out["untruncated_model"]["oracle_s_per_eval"] = round(cpu_u, 4)
+        out["untruncated_model"]["gpu_over_oracle"] = round(cpu_u / (abl["fp64"]["ms_per_step"] * 1e-3), 1)
+        out["untruncated_model"]["truncated_gpu_over_oracle"] = round(cpu_s / (wall64 * 1e-3), 1)
         out["parity"] = {
             "loglik_rel_err_fp64": abs(L64.item() - ev.loglik) / abs(ev.loglik),
             "grad_max_row_err_over_B_fp64": float(np.max(

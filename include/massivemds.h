@@ -80,6 +80,14 @@ enum mds_status {
 /* element types */
 enum mds_dtype { MDS_F64 = 0, MDS_F32 = 1 };
 
+/* Model flag, OR-ed into the y_dtype argument of the evaluation calls
+ * (mds_workspace_bytes, mds_resolve_tiling, mds_loglik, mds_gradient,
+ * mds_leapfrog, mds_hmc_*, mds_batch_*): evaluate the model WITHOUT the
+ * truncation to y > 0 -- plain normal errors, the ln Phi term of Eq. (2) and
+ * the phi/Phi term of Eq. (9) left out -- the comparison the paper draws in
+ * its scaling appendix. */
+#define MDS_UNTRUNCATED 0x100
+
 #define MDS_MAX_DIM 8
 /* largest N accepted: tile and row indices are 32-bit on the device */
 #define MDS_MAX_N ((int64_t)1 << 30)

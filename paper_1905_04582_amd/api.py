@@ -21,6 +21,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MDS_LIB_PATH", os.path.join(_PKG, "libmassivemds.so"))
 
 MDS_OK = 0
+MDS_UNTRUNCATED = 0x100      # model flag: no truncation to y > 0 (plain normal errors)
 MDS_ERR_NOT_SYMMETRIC = -5
 MDS_F64 = 0
 MDS_F32 = 1
@@ -135,6 +136,10 @@ def _ptr(t):
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ycode(y, truncated: bool) -> int:
+    return _dtype_code(y.dtype) | (0 if truncated else MDS_UNTRUNCATED)
 
 
 def _dtype_code(dt: torch.dtype) -> int:
@@ -269,13 +274,14 @@ def mds_permute_rows(src: torch.Tensor, perm: torch.Tensor, inverse: bool = Fals
     return out
 
 
-def mds_loglik(x, y, sigma, workspace, out=None, tile_rows=0, tile_waves=0, stream=None):
+def mds_loglik(x, y, sigma, workspace, out=None, tile_rows=0, tile_waves=0, stream=None,
+               truncated=True):
     _check_mat(x, "x")
     _check_mat(y, "y", y.dtype)
     n, d = x.shape
     sig = _dev_scalar(sigma, x.device)
     out = torch.empty((), dtype=torch.float64, device=x.device) if out is None else out
-    _check(lib().mds_loglik(n, d, _ptr(x), _ld(x), _ptr(y), _dtype_code(y.dtype),
+    _check(lib().mds_loglik(n, d, _ptr(x), _ld(x), _ptr(y), _ycode(y, truncated),
                             _ld(y), _ptr(sig), _ptr(out), _ptr(workspace),
                             workspace.numel(), tile_rows, tile_waves, _stream(stream)),
            "mds_loglik")
@@ -284,7 +290,7 @@ def mds_loglik(x, y, sigma, workspace, out=None, tile_rows=0, tile_waves=0, stre
 
 def mds_gradient(x, y, sigma, workspace, scale=None, grad=None, loglik=None, dsigma=None,
                  want_loglik=True, want_dsigma=True, dlogsigma=None, tile_rows=0, tile_waves=0,
-                 stream=None):
+                 stream=None, truncated=True):
     """Returns (grad N x D, loglik scalar or None, dsigma scalar or None); an
     optional `dlogsigma` device scalar receives scale * sigma * dL/dsigma."""
     _check_mat(x, "x")
@@ -299,7 +305,7 @@ def mds_gradient(x, y, sigma, workspace, scale=None, grad=None, loglik=None, dsi
         loglik = torch.empty((), dtype=torch.float64, device=dev)
     if want_dsigma and dsigma is None:
         dsigma = torch.empty((), dtype=torch.float64, device=dev)
-    _check(lib().mds_gradient(n, d, _ptr(x), _ld(x), _ptr(y), _dtype_code(y.dtype),
+    _check(lib().mds_gradient(n, d, _ptr(x), _ld(x), _ptr(y), _ycode(y, truncated),
                               _ld(y), _ptr(sig), _ptr(sc), _ptr(grad), _ld(grad),
                               _ptr(loglik), _ptr(dsigma), _ptr(dlogsigma), _ptr(workspace),
                               workspace.numel(), tile_rows, tile_waves, _stream(stream)),
@@ -309,7 +315,7 @@ def mds_gradient(x, y, sigma, workspace, scale=None, grad=None, loglik=None, dsi
 
 def mds_leapfrog(x, p, y, sigma, step, n_steps, workspace, grad_io, loglik_io,
                  cache_valid=False, inv_mass=None, prior=None, energy_start=None,
-                 energy_end=None, tile_rows=0, tile_waves=0, stream=None):
+                 energy_end=None, tile_rows=0, tile_waves=0, stream=None, truncated=True):
     """In-place leapfrog trajectory on (x, p); grad_io/loglik_io are the
     gradient/log-likelihood cache at x (read if cache_valid, always written)."""
     for t, nm in ((x, "x"), (p, "p"), (grad_io, "grad_io")):
@@ -326,7 +332,7 @@ def mds_leapfrog(x, p, y, sigma, step, n_steps, workspace, grad_io, loglik_io,
     eps = _dev_scalar(step, dev)
     lam = None if prior is None else _dev_scalar(prior, dev)
     _check(lib().mds_leapfrog(n, d, _ptr(x), _ld(x), _ptr(p), _ld(p), _ptr(y),
-                              _dtype_code(y.dtype), _ld(y), _ptr(sig), _ptr(inv_mass),
+                              _ycode(y, truncated), _ld(y), _ptr(sig), _ptr(inv_mass),
                               _ptr(eps), _ptr(lam), int(n_steps), _ptr(grad_io), _ptr(loglik_io),
                               1 if cache_valid else 0, _ptr(energy_start), _ptr(energy_end),
                               _ptr(workspace), workspace.numel(), tile_rows, tile_waves,
@@ -365,7 +371,7 @@ def mds_hmc_momentum(n: int, d: int, seed: int, iteration: torch.Tensor, inv_mas
 
 def mds_hmc_step(x, p, y, sigma, step, n_steps, seed, iteration, workspace, grad_io, loglik_io,
                  cache_valid=False, inv_mass=None, prior=None, stats=None, accepted_total=None,
-                 tile_rows=0, tile_waves=0, stream=None):
+                 tile_rows=0, tile_waves=0, stream=None, truncated=True):
     """One HMC transition of the chain at x (in place); see include/massivemds.h."""
     for t, nm in ((x, "x"), (p, "p"), (grad_io, "grad_io")):
         _check_mat(t, nm)
@@ -385,7 +391,7 @@ def mds_hmc_step(x, p, y, sigma, step, n_steps, seed, iteration, workspace, grad
     sig = _dev_scalar(sigma, dev)
     eps = _dev_scalar(step, dev)
     lam = None if prior is None else _dev_scalar(prior, dev)
-    _check(lib().mds_hmc_step(n, d, _ptr(x), _ld(x), _ptr(y), _dtype_code(y.dtype), _ld(y),
+    _check(lib().mds_hmc_step(n, d, _ptr(x), _ld(x), _ptr(y), _ycode(y, truncated), _ld(y),
                               _ptr(sig), _ptr(inv_mass), _ptr(eps), _ptr(lam), int(n_steps),
                               int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(iteration), _ptr(p), _ld(p),
                               _ptr(grad_io), _ptr(loglik_io), 1 if cache_valid else 0,
@@ -417,6 +423,8 @@ class MDSProblem:
     y      N x N (numpy or torch, any device), symmetric
     mask   optional N x N, non-zero = missing
     dtype  torch.float64 (FP64 form) or torch.float32 (FP32 form)
+    truncated  False: the model without the truncation to y > 0 (plain
+           normal errors; the paper's comparison of the two)
     order  optional N x D locations (e.g. the chain's starting X): the problem
            is stored relabelled in their spatial order (``perm``), and every
            X, P and gradient passed to its methods is in that labelling --
@@ -425,7 +433,7 @@ class MDSProblem:
 
     def __init__(self, y, d: int, mask=None, dtype=torch.float64, device="cuda",
                  tile_rows: int = 0, tile_waves: int = 0, autotuned: bool = False, order=None,
-                 check_symmetric: bool = False):
+                 check_symmetric: bool = False, truncated: bool = True):
         y = torch.as_tensor(y)
         n = y.shape[0]
         if autotuned and tile_rows == 0 and tile_waves == 0:
@@ -437,6 +445,7 @@ class MDSProblem:
         if mask is not None:
             m = (torch.as_tensor(mask) != 0).to(device=device, dtype=torch.uint8).contiguous()
         self.n, self.d, self.dtype, self.device = n, int(d), dtype, torch.device(device)
+        self.truncated = bool(truncated)
         self.perm = None
         if order is not None:
             xo = torch.as_tensor(order).to(device=device, dtype=torch.float64).contiguous()
@@ -474,7 +483,7 @@ class MDSProblem:
             self._hmc_ws = alloc_workspace(nb, self.device)
         mds_hmc_step(x, p, self.y, sigma, step, n_steps, seed, iteration, self._hmc_ws, grad_io,
                      loglik_io, cache_valid, inv_mass, prior, stats, accepted_total,
-                     self.tile_rows, self.tile_waves, stream)
+                     self.tile_rows, self.tile_waves, stream, self.truncated)
 
     def set_tiling(self, tile_rows: int, tile_waves: int):
         nb = mds_workspace_bytes(self.n, self.d, _dtype_code(self.dtype), tile_rows, tile_waves)
@@ -484,19 +493,19 @@ class MDSProblem:
 
     def loglik(self, x, sigma, out=None, stream=None):
         return mds_loglik(x, self.y, sigma, self.workspace, out, self.tile_rows,
-                          self.tile_waves, stream)
+                          self.tile_waves, stream, self.truncated)
 
     def gradient(self, x, sigma, scale=None, grad=None, loglik=None, dsigma=None,
                  want_loglik=True, want_dsigma=True, dlogsigma=None, stream=None):
         return mds_gradient(x, self.y, sigma, self.workspace, scale, grad, loglik, dsigma,
                             want_loglik, want_dsigma, dlogsigma, tile_rows=self.tile_rows,
-                            tile_waves=self.tile_waves, stream=stream)
+                            tile_waves=self.tile_waves, stream=stream, truncated=self.truncated)
 
     def leapfrog(self, x, p, sigma, step, n_steps, grad_io, loglik_io, cache_valid=False,
                  inv_mass=None, prior=None, energy_start=None, energy_end=None, stream=None):
         mds_leapfrog(x, p, self.y, sigma, step, n_steps, self.workspace, grad_io, loglik_io,
                      cache_valid, inv_mass, prior, energy_start, energy_end, self.tile_rows,
-                     self.tile_waves, stream)
+                     self.tile_waves, stream, self.truncated)
 
 
 class MDSBatch:
@@ -513,7 +522,7 @@ class MDSBatch:
     """
 
     def __init__(self, problems, dtype=torch.float32, device="cuda", tile_waves: int = 0,
-                 stream=None, autotuned: bool = False):
+                 stream=None, autotuned: bool = False, truncated: bool = True):
         self.device = torch.device(device)
         if autotuned:
             problems, tile_waves = _autotuned_batch(problems, dtype, device, tile_waves)
@@ -554,7 +563,7 @@ class MDSBatch:
             q.dsigma = self.dsigma.data_ptr() + 8 * k
             q.dlogsigma = self.dlogsigma.data_ptr() + 8 * k
         self._descs = descs
-        code = _dtype_code(dtype)
+        code = _dtype_code(dtype) | (0 if truncated else MDS_UNTRUNCATED)
         nb = ctypes.c_size_t(0)
         _check(lib().mds_batch_workspace_bytes(descs, count, code, tile_waves, ctypes.byref(nb)),
                "mds_batch_workspace_bytes")

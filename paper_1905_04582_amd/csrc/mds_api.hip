@@ -65,6 +65,18 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 size_t dtype_size(int dt) { return dt == MDS_F64 ? 8 : 4; }
 
+// Splits a y_dtype argument into the element type (left in y_dtype) and the
+// model flags: *truncated = 0 for MDS_UNTRUNCATED.
+int split_ytype(int32_t& y_dtype, int* truncated)
+{
+    const int32_t flags = y_dtype & ~0xFF;
+    if (flags & ~MDS_UNTRUNCATED)
+        return fail(MDS_ERR_UNSUPPORTED, "unknown model flags 0x%x in y_dtype", (unsigned)flags);
+    *truncated = (flags & MDS_UNTRUNCATED) ? 0 : 1;
+    y_dtype &= 0xFF;
+    return MDS_OK;
+}
+
 // Largest LDS a sweep work-group may use (row sums of all its waves).
 constexpr size_t kMaxSweepLds = 64 * 1024;
 
@@ -160,7 +172,7 @@ hipError_t timed_sweep(int y_dtype, int d, bool grad, const Tiling& t, const Swe
 
 SweepArgs sweep_args(const Tiling& t, const WorkspaceLayout& lay, void* ws, int64_t n,
                      const double* x, int64_t ldx, const void* y, int64_t ldy,
-                     const double* sigma)
+                     const double* sigma, int truncated)
 {
     char* base = static_cast<char*>(ws);
     SweepArgs a;
@@ -170,6 +182,7 @@ SweepArgs sweep_args(const Tiling& t, const WorkspaceLayout& lay, void* ws, int6
     a.y = y;
     a.ldy = ldy;
     a.sigma = sigma;
+    a.truncated = truncated;
     a.br = t.br;
     a.cw = t.cw;
     a.nrb = t.nrb;
@@ -220,6 +233,12 @@ int mds_version(void) { return 1 * 10000 + 0 * 100 + 0; }
 int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
                         int32_t tile_waves, size_t* bytes)
 {
+    int trunc = 1;
+    {
+        const int sst = split_ytype(y_dtype, &trunc);
+        if (sst) return sst;
+    }
+    (void)trunc;
     if (!bytes) return fail(MDS_ERR_INVALID_ARGUMENT, "bytes is NULL");
     if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
     if (d < 1 || d > MDS_MAX_DIM) return fail(MDS_ERR_UNSUPPORTED, "d=%d unsupported", d);
@@ -235,6 +254,12 @@ int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows
 int mds_resolve_tiling(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
                        int32_t tile_waves, int32_t* rows_out, int32_t* waves_out)
 {
+    int trunc = 1;
+    {
+        const int sst = split_ytype(y_dtype, &trunc);
+        if (sst) return sst;
+    }
+    (void)trunc;
     if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
     if (d < 1 || d > MDS_MAX_DIM)
         return fail(MDS_ERR_UNSUPPORTED, "d=%d: must be 1..%d", d, MDS_MAX_DIM);
@@ -339,6 +364,11 @@ int mds_loglik(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y
                void* workspace, size_t workspace_bytes, int32_t tile_rows, int32_t tile_waves,
                hipStream_t stream)
 {
+    int trunc = 1;
+    {
+        const int sst = split_ytype(y_dtype, &trunc);
+        if (sst) return sst;
+    }
     int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
     if (st) return st;
     if (!loglik_dev || !aligned(loglik_dev, 8))
@@ -348,7 +378,7 @@ int mds_loglik(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y
     WorkspaceLayout lay;
     if ((st = check_workspace(t, d, workspace, workspace_bytes, &lay))) return st;
 
-    SweepArgs sa = sweep_args(t, lay, workspace, n, x, ldx, y, ldy, sigma_dev);
+    SweepArgs sa = sweep_args(t, lay, workspace, n, x, ldx, y, ldy, sigma_dev, trunc);
     hipError_t e = timed_sweep(y_dtype, d, false, t, sa, stream);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     FinalizeArgs fa = finalize_args(t, sa);
@@ -364,6 +394,11 @@ int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void*
                  double* dlogsigma_dev, void* workspace, size_t workspace_bytes,
                  int32_t tile_rows, int32_t tile_waves, hipStream_t stream)
 {
+    int trunc = 1;
+    {
+        const int sst = split_ytype(y_dtype, &trunc);
+        if (sst) return sst;
+    }
     int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
     if (st) return st;
     if (n > 0 && !grad) return fail(MDS_ERR_INVALID_ARGUMENT, "grad is NULL");
@@ -376,7 +411,7 @@ int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void*
     WorkspaceLayout lay;
     if ((st = check_workspace(t, d, workspace, workspace_bytes, &lay))) return st;
 
-    SweepArgs sa = sweep_args(t, lay, workspace, n, x, ldx, y, ldy, sigma_dev);
+    SweepArgs sa = sweep_args(t, lay, workspace, n, x, ldx, y, ldy, sigma_dev, trunc);
     hipError_t e = timed_sweep(y_dtype, d, true, t, sa, stream);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     FinalizeArgs fa = finalize_args(t, sa);
@@ -399,6 +434,11 @@ int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_
                  size_t workspace_bytes, int32_t tile_rows, int32_t tile_waves,
                  hipStream_t stream)
 {
+    int trunc = 1;
+    {
+        const int sst = split_ytype(y_dtype, &trunc);
+        if (sst) return sst;
+    }
     int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
     if (st) return st;
     if (n > 0 && (!p || !grad_io)) return fail(MDS_ERR_INVALID_ARGUMENT, "p or grad_io is NULL");
@@ -416,7 +456,7 @@ int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_
     WorkspaceLayout lay;
     if ((st = check_workspace(t, d, workspace, workspace_bytes, &lay))) return st;
 
-    SweepArgs sa = sweep_args(t, lay, workspace, n, x, ldx, y, ldy, sigma_dev);
+    SweepArgs sa = sweep_args(t, lay, workspace, n, x, ldx, y, ldy, sigma_dev, trunc);
     hipError_t e;
 
     // grad log pi and L at a point: sweep + finalize, optionally followed by
@@ -488,6 +528,12 @@ static HmcLayout hmc_layout(const WorkspaceLayout& lay, int64_t n, int d)
 int mds_hmc_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
                             int32_t tile_waves, size_t* bytes)
 {
+    int trunc = 1;
+    {
+        const int sst = split_ytype(y_dtype, &trunc);
+        if (sst) return sst;
+    }
+    (void)trunc;
     if (!bytes) return fail(MDS_ERR_INVALID_ARGUMENT, "bytes is NULL");
     if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
     if (d < 1 || d > MDS_MAX_DIM)
@@ -526,6 +572,13 @@ int mds_hmc_step(int64_t n, int32_t d, double* x, int64_t ldx, const void* y, in
                  int64_t* accepted_total_dev, void* workspace, size_t workspace_bytes,
                  int32_t tile_rows, int32_t tile_waves, hipStream_t stream)
 {
+    const int32_t y_arg = y_dtype;  // with its model flags, for the leapfrog calls
+    int trunc = 1;
+    {
+        const int sst = split_ytype(y_dtype, &trunc);
+        if (sst) return sst;
+    }
+    (void)trunc;
     int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
     if (st) return st;
     if (!iteration_dev || !aligned(iteration_dev, 8))
@@ -549,7 +602,7 @@ int mds_hmc_step(int64_t n, int32_t d, double* x, int64_t ldx, const void* y, in
 
     // grad log pi and L at x, when the caller has no cached values
     if (!cache_valid) {
-        st = mds_leapfrog(n, d, x, ldx, p, ldp, y, y_dtype, ldy, sigma_dev, inv_mass, step_dev,
+        st = mds_leapfrog(n, d, x, ldx, p, ldp, y, y_arg, ldy, sigma_dev, inv_mass, step_dev,
                           prior_dev, 0, grad_io, loglik_io, 0, nullptr, nullptr, workspace,
                           lay.total, tile_rows, tile_waves, stream);
         if (st) return st;
@@ -557,7 +610,7 @@ int mds_hmc_step(int64_t n, int32_t d, double* x, int64_t ldx, const void* y, in
     hipError_t e = launch_hmc_begin(n, d, inv_mass, seed, iteration_dev, p, ldp, x, ldx, grad_io,
                                     loglik_io, x_save, g_save, scal, stream);
     if (e != hipSuccess) return hip_fail(e, "momentum launch");
-    st = mds_leapfrog(n, d, x, ldx, p, ldp, y, y_dtype, ldy, sigma_dev, inv_mass, step_dev,
+    st = mds_leapfrog(n, d, x, ldx, p, ldp, y, y_arg, ldy, sigma_dev, inv_mass, step_dev,
                       prior_dev, n_steps, grad_io, loglik_io, 1, scal + 1, scal + 2, workspace,
                       lay.total, tile_rows, tile_waves, stream);
     if (st) return st;
@@ -650,6 +703,12 @@ int mds_batch_workspace_bytes(const mds_problem_desc* descs, int32_t count, int3
                               int32_t tile_waves, size_t* bytes)
 {
     if (!bytes) return fail(MDS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    int trunc = 1;
+    {
+        const int sst = split_ytype(y_dtype, &trunc);
+        if (sst) return sst;
+    }
+    (void)trunc;
     BatchLayout L;
     size_t lds;
     int st = batch_layout(descs, count, y_dtype, tile_waves, &L, &lds);
@@ -663,6 +722,11 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
                    mds_batch_plan* plan, hipStream_t stream)
 {
     if (!plan) return fail(MDS_ERR_INVALID_ARGUMENT, "plan is NULL");
+    int trunc = 1;
+    {
+        const int sst = split_ytype(y_dtype, &trunc);
+        if (sst) return sst;
+    }
     BatchLayout L;
     size_t max_lds;
     int st = batch_layout(descs, count, y_dtype, tile_waves, &L, &max_lds);
@@ -686,7 +750,7 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
         const Tiling& t = L.tilings[k];
         BatchProblem P = {};
         P.sweep = sweep_args(t, workspace_layout(t, q.d), base + L.ws[k], q.n, q.x, q.ldx, q.y,
-                             q.ldy, q.sigma);
+                             q.ldy, q.sigma, trunc);
         P.d = q.d;
         P.tile_base = tiles;
         P.ntiles = t.ntiles;

@@ -133,6 +133,7 @@ struct SweepArgs {
     double* colpart;
     double* tscal;
     uint32_t* tcount;
+    int truncated;  // 0: the model without the truncation terms (ln Phi = m = 0)
 };
 
 // What the finalize kernel does with the summed gradient of one element.

@@ -340,7 +340,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             geom(q, ya, ga);
             count_ok(ga);
             T la = T(0), ma = T(0);
-            if (__builtin_amdgcn_ballot_w64(needs_tail(ga))) {
+            if (a.truncated && __builtin_amdgcn_ballot_w64(needs_tail(ga))) {
                 trunc_terms<T>(ga.t, la, ma);
                 la = ga.ok ? la : T(0);
                 ma = ga.ok ? ma : T(0);
@@ -367,7 +367,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 count_ok(gd);
                 T la = T(0), ma = T(0), lb = T(0), mb = T(0);
                 T lc = T(0), mc = T(0), ld = T(0), md = T(0);
-                if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb) ||
+                if (a.truncated && __builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb) ||
                                                 needs_tail(gc) || needs_tail(gd))) {
                     trunc_terms2<T>(ga.t, gb.t, la, ma, lb, mb);
                     trunc_terms2<T>(gc.t, gd.t, lc, mc, ld, md);
@@ -398,7 +398,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 count_ok(ga);
                 count_ok(gb);
                 T la = T(0), ma = T(0), lb = T(0), mb = T(0);
-                if (__builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb))) {
+                if (a.truncated && __builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb))) {
                     trunc_terms2<T>(ga.t, gb.t, la, ma, lb, mb);
                     la = ga.ok ? la : T(0);
                     ma = ga.ok ? ma : T(0);

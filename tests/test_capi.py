@@ -186,6 +186,19 @@ def test_hmc_rejects():
     assert L.mds_hmc_step(*bad) == ERR_ARG
 
 
+def test_model_flags():
+    L = api.lib()
+    nb = ctypes.c_size_t()
+    assert L.mds_workspace_bytes(1000, 2, 0 | api.MDS_UNTRUNCATED, 0, 0, ctypes.byref(nb)) == 0
+    assert L.mds_workspace_bytes(1000, 2, 1 | api.MDS_UNTRUNCATED, 0, 0, ctypes.byref(nb)) == 0
+    assert L.mds_workspace_bytes(1000, 2, 0x200, 0, 0, ctypes.byref(nb)) == ERR_UNSUP
+    assert L.mds_workspace_bytes(1000, 2, 2 | api.MDS_UNTRUNCATED, 0, 0,
+                                 ctypes.byref(nb)) == ERR_UNSUP
+    # the flag does not change the tiling or the workspace
+    assert api.mds_resolve_tiling(5392, 2, api.MDS_F64 | api.MDS_UNTRUNCATED) == \
+        api.mds_resolve_tiling(5392, 2, api.MDS_F64)
+
+
 def test_resolve_tiling():
     L = api.lib()
     f64, f32 = api.MDS_F64, api.MDS_F32

@@ -415,3 +415,56 @@ def test_leapfrog_paper_scale_parity():
     assert abs(L.item() - ref.loglik_end) <= 1e-11 * abs(ref.loglik_end)
     assert abs(e0.item() - ref.energy_start) <= 1e-11 * abs(ref.energy_start)
     assert abs(e1.item() - ref.energy_end) <= 1e-11 * abs(ref.energy_end)
+
+
+# ---------------------------------------- the model without truncation ----
+
+@pytest.mark.parametrize("d", [1, 2, 3, 6])
+def test_untruncated_fp64_ragged(d):
+    x, y, mask, sigma = _rand(333, d, seed=900 + d)
+    ref = oracle.evaluate(x, y, sigma, mask, truncated=False)
+    P = api.MDSProblem(y, d, mask, torch.float64, DEV, truncated=False)
+    xt = torch.as_tensor(x, dtype=torch.float64, device=DEV)
+    g, L, ds = P.gradient(xt, sigma)
+    L2 = P.loglik(xt, sigma)
+    torch.cuda.synchronize()
+    got = dict(grad=g.cpu().numpy(), loglik=L.item(), dsigma=ds.item(), loglik_only=L2.item(),
+               m_obs=int(P.m_obs.item()))
+    check64(got, ref, f"untruncated d={d}")
+
+
+@pytest.mark.parametrize("ordered", [False, True])
+def test_untruncated_paper_scale(ordered):
+    p = preset("paper_fp64")
+    ref = oracle.evaluate(p.x, p.y, p.sigma, p.mask, truncated=False)
+    P = api.MDSProblem(p.y, p.d, p.mask, torch.float64, DEV, order=p.x if ordered else None,
+                       truncated=False)
+    xr = P.relabel(p.x)
+    g, L, ds = P.gradient(xr, p.sigma)
+    L2 = P.loglik(xr, p.sigma)
+    got = dict(grad=P.unlabel(g).cpu().numpy(), loglik=L.item(), dsigma=ds.item(),
+               loglik_only=L2.item(), m_obs=int(P.m_obs.item()))
+    check64(got, ref, f"untruncated paper scale ordered={ordered}")
+    # FP32 form of the same model
+    P32 = api.MDSProblem(p.y, p.d, p.mask, torch.float32, DEV, truncated=False)
+    ref32 = oracle.evaluate(p.x, p.y.astype(np.float32).astype(np.float64), p.sigma, p.mask,
+                            truncated=False)
+    L32 = P32.loglik(torch.as_tensor(p.x, device=DEV), p.sigma).item()
+    assert abs(L32 - ref32.loglik) <= TOL32_LOGLIK * abs(ref32.loglik)
+
+
+def test_untruncated_batch_vs_oracle():
+    probs = [synth.make_problem(n, d, 0.6, seed=n, missing=0.1) for n, d in ((700, 2), (333, 4))]
+    B = api.MDSBatch([{"y": q.y, "d": q.d, "mask": q.mask} for q in probs], torch.float64, DEV,
+                     truncated=False)
+    for k, q in enumerate(probs):
+        B.set_x(k, q.x)
+        B.sigma[k] = q.sigma
+    B.eval()
+    torch.cuda.synchronize()
+    for k, q in enumerate(probs):
+        ref = oracle.evaluate(q.x, q.y, q.sigma, q.mask, truncated=False)
+        got = dict(grad=B.grad[k].cpu().numpy(), loglik=B.loglik[k].item(),
+                   dsigma=B.dsigma[k].item(), loglik_only=B.loglik[k].item(),
+                   m_obs=ref.m_obs)
+        check64(got, ref, f"untruncated batch problem {k}")
