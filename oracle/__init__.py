@@ -60,6 +60,9 @@ def _load():
     lib.oracle_eval.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
                                 ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
                                 _dp, _dp, _dp, _dp, _dp, _dp, _dp, _i64p]
+    lib.oracle_lpd.restype = ctypes.c_int
+    lib.oracle_lpd.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp,
+                               ctypes.c_int64, _u8p, ctypes.c_int64, _dp, _i64p]
     lib.oracle_eval_normal.restype = ctypes.c_int
     lib.oracle_eval_normal.argtypes = lib.oracle_eval.argtypes
     lib.oracle_leapfrog.restype = ctypes.c_int
@@ -295,3 +298,25 @@ def hmc_step(x, y, sigma: float, eps: float, n_steps: int, seed: int, iteration:
         raise ValueError("oracle_hmc_step rejected its arguments")
     return HMCStep(x, p, g, out[0], out[1], out[2], out[3], bool(acc.value))
 
+
+def lpd(xs, sigmas, y, heldout, mask=None):
+    """Log pointwise predictive density of the held-out pairs (heldout != 0,
+    observed: mask zero and y not NaN) over the posterior draws xs (S x N x D,
+    or one N x D state) and sigmas (S values); returns (lpd, pairs)."""
+    lib = _load()
+    xs = np.ascontiguousarray(xs, dtype=np.float64)
+    if xs.ndim == 2:
+        xs = xs[None]
+    s_draws, n, d = xs.shape
+    sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigmas, dtype=np.float64), (s_draws,)))
+    y = _as_y(y)
+    keep_out = np.asarray(heldout) == 0
+    m = keep_out if mask is None else (keep_out | (np.asarray(mask) != 0))
+    m = np.ascontiguousarray(m, dtype=np.uint8)
+    out = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    rc = lib.oracle_lpd(n, d, s_draws, _ptr(xs), _ptr(sig), _ptr(y), y.shape[1], _ptr(m, _u8p), n,
+                        ctypes.byref(out), ctypes.byref(cnt))
+    if rc != 0:
+        raise ValueError("oracle_lpd rejected its arguments")
+    return out.value, int(cnt.value)

@@ -263,6 +263,62 @@ int oracle_eval_normal(int64_t n, int d, const double* x, int64_t ldx, const dou
                       condrow, abs_l, abs_ds, m_obs);
 }
 
+/*
+ * Log pointwise predictive density of held-out pairs over posterior draws
+ * (the model-selection subsection of Section 2: for each held-out pair, the
+ * log of the Monte Carlo average over the S draws of the pair's predictive
+ * density, summed over the held-out pairs).  The pair's density is the
+ * truncated normal of Section 2.1 with its full normalising constant,
+ *     ln p(y | delta, sigma) = -ln(sqrt(2 pi) sigma) - (y - delta)^2/(2 sigma^2)
+ *                              - ln Phi(delta / sigma).
+ *   xs      S draws of X, each n*d contiguous (row-major), one after another
+ *   sigmas  S draws of sigma
+ *   mask    every pair that is NOT held out (non-zero), as in oracle_eval
+ * Writes the sum to *lpd and the number of held-out pairs to *m.  For S = 1
+ * the value is the sum of the log densities at that one state.
+ */
+int oracle_lpd(int64_t n, int d, int64_t n_draws, const double* xs, const double* sigmas,
+               const double* y, int64_t ldy, const unsigned char* mask, int64_t ldm,
+               double* lpd, int64_t* m)
+{
+    if (n < 0 || d < 1 || n_draws < 1 || (n > 0 && ldy < n)) return -1;
+    if (mask && n > 0 && ldm < n) return -1;
+    double* l = (double*)malloc(sizeof(double) * (size_t)n_draws);
+    if (!l) return -1;
+    nsum total = {0, 0};
+    int64_t cnt = 0;
+    for (int64_t i = 1; i < n; ++i) {
+        for (int64_t j = 0; j < i; ++j) {
+            if (!pair_observed(i, j, y, ldy, mask, ldm)) continue;
+            double lmax = -INFINITY;
+            for (int64_t s = 0; s < n_draws; ++s) {
+                const double* x = xs + s * n * d;
+                const double sigma = sigmas[s];
+                double dd = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    const double diff = x[i * d + k] - x[j * d + k];
+                    dd += diff * diff;
+                }
+                const double delta = sqrt(dd);
+                const double z = (y[i * ldy + j] - delta) / sigma;
+                const double log_norm = -ORACLE_LN_SQRT_2PI - log(sigma) - 0.5 * z * z;
+                const double log_trunc = log1p(-0.5 * erfc(delta / sigma / ORACLE_SQRT2));
+                l[s] = log_norm - log_trunc;
+                if (l[s] > lmax) lmax = l[s];
+            }
+            /* log of the average of exp(l_s), shifted by the largest term */
+            nsum acc = {0, 0};
+            for (int64_t s = 0; s < n_draws; ++s) nsum_add(&acc, exp(l[s] - lmax));
+            nsum_add(&total, lmax + log(nsum_get(&acc)) - log((double)n_draws));
+            ++cnt;
+        }
+    }
+    free(l);
+    if (lpd) *lpd = nsum_get(&total);
+    if (m) *m = cnt;
+    return 0;
+}
+
 /* ----------------------------------------------------------- leapfrog -- */
 
 /* gradient of the HMC target log pi(x) = L(x) - (lambda/2)||x||^2 */

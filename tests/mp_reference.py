@@ -101,3 +101,27 @@ def brute_force_normal(x, y, sigma, mask=None, dps=40):
         dS = mp.diff(lambda v: loglik(flat, v), s)
         return dict(loglik=L, grad=[G[i * d:(i + 1) * d] for i in range(n)], dsigma=dS,
                     m_obs=len(pairs))
+
+
+def brute_force_lpd(xs, sigmas, y, heldout, mask=None, dps=40):
+    """Log pointwise predictive density from mpmath's normal density and
+    normal CDF: for each held-out observed pair, ln of the average over the
+    draws of npdf(y; delta, sigma) / ncdf(delta / sigma)."""
+    with mp.workdps(dps):
+        n = len(xs[0])
+        d = len(xs[0][0])
+        tot = mp.mpf(0)
+        cnt = 0
+        for i in range(n):
+            for j in range(i):
+                if not heldout[i][j] or not _observed(y, mask, i, j):
+                    continue
+                dens = []
+                for x, s in zip(xs, sigmas):
+                    s = mp.mpf(float(s))
+                    delta = mp.sqrt(mp.fsum((mp.mpf(float(x[i][k])) - mp.mpf(float(x[j][k]))) ** 2
+                                            for k in range(d)))
+                    dens.append(mp.npdf(mp.mpf(float(y[i][j])), delta, s) / mp.ncdf(delta / s))
+                tot += mp.log(mp.fsum(dens) / len(dens))
+                cnt += 1
+        return tot, cnt

@@ -415,3 +415,53 @@ def test_truncation_term_is_the_only_difference():
     assert a.m_obs == b.m_obs
     # the untruncated gradient has no phi/Phi term: its rows sum to zero too
     assert np.abs(b.grad.sum(0)).max() <= 1e-12 * np.abs(b.grad).max()
+
+
+# --------------------------------------------- held-out predictive density ----
+
+def _heldout_case(seed, n=7, d=2, frac=0.4):
+    rng = np.random.default_rng(seed)
+    y = np.abs(rng.standard_normal((n, n))) * 2 + 0.2
+    y = np.tril(y, -1)
+    y = y + y.T
+    h = np.tril(rng.random((n, n)) < frac, -1)
+    heldout = (h | h.T).astype(np.uint8)
+    mask = np.zeros((n, n), np.uint8)
+    i, j = np.nonzero(np.tril(heldout, -1))
+    mask[i[0], j[0]] = mask[j[0], i[0]] = 1          # one held-out pair is missing
+    return rng, y, heldout, mask
+
+
+def test_lpd_against_mpmath_density():
+    rng, y, heldout, mask = _heldout_case(5)
+    xs = rng.standard_normal((4, 7, 2)) * 1.5
+    sig = rng.uniform(0.5, 1.2, 4)
+    ref, cnt = mpr.brute_force_lpd(xs, sig, y, heldout, mask)
+    got, m = oracle.lpd(xs, sig, y, heldout, mask)
+    assert m == cnt == int(np.tril(heldout, -1).sum()) - 1
+    assert abs(got - float(ref)) <= 1e-13 * abs(float(ref))
+
+
+def test_lpd_one_draw_is_the_likelihood_with_constant():
+    """With one draw the lpd is the held-out problem's log-likelihood of
+    Eq. (2) plus the 2 pi constant that Eq. (2) drops."""
+    rng, y, heldout, mask = _heldout_case(6, n=30, d=3, frac=0.3)
+    x = rng.standard_normal((30, 3)) * 2
+    got, m = oracle.lpd(x, 0.8, y, heldout, mask)
+    not_held = ((heldout == 0) | (mask != 0)).astype(np.uint8)
+    ev = oracle.evaluate(x, y, 0.8, not_held)
+    assert m == ev.m_obs
+    assert abs(got - (ev.loglik - 0.5 * m * math.log(2 * math.pi))) <= 1e-12 * abs(got)
+
+
+def test_lpd_draw_averaging():
+    rng, y, heldout, _ = _heldout_case(7, n=20, d=2, frac=0.5)
+    xs = rng.standard_normal((3, 20, 2)) * 2
+    sig = np.array([0.7, 0.9, 1.1])
+    a, _ = oracle.lpd(xs, sig, y, heldout)
+    # repeating every draw leaves the average unchanged
+    b, _ = oracle.lpd(np.concatenate([xs, xs]), np.concatenate([sig, sig]), y, heldout)
+    assert abs(a - b) <= 1e-13 * abs(a)
+    # Jensen: the log of the average is at least the average of the logs
+    singles = [oracle.lpd(xs[s], sig[s], y, heldout)[0] for s in range(3)]
+    assert a >= np.mean(singles) - 1e-12 * abs(a)
