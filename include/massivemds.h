@@ -297,6 +297,41 @@ int mds_hmc_momentum(int64_t n, int32_t d, const double* inv_mass, uint64_t seed
                      const uint64_t* iteration_dev, double* p, int64_t ldp, hipStream_t stream);
 
 /*
+ * Log pointwise predictive density of held-out pairs (the model-selection
+ * part of Section 2): for each held-out pair, ln of the average over the
+ * posterior draws s = 1..S of its truncated-normal density with the full
+ * constant, ln p(y | delta, sigma) = -ln(sqrt(2 pi) sigma)
+ * - (y - delta)^2 / (2 sigma^2) - ln Phi(delta / sigma); summed over pairs.
+ *
+ * 1. mds_heldout_count: the number of held-out pairs i > j (heldout byte
+ *    non-zero, not missing: mask byte zero and y not NaN) into *m_dev, and
+ *    the per-row offsets into the workspace (mds_heldout_workspace_bytes).
+ * 2. mds_heldout_fill (same arguments and workspace): the pairs, in
+ *    row-major order, into pi/pj (int32 row and column) and py (y as FP64);
+ *    at most `capacity` are written.
+ * 3. mds_lpd_accumulate, once per draw (x, sigma_dev): updates acc (2*m
+ *    doubles, caller-owned: a running log-sum-exp per pair); first != 0
+ *    starts it.
+ * 4. mds_lpd_finalize: lpd = sum over pairs of ln(average of the densities)
+ *    over n_draws draws, into lpd_dev.
+ */
+int mds_heldout_workspace_bytes(int64_t n, size_t* bytes);
+int mds_heldout_count(const void* y_src, int32_t src_dtype, int64_t ld_src,
+                      const uint8_t* missing, int64_t ld_mask, const uint8_t* heldout,
+                      int64_t ld_heldout, int64_t n, int64_t* m_dev, void* workspace,
+                      size_t workspace_bytes, hipStream_t stream);
+int mds_heldout_fill(const void* y_src, int32_t src_dtype, int64_t ld_src,
+                     const uint8_t* missing, int64_t ld_mask, const uint8_t* heldout,
+                     int64_t ld_heldout, int64_t n, const void* workspace,
+                     size_t workspace_bytes, int64_t capacity, int32_t* pi, int32_t* pj,
+                     double* py, hipStream_t stream);
+int mds_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj, const double* py,
+                       int32_t d, const double* x, int64_t ldx, const double* sigma_dev,
+                       double* acc, int32_t first, hipStream_t stream);
+int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* lpd_dev,
+                     hipStream_t stream);
+
+/*
  * The device special functions of the sweeps, elementwise: ln Phi(t) and
  * phi(t)/Phi(t) (Eq. 2 and Eq. 9) for any real t, in the arithmetic of
  * `precision` (MDS_F64, or MDS_F32: t rounded to FP32 and FP32 arithmetic,

@@ -84,6 +84,19 @@ def lib():
     L.mds_hmc_step.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i64, _vp, _vp, _vp,
                                _vp, _c_i32, ctypes.c_uint64, _vp, _vp, _c_i64, _vp, _vp, _c_i32,
                                _vp, _vp, _vp, ctypes.c_size_t, _c_i32, _c_i32, _vp]
+    L.mds_heldout_workspace_bytes.restype = ctypes.c_int
+    L.mds_heldout_workspace_bytes.argtypes = [_c_i64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mds_heldout_count.restype = ctypes.c_int
+    L.mds_heldout_count.argtypes = [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_i64, _vp,
+                                    _vp, ctypes.c_size_t, _vp]
+    L.mds_heldout_fill.restype = ctypes.c_int
+    L.mds_heldout_fill.argtypes = [_vp, _c_i32, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_i64, _vp,
+                                   ctypes.c_size_t, _c_i64, _vp, _vp, _vp, _vp]
+    L.mds_lpd_accumulate.restype = ctypes.c_int
+    L.mds_lpd_accumulate.argtypes = [_c_i64, _vp, _vp, _vp, _c_i32, _vp, _c_i64, _vp, _vp, _c_i32,
+                                     _vp]
+    L.mds_lpd_finalize.restype = ctypes.c_int
+    L.mds_lpd_finalize.argtypes = [_c_i64, _vp, _c_i64, _vp, _vp]
     L.mds_check_symmetric.restype = ctypes.c_int
     L.mds_check_symmetric.argtypes = [_vp, _c_i32, _c_i64, _c_i64, _vp, _vp]
     L.mds_resolve_tiling.restype = ctypes.c_int
@@ -601,3 +614,71 @@ def _autotuned_batch(problems, dtype, device, tile_waves):
             q["tile_rows"] = br
         out.append(q)
     return out, tile_waves
+
+
+class HeldOutPairs:
+    """The held-out pairs of a cross-validation fold on the device and the
+    log pointwise predictive density over posterior draws.
+
+    y        N x N dissimilarities (the raw values; NaN = missing)
+    heldout  N x N, non-zero marks a held-out pair (read below the diagonal)
+    mask     optional N x N, non-zero marks a missing pair
+
+    ``add_draw(x, sigma)`` folds one posterior draw (x in the original
+    labelling, N x D) into every pair's running average; ``lpd()`` returns the
+    sum over pairs of ln(average density) as a device scalar.
+    """
+
+    def __init__(self, y, heldout, mask=None, device="cuda", stream=None):
+        dev = torch.device(device)
+        y = torch.as_tensor(y)
+        src = y.to(device=dev, dtype=torch.float64 if y.dtype == torch.float64 else
+                   torch.float32).contiguous()
+        h = (torch.as_tensor(heldout) != 0).to(device=dev, dtype=torch.uint8).contiguous()
+        m = None
+        if mask is not None:
+            m = (torch.as_tensor(mask) != 0).to(device=dev, dtype=torch.uint8).contiguous()
+        n = src.shape[0]
+        if src.dim() != 2 or src.shape[1] != n or h.shape != src.shape or \
+                (m is not None and m.shape != src.shape):
+            raise ValueError("y, heldout and mask must be N x N")
+        nb = ctypes.c_size_t()
+        _check(lib().mds_heldout_workspace_bytes(n, ctypes.byref(nb)), "mds_heldout_workspace_bytes")
+        ws = alloc_workspace(nb.value, dev)
+        cnt = torch.zeros((), dtype=torch.int64, device=dev)
+        args = (_ptr(src), _dtype_code(src.dtype), _ld(src), _ptr(m), _ld(m) if m is not None else 0,
+                _ptr(h), _ld(h), n)
+        _check(lib().mds_heldout_count(*args, _ptr(cnt), _ptr(ws), ws.numel(), _stream(stream)),
+               "mds_heldout_count")
+        self.m = int(cnt.item())
+        k = max(self.m, 1)
+        self.pi = torch.empty(k, dtype=torch.int32, device=dev)
+        self.pj = torch.empty(k, dtype=torch.int32, device=dev)
+        self.py = torch.empty(k, dtype=torch.float64, device=dev)
+        _check(lib().mds_heldout_fill(*args, _ptr(ws), ws.numel(), self.m, _ptr(self.pi),
+                                      _ptr(self.pj), _ptr(self.py), _stream(stream)),
+               "mds_heldout_fill")
+        self.acc = torch.empty(2 * k, dtype=torch.float64, device=dev)
+        self.draws = 0
+        self.n, self.device = n, dev
+
+    def add_draw(self, x, sigma, stream=None):
+        x = torch.as_tensor(x).to(device=self.device, dtype=torch.float64)
+        _check_mat(x, "x")
+        if x.shape[0] != self.n:
+            raise ValueError(f"x has {x.shape[0]} rows, the pairs index {self.n}")
+        sig = _dev_scalar(sigma, self.device)
+        _check(lib().mds_lpd_accumulate(self.m, _ptr(self.pi), _ptr(self.pj), _ptr(self.py),
+                                        x.shape[1], _ptr(x), _ld(x), _ptr(sig), _ptr(self.acc),
+                                        1 if self.draws == 0 else 0, _stream(stream)),
+               "mds_lpd_accumulate")
+        self.draws += 1
+
+    def lpd(self, stream=None) -> torch.Tensor:
+        if self.draws == 0:
+            raise ValueError("no posterior draw added")
+        out = torch.empty((), dtype=torch.float64, device=self.device)
+        _check(lib().mds_lpd_finalize(self.m, _ptr(self.acc), self.draws, _ptr(out),
+                                      _stream(stream)), "mds_lpd_finalize")
+        return out
+

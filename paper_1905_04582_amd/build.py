@@ -18,8 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmassivemds.so")
-SOURCES = ["mds_api.hip", "mds_kernels.hip", "mds_order.hip", "mds_hmc.hip", "mds_sweep_f64.hip",
-           "mds_sweep_f32.hip"]
+SOURCES = ["mds_api.hip", "mds_kernels.hip", "mds_order.hip", "mds_hmc.hip", "mds_lpd.hip",
+           "mds_sweep_f64.hip", "mds_sweep_f32.hip"]
 ARCH = "gfx950"
 
 

@@ -36,6 +36,18 @@ hipError_t launch_hmc_decide(uint64_t seed, uint64_t* iteration, const double* e
 hipError_t launch_hmc_finish(int64_t n, int d, const double* flag, double* x, int64_t ldx,
                              double* grad, double* loglik, const double* x_save,
                              const double* g_save, const double* l_save, hipStream_t s);
+hipError_t launch_heldout_count(const void* y, int dt, int64_t ld_y, const uint8_t* missing,
+                                int64_t ld_m, const uint8_t* heldout, int64_t ld_h, int64_t n,
+                                int64_t* rows, int64_t* total, hipStream_t s);
+hipError_t launch_heldout_fill(const void* y, int dt, int64_t ld_y, const uint8_t* missing,
+                               int64_t ld_m, const uint8_t* heldout, int64_t ld_h, int64_t n,
+                               const int64_t* rows, int64_t capacity, int32_t* pi, int32_t* pj,
+                               double* py, hipStream_t s);
+hipError_t launch_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj,
+                                 const double* py, int d, const double* x, int64_t ldx,
+                                 const double* sigma, double* acc, int first, hipStream_t s);
+hipError_t launch_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* out,
+                               hipStream_t s);
 hipError_t launch_log_phi(const double* t, double* lnphi, double* mills, int64_t count, int prec,
                           hipStream_t s);
 }  // namespace mds
@@ -620,6 +632,102 @@ int mds_hmc_step(int64_t n, int32_t d, double* x, int64_t ldx, const void* y, in
     e = launch_hmc_finish(n, d, scal + 3, x, ldx, grad_io, loglik_io, x_save, g_save, scal,
                           stream);
     if (e != hipSuccess) return hip_fail(e, "restore launch");
+    return MDS_OK;
+}
+
+int mds_heldout_workspace_bytes(int64_t n, size_t* bytes)
+{
+    if (!bytes) return fail(MDS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    *bytes = align_up((size_t)(n + 1) * sizeof(int64_t), 256);
+    return MDS_OK;
+}
+
+static int check_heldout_args(const void* y_src, int32_t src_dtype, int64_t ld_src,
+                              const uint8_t* missing, int64_t ld_mask, const uint8_t* heldout,
+                              int64_t ld_heldout, int64_t n, void* ws, size_t ws_bytes)
+{
+    if (n < 0 || n > MDS_MAX_N) return fail(MDS_ERR_INVALID_ARGUMENT, "n out of range");
+    if (src_dtype != MDS_F64 && src_dtype != MDS_F32)
+        return fail(MDS_ERR_UNSUPPORTED, "src_dtype must be MDS_F64 or MDS_F32");
+    if (n > 0 && (!y_src || !heldout || !ws))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "y_src, heldout and workspace must be non-NULL");
+    if (ld_src < n || ld_heldout < n || (missing && ld_mask < n))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "leading dimension < n");
+    if (!aligned(y_src, dtype_size(src_dtype)) || !aligned(ws, MDS_WORKSPACE_ALIGN))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    size_t need = 0;
+    mds_heldout_workspace_bytes(n, &need);
+    if (ws_bytes < need)
+        return fail(MDS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes,
+                    need);
+    return MDS_OK;
+}
+
+int mds_heldout_count(const void* y_src, int32_t src_dtype, int64_t ld_src,
+                      const uint8_t* missing, int64_t ld_mask, const uint8_t* heldout,
+                      int64_t ld_heldout, int64_t n, int64_t* m_dev, void* workspace,
+                      size_t workspace_bytes, hipStream_t stream)
+{
+    int st = check_heldout_args(y_src, src_dtype, ld_src, missing, ld_mask, heldout, ld_heldout,
+                                n, workspace, workspace_bytes);
+    if (st) return st;
+    if (!m_dev || !aligned(m_dev, 8)) return fail(MDS_ERR_INVALID_ARGUMENT, "m_dev NULL or misaligned");
+    hipError_t e = launch_heldout_count(y_src, src_dtype, ld_src, missing, ld_mask, heldout,
+                                        ld_heldout, n, static_cast<int64_t*>(workspace), m_dev,
+                                        stream);
+    if (e != hipSuccess) return hip_fail(e, "held-out count launch");
+    return MDS_OK;
+}
+
+int mds_heldout_fill(const void* y_src, int32_t src_dtype, int64_t ld_src,
+                     const uint8_t* missing, int64_t ld_mask, const uint8_t* heldout,
+                     int64_t ld_heldout, int64_t n, const void* workspace, size_t workspace_bytes,
+                     int64_t capacity, int32_t* pi, int32_t* pj, double* py, hipStream_t stream)
+{
+    int st = check_heldout_args(y_src, src_dtype, ld_src, missing, ld_mask, heldout, ld_heldout,
+                                n, const_cast<void*>(workspace), workspace_bytes);
+    if (st) return st;
+    if (capacity < 0) return fail(MDS_ERR_INVALID_ARGUMENT, "capacity < 0");
+    if (capacity > 0 && (!pi || !pj || !py))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "pair arrays must be non-NULL");
+    if (!aligned(pi, 4) || !aligned(pj, 4) || !aligned(py, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    hipError_t e = launch_heldout_fill(y_src, src_dtype, ld_src, missing, ld_mask, heldout,
+                                       ld_heldout, n, static_cast<const int64_t*>(workspace),
+                                       capacity, pi, pj, py, stream);
+    if (e != hipSuccess) return hip_fail(e, "held-out fill launch");
+    return MDS_OK;
+}
+
+int mds_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj, const double* py,
+                       int32_t d, const double* x, int64_t ldx, const double* sigma_dev,
+                       double* acc, int32_t first, hipStream_t stream)
+{
+    if (m < 0) return fail(MDS_ERR_INVALID_ARGUMENT, "m < 0");
+    if (d < 1 || d > MDS_MAX_DIM)
+        return fail(MDS_ERR_UNSUPPORTED, "d=%d: must be 1..%d", d, MDS_MAX_DIM);
+    if (ldx < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldx < d");
+    if (m > 0 && (!pi || !pj || !py || !x || !sigma_dev || !acc))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "NULL pointer");
+    if (!aligned(pi, 4) || !aligned(pj, 4) || !aligned(py, 8) || !aligned(x, 8) ||
+        !aligned(sigma_dev, 8) || !aligned(acc, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    hipError_t e = launch_lpd_accumulate(m, pi, pj, py, d, x, ldx, sigma_dev, acc, first ? 1 : 0,
+                                         stream);
+    if (e != hipSuccess) return hip_fail(e, "lpd accumulate launch");
+    return MDS_OK;
+}
+
+int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* lpd_dev,
+                     hipStream_t stream)
+{
+    if (m < 0 || n_draws < 1) return fail(MDS_ERR_INVALID_ARGUMENT, "m < 0 or n_draws < 1");
+    if ((m > 0 && !acc) || !lpd_dev) return fail(MDS_ERR_INVALID_ARGUMENT, "NULL pointer");
+    if (!aligned(acc, 8) || !aligned(lpd_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    hipError_t e = launch_lpd_finalize(m, acc, n_draws, lpd_dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "lpd finalize launch");
     return MDS_OK;
 }
 

@@ -1,0 +1,255 @@
+// mds_lpd.hip -- log pointwise predictive density of held-out pairs (the
+// model-selection part of Section 2): for each held-out pair, the log of the
+// average over posterior draws of its truncated-normal density, summed over
+// the pairs.
+//
+// The held-out pairs are first compacted into a list (row i, column j < i,
+// y) in row-major order -- a count pass, an exclusive scan over the rows and
+// a fill pass -- so that each draw costs O(pairs), not O(N^2).  Each draw
+// then updates, per pair, a running log-sum-exp (largest term, sum of
+// exp(l - largest)), and a last pass adds ln(average) over the pairs in a
+// fixed order.
+#include "mds_internal.h"
+#include "mds_math.h"
+
+namespace mds {
+namespace {
+
+constexpr int kRowThreads = 256;
+constexpr int kScanThreads = 1024;
+
+template <typename S>
+__device__ __forceinline__ bool heldout_pair(const S* y, int64_t ld_y, const uint8_t* missing,
+                                             int64_t ld_m, const uint8_t* heldout, int64_t ld_h,
+                                             int64_t i, int64_t j)
+{
+    if (heldout[i * ld_h + j] == 0) return false;
+    if (missing && missing[i * ld_m + j] != 0) return false;
+    return !isnan(y[i * ld_y + j]);
+}
+
+// held-out pairs of row i (j < i)
+template <typename S>
+__global__ void __launch_bounds__(kRowThreads)
+    heldout_count_kernel(const S* __restrict__ y, int64_t ld_y, const uint8_t* __restrict__ missing,
+                         int64_t ld_m, const uint8_t* __restrict__ heldout, int64_t ld_h,
+                         int64_t* __restrict__ row_count)
+{
+    const int64_t i = blockIdx.x;
+    int c = 0;
+    for (int64_t j = threadIdx.x; j < i; j += kRowThreads)
+        c += heldout_pair(y, ld_y, missing, ld_m, heldout, ld_h, i, j) ? 1 : 0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m, kWave);
+    __shared__ int wsum[kRowThreads / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int q = 0; q < kRowThreads / kWave; ++q) t += wsum[q];
+        row_count[i] = t;
+    }
+}
+
+// in place: row_count -> exclusive row offsets; row n holds the total
+__global__ void __launch_bounds__(kScanThreads)
+    row_scan_kernel(int64_t n, int64_t* __restrict__ rows, int64_t* __restrict__ total)
+{
+    __shared__ int64_t part[kScanThreads];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + kScanThreads - 1) / kScanThreads;
+    const int64_t r0 = min(n, (int64_t)t * chunk), r1 = min(n, r0 + chunk);
+    int64_t s = 0;
+    for (int64_t r = r0; r < r1; ++r) s += rows[r];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int q = 0; q < kScanThreads; ++q) {
+            const int64_t v = part[q];
+            part[q] = run;
+            run += v;
+        }
+        rows[n] = run;
+        *total = run;
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int64_t r = r0; r < r1; ++r) {
+        const int64_t v = rows[r];
+        rows[r] = run;
+        run += v;
+    }
+}
+
+// writes the held-out pairs of row i at its offset, in column order
+template <typename S>
+__global__ void __launch_bounds__(kRowThreads)
+    heldout_fill_kernel(const S* __restrict__ y, int64_t ld_y, const uint8_t* __restrict__ missing,
+                        int64_t ld_m, const uint8_t* __restrict__ heldout, int64_t ld_h,
+                        const int64_t* __restrict__ row_off, int64_t capacity,
+                        int32_t* __restrict__ pi, int32_t* __restrict__ pj, double* __restrict__ py)
+{
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    __shared__ int wcount[kRowThreads / kWave];
+    int64_t base = row_off[i];
+    for (int64_t j0 = 0; j0 < i; j0 += kRowThreads) {
+        const int64_t j = j0 + threadIdx.x;
+        const bool keep = j < i && heldout_pair(y, ld_y, missing, ld_m, heldout, ld_h, i, j);
+        const uint64_t mask = __builtin_amdgcn_ballot_w64(keep);
+        const int before = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wcount[w] = __builtin_popcountll(mask);
+        __syncthreads();
+        int wbase = 0, all = 0;
+        for (int q = 0; q < kRowThreads / kWave; ++q) {
+            wbase += (q < w) ? wcount[q] : 0;
+            all += wcount[q];
+        }
+        const int64_t k = base + wbase + before;
+        if (keep && k < capacity) {
+            pi[k] = (int32_t)i;
+            pj[k] = (int32_t)j;
+            py[k] = (double)y[i * ld_y + j];
+        }
+        base += all;
+        __syncthreads();
+    }
+}
+
+// per pair: l = ln p(y | delta, sigma) of the truncated normal, folded into
+// the running log-sum-exp (acc[2k] = largest term, acc[2k+1] = sum of
+// exp(l - largest)); `first` starts the sums
+template <int D>
+__global__ void __launch_bounds__(256)
+    lpd_accumulate_kernel(int64_t m, const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
+                          const double* __restrict__ py, const double* __restrict__ x, int64_t ldx,
+                          const double* __restrict__ sigma_p, double* __restrict__ acc, int first)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const double sigma = *sigma_p;
+    const int64_t i = pi[k], j = pj[k];
+    double s2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double diff = x[i * ldx + d] - x[j * ldx + d];
+        s2 = fma(diff, diff, s2);
+    }
+    const double delta = sqrt(s2);
+    const double z = (py[k] - delta) / sigma;
+    double lnphi, mills;
+    log_phi_general_f64(delta / sigma, lnphi, mills);
+    constexpr double kLnSqrt2Pi = 0.91893853320467274178;
+    const double l = -kLnSqrt2Pi - log(sigma) - 0.5 * z * z - lnphi;
+    if (first) {
+        acc[2 * k] = l;
+        acc[2 * k + 1] = 1.0;
+    } else {
+        const double mx = acc[2 * k];
+        if (l > mx) {
+            acc[2 * k + 1] = acc[2 * k + 1] * exp(mx - l) + 1.0;
+            acc[2 * k] = l;
+        } else {
+            acc[2 * k + 1] += exp(l - mx);
+        }
+    }
+}
+
+// lpd = sum_k [acc_max + ln(acc_sum) - ln S]: compensated per-thread sums,
+// then a fixed tree
+__global__ void __launch_bounds__(kScanThreads)
+    lpd_finalize_kernel(int64_t m, const double* __restrict__ acc, double log_draws,
+                        double* __restrict__ out)
+{
+    __shared__ double ps[kScanThreads];
+    const int t = threadIdx.x;
+    double s = 0.0, c = 0.0;
+    for (int64_t k = t; k < m; k += kScanThreads) {
+        const double v = acc[2 * k] + log(acc[2 * k + 1]) - log_draws;
+        const double u = s + v;
+        c += (fabs(s) >= fabs(v)) ? (s - u) + v : (v - u) + s;
+        s = u;
+    }
+    ps[t] = s + c;
+    __syncthreads();
+    for (int h = kScanThreads / 2; h > 0; h >>= 1) {
+        if (t < h) ps[t] += ps[t + h];
+        __syncthreads();
+    }
+    if (t == 0) *out = ps[0];
+}
+
+}  // namespace
+
+hipError_t launch_heldout_count(const void* y, int dt, int64_t ld_y, const uint8_t* missing,
+                                int64_t ld_m, const uint8_t* heldout, int64_t ld_h, int64_t n,
+                                int64_t* rows, int64_t* total, hipStream_t s)
+{
+    if (n > 0) {
+        if (dt == 0)
+            hipLaunchKernelGGL((heldout_count_kernel<double>), dim3((unsigned)n), dim3(kRowThreads),
+                               0, s, (const double*)y, ld_y, missing, ld_m, heldout, ld_h, rows);
+        else
+            hipLaunchKernelGGL((heldout_count_kernel<float>), dim3((unsigned)n), dim3(kRowThreads),
+                               0, s, (const float*)y, ld_y, missing, ld_m, heldout, ld_h, rows);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(row_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, n, rows, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_heldout_fill(const void* y, int dt, int64_t ld_y, const uint8_t* missing,
+                               int64_t ld_m, const uint8_t* heldout, int64_t ld_h, int64_t n,
+                               const int64_t* rows, int64_t capacity, int32_t* pi, int32_t* pj,
+                               double* py, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (dt == 0)
+        hipLaunchKernelGGL((heldout_fill_kernel<double>), dim3((unsigned)n), dim3(kRowThreads), 0,
+                           s, (const double*)y, ld_y, missing, ld_m, heldout, ld_h, rows, capacity,
+                           pi, pj, py);
+    else
+        hipLaunchKernelGGL((heldout_fill_kernel<float>), dim3((unsigned)n), dim3(kRowThreads), 0,
+                           s, (const float*)y, ld_y, missing, ld_m, heldout, ld_h, rows, capacity,
+                           pi, pj, py);
+    return hipGetLastError();
+}
+
+hipError_t launch_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj,
+                                 const double* py, int d, const double* x, int64_t ldx,
+                                 const double* sigma, double* acc, int first, hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    const dim3 grid((unsigned)((m + 255) / 256)), block(256);
+#define MDS_LPD_CASE(DD)                                                                     \
+    case DD:                                                                                 \
+        hipLaunchKernelGGL(lpd_accumulate_kernel<DD>, grid, block, 0, s, m, pi, pj, py, x, ldx, \
+                           sigma, acc, first);                                               \
+        break;
+    switch (d) {
+        MDS_LPD_CASE(1)
+        MDS_LPD_CASE(2)
+        MDS_LPD_CASE(3)
+        MDS_LPD_CASE(4)
+        MDS_LPD_CASE(5)
+        MDS_LPD_CASE(6)
+        MDS_LPD_CASE(7)
+        MDS_LPD_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef MDS_LPD_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* out,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(lpd_finalize_kernel, dim3(1), dim3(kScanThreads), 0, s, m, acc,
+                       log((double)n_draws), out);
+    return hipGetLastError();
+}
+
+}  // namespace mds

@@ -186,6 +186,59 @@ def test_hmc_rejects():
     assert L.mds_hmc_step(*bad) == ERR_ARG
 
 
+def test_heldout_and_lpd_reject():
+    L = api.lib()
+    nb = ctypes.c_size_t()
+    assert L.mds_heldout_workspace_bytes(100, None) == ERR_ARG
+    assert L.mds_heldout_workspace_bytes(-1, ctypes.byref(nb)) == ERR_ARG
+    assert L.mds_heldout_workspace_bytes(100, ctypes.byref(nb)) == 0
+    assert nb.value >= 101 * 8 and nb.value % 256 == 0
+    ws = _p(FAKE + 65536)
+    ok = [_p(), 0, 100, None, 0, _p(FAKE + 4096), 100, 100, _p(FAKE + 8192), ws, nb.value, None]
+    assert L.mds_heldout_count(*ok[:8], ok[8], ok[9], 8, None) == ERR_WS
+    bad = list(ok)
+    bad[1] = 2                                       # unsupported dtype
+    assert L.mds_heldout_count(*bad) == ERR_UNSUP
+    bad = list(ok)
+    bad[6] = 99                                      # ld_heldout < n
+    assert L.mds_heldout_count(*bad) == ERR_ARG
+    bad = list(ok)
+    bad[3], bad[4] = _p(FAKE + 12288), 50            # ld_mask < n
+    assert L.mds_heldout_count(*bad) == ERR_ARG
+    bad = list(ok)
+    bad[8] = None                                    # no count output
+    assert L.mds_heldout_count(*bad) == ERR_ARG
+    bad = list(ok)
+    bad[9] = _p(FAKE + 65536 + 8)                    # misaligned workspace
+    assert L.mds_heldout_count(*bad) == ERR_ARG
+    fill = ok[:8] + [ws, nb.value, 10, _p(), _p(), _p(), None]
+    bad = list(fill)
+    bad[10] = -1                                     # negative capacity
+    assert L.mds_heldout_fill(*bad) == ERR_ARG
+    bad = list(fill)
+    bad[11] = None                                   # no row array
+    assert L.mds_heldout_fill(*bad) == ERR_ARG
+    bad = list(fill)
+    bad[13] = _p(FAKE + 4)                           # misaligned y list
+    assert L.mds_heldout_fill(*bad) == ERR_ARG
+    acc = [10, _p(), _p(), _p(), 2, _p(), 2, _p(), _p(), 1, None]
+    bad = list(acc)
+    bad[0] = -1
+    assert L.mds_lpd_accumulate(*bad) == ERR_ARG
+    bad = list(acc)
+    bad[4] = 9
+    assert L.mds_lpd_accumulate(*bad) == ERR_UNSUP
+    bad = list(acc)
+    bad[6] = 1                                       # ldx < d
+    assert L.mds_lpd_accumulate(*bad) == ERR_ARG
+    bad = list(acc)
+    bad[7] = None                                    # no sigma
+    assert L.mds_lpd_accumulate(*bad) == ERR_ARG
+    assert L.mds_lpd_finalize(10, _p(), 0, _p(), None) == ERR_ARG
+    assert L.mds_lpd_finalize(10, None, 1, _p(), None) == ERR_ARG
+    assert L.mds_lpd_finalize(10, _p(), 1, _p(FAKE + 4), None) == ERR_ARG
+
+
 def test_model_flags():
     L = api.lib()
     nb = ctypes.c_size_t()
