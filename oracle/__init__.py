@@ -70,6 +70,10 @@ def _load():
                                     ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
                                     _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                     _dp, _dp, _dp, _dp, _dp]
+    lib.oracle_grad_rows_given.restype = ctypes.c_int
+    lib.oracle_grad_rows_given.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
+                                           ctypes.c_int64, ctypes.c_double, _i64p, ctypes.c_int64,
+                                           _dp, _dp, _dp]
     lib.oracle_grad_rows.restype = ctypes.c_int
     lib.oracle_philox4x32_10.restype = None
     lib.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
@@ -192,6 +196,26 @@ def grad_rows(x, y, sigma: float, rows, mask=None):
                               rows.size, _ptr(g), _ptr(a), _ptr(b))
     if rc != 0:
         raise ValueError("oracle_grad_rows rejected its arguments")
+    return g, a, b
+
+
+def grad_rows_given(x, yrows, sigma: float, rows):
+    """Gradient rows (Eq. 9) of the listed points from their whole rows of the
+    symmetric Y (len(rows) x N, NaN = missing), with A_i and B_i."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n, d = x.shape
+    yr = np.ascontiguousarray(yrows, dtype=np.float64).reshape(-1, n)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    if yr.shape[0] != rows.size:
+        raise ValueError("one Y row per listed point")
+    g = np.zeros((rows.size, d), dtype=np.float64)
+    a = np.zeros(rows.size, dtype=np.float64)
+    b = np.zeros(rows.size, dtype=np.float64)
+    rc = lib.oracle_grad_rows_given(n, d, _ptr(x), d, _ptr(yr), n, float(sigma),
+                                    _ptr(rows, _i64p), rows.size, _ptr(g), _ptr(a), _ptr(b))
+    if rc != 0:
+        raise ValueError("oracle_grad_rows_given rejected its arguments")
     return g, a, b
 
 

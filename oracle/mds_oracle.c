@@ -534,12 +534,56 @@ int oracle_hmc_step(int64_t n, int d, double* x, const double* y, int64_t ldy,
  * A_i = sum_j |w_ij| and the rounding scale B_i of oracle_eval.  grad_rows
  * is nrows*d contiguous.
  */
+/*
+ * One gradient row of Eq. (9): point i against every j != i, where y_ij and
+ * its mask byte are read as ylo[j] / mlo[j] for j < i and as
+ * yhi[j * yst] / mhi[j * mst] for j > i (so the same code serves a row of
+ * the lower triangle with its column, or a whole row of a symmetric
+ * matrix).  u and g are caller scratch of d entries.
+ */
+static void grad_row(int64_t n, int d, const double* x, int64_t ldx, int64_t i,
+                     const double* ylo, const double* yhi, int64_t yst,
+                     const unsigned char* mlo, const unsigned char* mhi, int64_t mst,
+                     double sigma, double* u, nsum* g, double* grad, double* absrow,
+                     double* condrow)
+{
+    const double s2 = sigma * sigma;
+    memset(g, 0, sizeof(nsum) * (size_t)d);
+    nsum a = {0, 0}, b = {0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double yij = j < i ? ylo[j] : yhi[j * yst];
+        const int missing = mlo ? (j < i ? mlo[j] : mhi[j * mst]) != 0 : 0;
+        if (missing || isnan(yij)) continue;
+        double dd = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double diff = x[i * ldx + k] - x[j * ldx + k];
+            u[k] = diff;
+            dd += diff * diff;
+        }
+        const double delta = sqrt(dd);
+        const double t = delta / sigma;
+        const double q = 0.5 * erfc(t / ORACLE_SQRT2);
+        const double mills = exp(-0.5 * t * t) * ORACLE_INV_SQRT_2PI / (1.0 - q);
+        const double w = (delta - yij) / s2 + mills / sigma;
+        nsum_add(&a, fabs(w));
+        nsum_add(&b, (delta + fabs(yij)) / s2 + mills / sigma);
+        if (delta > 0.0)
+            for (int k = 0; k < d; ++k) nsum_add(&g[k], -w * (u[k] / delta));
+    }
+    for (int k = 0; k < d; ++k) grad[k] = nsum_get(&g[k]);
+    if (absrow) *absrow = nsum_get(&a);
+    if (condrow) *condrow = nsum_get(&b);
+}
+
 int oracle_grad_rows(int64_t n, int d, const double* x, int64_t ldx, const double* y,
                      int64_t ldy, const unsigned char* mask, int64_t ldm, double sigma,
                      const int64_t* rows, int64_t nrows, double* grad_rows, double* absrow,
                      double* condrow)
 {
     if (n < 0 || d < 1 || ldx < d || (n > 0 && ldy < n)) return -1;
+    for (int64_t r = 0; r < nrows; ++r)
+        if (rows[r] < 0 || rows[r] >= n) return -1;
     double* u = (double*)malloc(sizeof(double) * (size_t)d);
     nsum* g = (nsum*)calloc((size_t)d, sizeof(nsum));
     if (!u || !g) {
@@ -547,40 +591,41 @@ int oracle_grad_rows(int64_t n, int d, const double* x, int64_t ldx, const doubl
         free(g);
         return -1;
     }
-    const double s2 = sigma * sigma;
     for (int64_t r = 0; r < nrows; ++r) {
         const int64_t i = rows[r];
-        if (i < 0 || i >= n) {
-            free(u);
-            free(g);
-            return -1;
-        }
-        memset(g, 0, sizeof(nsum) * (size_t)d);
-        nsum a = {0, 0}, b = {0, 0};
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            const int64_t hi = i > j ? i : j, lo = i > j ? j : i;
-            if (!pair_observed(hi, lo, y, ldy, mask, ldm)) continue;
-            const double yij = y[hi * ldy + lo];
-            double dd = 0.0;
-            for (int k = 0; k < d; ++k) {
-                const double diff = x[i * ldx + k] - x[j * ldx + k];
-                u[k] = diff;
-                dd += diff * diff;
-            }
-            const double delta = sqrt(dd);
-            const double t = delta / sigma;
-            const double q = 0.5 * erfc(t / ORACLE_SQRT2);
-            const double mills = exp(-0.5 * t * t) * ORACLE_INV_SQRT_2PI / (1.0 - q);
-            const double w = (delta - yij) / s2 + mills / sigma;
-            nsum_add(&a, fabs(w));
-            nsum_add(&b, (delta + fabs(yij)) / s2 + mills / sigma);
-            if (delta > 0.0)
-                for (int k = 0; k < d; ++k) nsum_add(&g[k], -w * (u[k] / delta));
-        }
-        for (int k = 0; k < d; ++k) grad_rows[r * d + k] = nsum_get(&g[k]);
-        if (absrow) absrow[r] = nsum_get(&a);
-        if (condrow) condrow[r] = nsum_get(&b);
+        grad_row(n, d, x, ldx, i, y + i * ldy, y + i, ldy, mask ? mask + i * ldm : NULL,
+                 mask ? mask + i : NULL, ldm, sigma, u, g, grad_rows + r * d,
+                 absrow ? absrow + r : NULL, condrow ? condrow + r : NULL);
+    }
+    free(u);
+    free(g);
+    return 0;
+}
+
+/*
+ * The same for rows given whole: yrows holds, for each listed point i, row i
+ * of the symmetric dissimilarity matrix (nrows x n, leading dimension ldyr;
+ * y_ij = yrows[r][j], NaN = missing), so that rows can be checked at sizes
+ * where Y itself does not fit host memory.
+ */
+int oracle_grad_rows_given(int64_t n, int d, const double* x, int64_t ldx, const double* yrows,
+                           int64_t ldyr, double sigma, const int64_t* rows, int64_t nrows,
+                           double* grad_rows, double* absrow, double* condrow)
+{
+    if (n < 0 || d < 1 || ldx < d || (nrows > 0 && ldyr < n)) return -1;
+    for (int64_t r = 0; r < nrows; ++r)
+        if (rows[r] < 0 || rows[r] >= n) return -1;
+    double* u = (double*)malloc(sizeof(double) * (size_t)d);
+    nsum* g = (nsum*)calloc((size_t)d, sizeof(nsum));
+    if (!u || !g) {
+        free(u);
+        free(g);
+        return -1;
+    }
+    for (int64_t r = 0; r < nrows; ++r) {
+        const double* yr = yrows + r * ldyr;
+        grad_row(n, d, x, ldx, rows[r], yr, yr, 1, NULL, NULL, 0, sigma, u, g,
+                 grad_rows + r * d, absrow ? absrow + r : NULL, condrow ? condrow + r : NULL);
     }
     free(u);
     free(g);

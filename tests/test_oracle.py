@@ -368,6 +368,23 @@ def test_grad_rows_vs_brute_force():
         assert b[r] == pytest.approx(ev.condrow[i], rel=1e-15)
 
 
+def test_grad_rows_given_vs_brute_force():
+    # the same rows from whole rows of the symmetric Y (missing folded to NaN)
+    x, y, mask = _rand_problem(9, 2, 0.6, 27, missing=0.2, nan_frac=0.1)
+    ref = mpr.brute_force(x, y, 0.6, mask)
+    yf = np.where(mask != 0, np.nan, y)
+    rows = [8, 0, 4]
+    g, a, b = oracle.grad_rows_given(x, yf[rows], 0.6, rows)
+    ev = oracle.evaluate(x, y, 0.6, mask)
+    for r, i in enumerate(rows):
+        gref = np.array([float(v) for v in ref["grad"][i]])
+        assert np.max(np.abs(g[r] - gref)) <= 1e-14 * ev.absrow[i]
+        assert a[r] == pytest.approx(ev.absrow[i], rel=1e-15)
+        assert b[r] == pytest.approx(ev.condrow[i], rel=1e-15)
+    with pytest.raises(ValueError):
+        oracle.grad_rows_given(x, yf[rows], 0.6, [0, 9, 1])
+
+
 def test_row_rounding_scale_bounds_the_row():
     # B_i = sum (delta + |y|)/sigma^2 + m/sigma bounds every |w_ij|, so B_i >= A_i
     x, y, mask = _rand_problem(40, 2, 0.3, 26, missing=0.1)
