@@ -124,6 +124,84 @@ def cold_sweep_ms(P, x, sigma, reps, events):
     return sorted(out)[len(out) // 2]
 
 
+def progress(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def n_sweep(args, events):
+    """Time per fused evaluation against N (the paper's scaling study over
+    randomly sampled 2-D Gaussian points): GPU FP64 and FP32 forms in the
+    spatial labelling, the serial oracle where it finishes in seconds, and
+    sampled gradient rows against the row oracle at every N."""
+    import numpy as np
+    import torch
+
+    from paper_1905_04582_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    d, sigma = 2, 0.5
+    rows_out = []
+    for n in args.n_list:
+        t0 = time.perf_counter()
+        x_true, x, y = synth.device_problem(n, d, sigma, seed=n, device=dev)
+        torch.cuda.synchronize()
+        gen_s = time.perf_counter() - t0
+        progress(f"n-sweep N={n}: Y drawn on the device in {gen_s:.1f} s")
+        npairs = n * (n - 1) // 2
+        steps = max(5, min(args.steps, int(4e10 / (n * n))))
+        warm = max(2, min(args.warmup, steps // 5))
+        rec = {"n": n, "pairs": npairs, "steps": steps}
+        rng = np.random.default_rng(n)
+        rows = np.sort(rng.choice(n, size=min(n, 8), replace=False))
+        yrows = y[torch.as_tensor(rows, device=dev)].cpu().numpy() if not args.no_cpu else None
+        xd = torch.as_tensor(x, device=dev)
+        for name, dt, ybytes in (("fp64", torch.float64, 8), ("fp32", torch.float32, 4)):
+            P = api.MDSProblem(y, d, None, dt, dev, order=x)
+            xr = P.relabel(xd)
+            wall, sw, swm, (g, L, ds) = timed_evals(P, xr, sigma, steps, warm, events)
+            r = {"ms_per_eval": round(wall, 5), "sweep_ms_mean": round(sw, 5),
+                 "evals_per_s": round(1e3 / wall, 3),
+                 "y_stream_gbs": round(npairs * ybytes / (sw * 1e-3) / 1e9, 2),
+                 "gpairs_per_s": round(npairs / (sw * 1e-3) / 1e9, 3),
+                 "tiles": list(api.mds_resolve_tiling(n, d, api._dtype_code(dt)))}
+            if yrows is not None:
+                import oracle
+                gref, _, b = oracle.grad_rows_given(x, yrows, sigma, rows)
+                gdev = P.unlabel(g).cpu().numpy()[rows]
+                r["sampled_rows_max_err_over_B"] = float(np.max(
+                    np.max(np.abs(gdev - gref), axis=1) / b))
+            r["loglik"] = L.item()
+            rec[name] = r
+            progress(f"  {name}: {wall:.4f} ms per evaluation (sweep {sw:.4f} ms)")
+            del P, xr, g
+        if not args.no_cpu and n <= args.cpu_max_n:
+            import oracle
+            yh = y.cpu().numpy()
+            reps = max(1, int(2e7 / npairs))
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ev = oracle.evaluate(x, yh, sigma)
+            cpu_s = (time.perf_counter() - t0) / reps
+            rec["oracle"] = {"s_per_eval": round(cpu_s, 5), "cores": 1, "evals": reps}
+            rec["fp64"]["loglik_rel_err"] = abs(rec["fp64"]["loglik"] - ev.loglik) / abs(ev.loglik)
+            rec["fp32"]["loglik_rel_err"] = abs(rec["fp32"]["loglik"] - ev.loglik) / abs(ev.loglik)
+            rec["gpu_fp64_over_oracle"] = round(cpu_s / (rec["fp64"]["ms_per_eval"] * 1e-3), 1)
+            progress(f"  oracle: {cpu_s:.4f} s per evaluation")
+            del yh
+        rec["y_draw_s"] = round(gen_s, 2)
+        rows_out.append(rec)
+        del y, xd
+        torch.cuda.empty_cache()
+    print(json.dumps({
+        "metric": "fused loglik+grad evaluation time vs N (D=2, sigma=0.5, no missing pairs)",
+        "unit": "ms per evaluation", "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": "N sweep: X_true ~ N(0, I_2)*3, y_ij truncated N(delta_ij, "
+                               "0.25) drawn on the device, evaluation point X_true + "
+                               "N(0, 0.01); locations relabelled in Hilbert order",
+                   "d": d, "sigma": sigma},
+        "points": rows_out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +211,13 @@ def main():
     ap.add_argument("--cpu-evals", type=int, default=10)
     ap.add_argument("--only", choices=("fp64", "fp32", "fp64-plain", "fp32-plain"), default=None,
                     help="time one form only (for profiler runs); prints a short JSON line")
+    ap.add_argument("--n-sweep", action="store_true",
+                    help="time the evaluation against N instead (one JSON line with a point "
+                         "per N)")
+    ap.add_argument("--n-list", type=lambda v: [int(t) for t in v.split(",")],
+                    default=[1000, 2000, 5000, 10000, 20000, 50000, 100000])
+    ap.add_argument("--cpu-max-n", type=int, default=20000,
+                    help="largest N at which the N sweep times the serial oracle")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of MB megabytes (calibrates the HBM "
                          "byte counters) and exit")
@@ -151,6 +236,12 @@ def main():
         print("bench.py measures one GPU only: the MDS sweep is built and measured on a "
               "single MI355X (see the sharding design); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.n_sweep:
+        import torch
+        torch.cuda.init()      # the HIP runtime torch loads is the one the events use
+        n_sweep(args, HipEvents())
+        return
 
     import numpy as np
     import torch
@@ -226,6 +317,31 @@ def main():
     torch.cuda.synchronize()
     hmc_ms = (time.perf_counter() - t0) * 1e3 / 100
     hmc_acc = chain.accepted.item() / 110
+
+    # held-out predictive density: 10% of the pairs held out (symmetric
+    # Bernoulli), compacted once, then one accumulation pass per posterior
+    # draw (the chain's states stand in for draws) and one finalize
+    held = synth.symmetric_mask(n, 0.10, np.random.Generator(np.random.PCG64(prob.seed + 9)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = api.HeldOutPairs(prob.y, held, prob.mask, dev)
+    torch.cuda.synchronize()
+    lpd_setup_ms = (time.perf_counter() - t0) * 1e3
+    xd = P64.unlabel(chain.x)
+    sig_d = torch.tensor(sigma, dtype=torch.float64, device=dev)
+    for _ in range(5):
+        H.add_draw(xd, sig_d)
+    torch.cuda.synchronize()
+    lpd_draws = 100
+    t0 = time.perf_counter()
+    for _ in range(lpd_draws):
+        H.add_draw(xd, sig_d)
+    torch.cuda.synchronize()
+    lpd_draw_ms = (time.perf_counter() - t0) * 1e3 / lpd_draws
+    lpd_val = H.lpd().item()
+    heldout = {"pairs": H.m, "draws": H.draws, "compaction_ms": round(lpd_setup_ms, 3),
+               "ms_per_draw": round(lpd_draw_ms, 5),
+               "pairs_per_s": round(H.m / (lpd_draw_ms * 1e-3), 1), "lpd": lpd_val}
 
     # the model without truncation (the paper's comparison of the two): the
     # same sweep with the special functions left out, and the oracle's time
@@ -303,6 +419,7 @@ def main():
         },
         "original_labelling": plain,
         "untruncated_model": abl,
+        "heldout_lpd": heldout,
         "leapfrog": {"steps": 20, "step_size": 1e-3, "ms_per_trajectory": round(traj_ms, 4),
                      "gradient_evals": 20},
         "hmc": {"transitions": 100, "leapfrog_steps": 20, "step_size": 1e-3,
@@ -334,6 +451,11 @@ def main():
         out["untruncated_model"]["oracle_s_per_eval"] = round(cpu_u, 4)
         out["untruncated_model"]["gpu_over_oracle"] = round(cpu_u / (abl["fp64"]["ms_per_step"] * 1e-3), 1)
         out["untruncated_model"]["truncated_gpu_over_oracle"] = round(cpu_s / (wall64 * 1e-3), 1)
+        t0 = time.perf_counter()
+        lpd_ref, m_ref = oracle.lpd(xd.cpu().numpy(), [sigma], prob.y, held, prob.mask)
+        out["heldout_lpd"]["oracle_s_per_draw"] = round(time.perf_counter() - t0, 4)
+        # every accumulated draw is the same state, so the lpd equals the one-draw value
+        out["heldout_lpd"]["rel_err_vs_oracle"] = abs(lpd_val - lpd_ref) / abs(lpd_ref)
         out["parity"] = {
             "loglik_rel_err_fp64": abs(L64.item() - ev.loglik) / abs(ev.loglik),
             "grad_max_row_err_over_B_fp64": float(np.max(

@@ -139,6 +139,54 @@ def make_problem(n: int, d: int, sigma: float, *, seed: int = 0, missing: float 
     return Problem(n, d, float(sigma), x_true, x, y, mask, seed, recipe)
 
 
+def device_problem(n: int, d: int, sigma: float, *, seed: int = 0, dtype=None,
+                   device="cuda", eval_noise: float = 0.1, block_rows: int = 1024):
+    """A problem of the same recipe (no missing pairs, no duplicates) whose
+    symmetric Y is drawn directly in device memory, for sizes where the host
+    recipe would take minutes (N = 10^5: 10^10 entries, 80 GB in FP64).
+
+    X_true and the evaluation point come from the same PCG64 streams as
+    ``make_problem``; the truncated-normal draws use the same inverse-CDF
+    transform in FP64 (torch's ndtr/ndtri) with uniforms from torch's device
+    generator seeded with ``seed + 1`` (one (rows x columns) draw per block of
+    ``block_rows`` rows, lower triangle used), so Y follows the same
+    distribution as the host recipe but not the same values.  Returns
+    (x_true, x) as host arrays and Y as an N x N device tensor of ``dtype``
+    (float64 by default).
+    """
+    import torch
+
+    dtype = torch.float64 if dtype is None else dtype
+    rng_x = np.random.Generator(np.random.PCG64(seed))
+    x_true = rng_x.standard_normal((n, d)) * 3.0
+    rng_e = np.random.Generator(np.random.PCG64(seed + 3))
+    x = x_true + eval_noise * rng_e.standard_normal((n, d))
+    xt = torch.as_tensor(x_true, device=device)
+    y = torch.empty((n, n), dtype=dtype, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed + 1)
+    hi = 1.0 - 2.0 ** -53
+    for i0 in range(0, n, block_rows):
+        i1 = min(n, i0 + block_rows)
+        delta = torch.zeros((i1 - i0, i1), dtype=torch.float64, device=device)
+        for k in range(d):
+            delta += (xt[i0:i1, k, None] - xt[None, :i1, k]).square_()
+        delta.sqrt_()
+        u = torch.rand((i1 - i0, i1), generator=gen, dtype=torch.float64, device=device)
+        lo = torch.special.ndtr(-delta / sigma)
+        z = torch.special.ndtri((lo + u * (1.0 - lo)).clamp_(1e-300, hi))
+        y[i0:i1, :i1] = (delta + sigma * z).clamp_(min=np.finfo(np.float64).tiny)
+        del delta, u, lo, z
+    # mirror the strict lower triangle, zero diagonal
+    for i0 in range(0, n, block_rows):
+        i1 = min(n, i0 + block_rows)
+        blk = torch.tril(y[i0:i1, i0:i1], -1)
+        y[i0:i1, i0:i1] = blk + blk.T
+        if i0 > 0:
+            y[:i0, i0:i1] = y[i0:i1, :i0].T
+    return x_true, x, y
+
+
 # Workload presets: sizes, sigma, missing rate and duplicates of the paper's
 # application scale (N = 5392 locations, Section 3) and of the precision,
 # differentiation and batched forms built around it.

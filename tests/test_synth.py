@@ -4,6 +4,7 @@ import pytest
 from scipy import stats
 from scipy.spatial.distance import cdist
 from scipy.special import ndtr
+import torch
 
 from paper_1905_04582_amd import synth
 
@@ -65,3 +66,25 @@ def test_batch_specs():
 def test_presets(name):
     p = synth.preset(name)
     assert p.x.shape == (p.n, p.d) and p.y.shape == (p.n, p.n)
+
+
+def test_device_problem_same_recipe():
+    # the device-drawn Y (run here on the CPU device) is symmetric, positive
+    # off the diagonal, and follows the host recipe's distribution; the
+    # locations are the host recipe's exactly
+    xt, x, y = synth.device_problem(1500, 2, 0.5, seed=11, device="cpu", block_rows=600)
+    host = synth.make_problem(1500, 2, 0.5, seed=11)
+    assert np.array_equal(xt, host.x_true) and np.array_equal(x, host.x)
+    yn = y.numpy()
+    assert np.array_equal(yn, yn.T) and not np.any(np.diag(yn))
+    i, j = np.tril_indices(1500, -1)
+    assert (yn[i, j] > 0).all()
+    dist = np.sqrt(((xt[i] - xt[j]) ** 2).sum(1))
+    r_dev = (yn[i, j] - dist) / 0.5
+    r_host = (host.y[i, j] - dist) / 0.5
+    assert abs(r_dev.mean() - r_host.mean()) < 0.01 and abs(r_dev.std() - r_host.std()) < 0.01
+    # deterministic for a seed and block size
+    _, _, y2 = synth.device_problem(1500, 2, 0.5, seed=11, device="cpu", block_rows=600)
+    assert torch.equal(y, y2)
+    _, _, y32 = synth.device_problem(300, 2, 0.5, seed=1, device="cpu", dtype=torch.float32)
+    assert y32.dtype == torch.float32
