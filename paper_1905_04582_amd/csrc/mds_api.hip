@@ -182,6 +182,11 @@ hipError_t timed_sweep(int y_dtype, int d, bool grad, const Tiling& t, const Swe
     return launch_sweep(y_dtype, d, grad, t, a, s, g_ev_before, g_ev_after);
 }
 
+#if MDS_TILE_TRACE
+// diagnostic build only: where the sweep writes its per-wave clocks
+unsigned long long* g_tile_trace = nullptr;
+#endif
+
 SweepArgs sweep_args(const Tiling& t, const WorkspaceLayout& lay, void* ws, int64_t n,
                      const double* x, int64_t ldx, const void* y, int64_t ldy,
                      const double* sigma, int truncated)
@@ -202,6 +207,9 @@ SweepArgs sweep_args(const Tiling& t, const WorkspaceLayout& lay, void* ws, int6
     a.colpart = reinterpret_cast<double*>(base + lay.colpart);
     a.tscal = reinterpret_cast<double*>(base + lay.tscal);
     a.tcount = reinterpret_cast<uint32_t*>(base + lay.tcount);
+#if MDS_TILE_TRACE
+    a.trace = g_tile_trace;
+#endif
     return a;
 }
 
@@ -224,6 +232,14 @@ FinalizeArgs finalize_args(const Tiling& t, const SweepArgs& s)
 }  // namespace
 
 extern "C" {
+
+#if MDS_TILE_TRACE
+int mds_set_tile_trace(void* p)
+{
+    g_tile_trace = static_cast<unsigned long long*>(p);
+    return 0;
+}
+#endif
 
 const char* mds_status_string(int status)
 {

@@ -134,6 +134,9 @@ struct SweepArgs {
     double* tscal;
     uint32_t* tcount;
     int truncated;  // 0: the model without the truncation terms (ln Phi = m = 0)
+#if MDS_TILE_TRACE
+    unsigned long long* trace;  // diagnostic build only: per-wave start/end clocks
+#endif
 };
 
 // What the finalize kernel does with the summed gradient of one element.

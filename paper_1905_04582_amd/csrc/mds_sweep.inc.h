@@ -30,7 +30,10 @@
 #include "mds_internal.h"
 #include "mds_math.h"
 
-// build-time variants of the sweep (the defaults are the measured best)
+// Build-time variants of the sweep (the defaults are the measured best):
+// rows per step, reduction form, x_i fetched with the Y prefetch, shared
+// special-function coefficient loads, rows of Y prefetched ahead, and a
+// diagnostic build that records each wave's start and end clock.
 #ifndef MDS_ROW_UNROLL
 #define MDS_ROW_UNROLL 2
 #endif
@@ -42,6 +45,12 @@
 #endif
 #ifndef MDS_SHARED_COEF
 #define MDS_SHARED_COEF 1
+#endif
+#ifndef MDS_PREFETCH_ROWS
+#define MDS_PREFETCH_ROWS 2
+#endif
+#ifndef MDS_TILE_TRACE
+#define MDS_TILE_TRACE 0
 #endif
 
 namespace mds {
@@ -264,7 +273,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     // rows per iteration (UR) and rows prefetched ahead (PF); a batch of RB
     // staged rows holds whole iterations
     constexpr int UR = (MDS_ROW_UNROLL >= 4 && RB % 4 == 0) ? 4 : (MDS_ROW_UNROLL >= 2 ? 2 : 1);
-    constexpr int PF = UR < 2 ? 2 : UR;
+    constexpr int PF = (UR < 2 ? 2 : UR) > MDS_PREFETCH_ROWS ? (UR < 2 ? 2 : UR) : MDS_PREFETCH_ROWS;
     RowIn pf[PF];
 #pragma unroll
     for (int k = 0; k < PF; ++k) pf[k] = load_y(ib0 + k);
@@ -355,7 +364,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             for (; q + 3 < nq; q += 4) {
                 const RowIn ya = pf[0], yb = pf[1], yc = pf[2], yd = pf[3];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) pf[k] = load_y(ib + q + 4 + k);
+                for (int k = 0; k + 4 < PF; ++k) pf[k] = pf[k + 4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) pf[PF - 4 + k] = load_y(ib + q + PF + k);
                 PairGeom<T, D> ga, gb, gc, gd;
                 geom(q, ya, ga);
                 geom(q + 1, yb, gb);
@@ -386,15 +397,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 accum(q + 3, gd, ld, md);
             }
         } else if constexpr (UR == 2) {
-            // two rows per iteration: independent dependency chains interleave
-#pragma unroll 1
-            for (; q + 1 < nq; q += 2) {
-                const RowIn ya = pf[0], yb = pf[1];
-                pf[0] = load_y(ib + q + 2);
-                pf[1] = load_y(ib + q + 3);
+            // two rows per step: independent dependency chains interleave
+            auto two_rows = [&](const int qq, const RowIn& ya, const RowIn& yb) {
                 PairGeom<T, D> ga, gb;
-                geom(q, ya, ga);
-                geom(q + 1, yb, gb);
+                geom(qq, ya, ga);
+                geom(qq + 1, yb, gb);
                 count_ok(ga);
                 count_ok(gb);
                 T la = T(0), ma = T(0), lb = T(0), mb = T(0);
@@ -405,8 +412,33 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                     lb = gb.ok ? lb : T(0);
                     mb = gb.ok ? mb : T(0);
                 }
-                accum(q, ga, la, ma);
-                accum(q + 1, gb, lb, mb);
+                accum(qq, ga, la, ma);
+                accum(qq + 1, gb, lb, mb);
+            };
+            if constexpr (PF > 2 && RB % PF == 0) {
+                // PF/2 steps per trip, unrolled, so that each step reloads
+                // the two ring slots it consumed: the ring needs no register
+                // moves (a move of a register with a load in flight would wait
+                // for that load)
+#pragma unroll 1
+                for (; q + PF - 1 < nq; q += PF) {
+#pragma unroll
+                    for (int k = 0; k < PF; k += 2) {
+                        const RowIn ya = pf[k], yb = pf[k + 1];
+                        pf[k] = load_y(ib + q + k + PF);
+                        pf[k + 1] = load_y(ib + q + k + 1 + PF);
+                        two_rows(q + k, ya, yb);
+                    }
+                }
+            }
+#pragma unroll 1
+            for (; q + 1 < nq; q += 2) {
+                const RowIn ya = pf[0], yb = pf[1];
+#pragma unroll
+                for (int k = 0; k + 2 < PF; ++k) pf[k] = pf[k + 2];
+                pf[PF - 2] = load_y(ib + q + PF);
+                pf[PF - 1] = load_y(ib + q + PF + 1);
+                two_rows(q, ya, yb);
             }
         }
 #pragma unroll 1
@@ -505,7 +537,20 @@ template <typename T, int D, bool GRAD>
 __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
+#if MDS_TILE_TRACE
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+#endif
     sweep_tile<T, D, GRAD>(a, blockIdx.x, lds);
+#if MDS_TILE_TRACE
+    // diagnostic build only: start and end clock (100 MHz) and HW_ID of each wave
+    const unsigned long long t1 = __builtin_amdgcn_s_memrealtime();
+    const unsigned long long hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);
+    const int ln = threadIdx.x & (kWave - 1);
+    if (a.trace && ln < 3) {
+        const unsigned long long v = ln == 0 ? t0 : (ln == 1 ? t1 : hw);
+        a.trace[((size_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * 3 + ln] = v;
+    }
+#endif
 }
 
 // Persistent sweep over the tiles of a batch of independent problems: each
