@@ -322,9 +322,12 @@ def main():
     # Bernoulli), compacted once, then one accumulation pass per posterior
     # draw (the chain's states stand in for draws) and one finalize
     held = synth.symmetric_mask(n, 0.10, np.random.Generator(np.random.PCG64(prob.seed + 9)))
+    y_d = torch.as_tensor(prob.y, device=dev)
+    held_d = torch.as_tensor(held, device=dev)
+    mask_d = torch.as_tensor(prob.mask, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    H = api.HeldOutPairs(prob.y, held, prob.mask, dev)
+    H = api.HeldOutPairs(y_d, held_d, mask_d, dev)
     torch.cuda.synchronize()
     lpd_setup_ms = (time.perf_counter() - t0) * 1e3
     xd = P64.unlabel(chain.x)
@@ -339,6 +342,7 @@ def main():
     torch.cuda.synchronize()
     lpd_draw_ms = (time.perf_counter() - t0) * 1e3 / lpd_draws
     lpd_val = H.lpd().item()
+    del y_d, held_d, mask_d
     heldout = {"pairs": H.m, "draws": H.draws, "compaction_ms": round(lpd_setup_ms, 3),
                "ms_per_draw": round(lpd_draw_ms, 5),
                "pairs_per_s": round(H.m / (lpd_draw_ms * 1e-3), 1), "lpd": lpd_val}

@@ -313,7 +313,9 @@ int mds_hmc_momentum(int64_t n, int32_t d, const double* inv_mass, uint64_t seed
  *    doubles, caller-owned: a running log-sum-exp per pair); first != 0
  *    starts it.
  * 4. mds_lpd_finalize: lpd = sum over pairs of ln(average of the densities)
- *    over n_draws draws, into lpd_dev.
+ *    over n_draws draws, into lpd_dev; its workspace (mds_lpd_workspace_bytes,
+ *    256-byte aligned, caller-owned) holds partial sums.  The sums run in a
+ *    fixed order, so the result is deterministic.
  */
 int mds_heldout_workspace_bytes(int64_t n, size_t* bytes);
 int mds_heldout_count(const void* y_src, int32_t src_dtype, int64_t ld_src,
@@ -328,8 +330,9 @@ int mds_heldout_fill(const void* y_src, int32_t src_dtype, int64_t ld_src,
 int mds_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj, const double* py,
                        int32_t d, const double* x, int64_t ldx, const double* sigma_dev,
                        double* acc, int32_t first, hipStream_t stream);
-int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* lpd_dev,
-                     hipStream_t stream);
+int mds_lpd_workspace_bytes(int64_t m, size_t* bytes);
+int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, void* workspace,
+                     size_t workspace_bytes, double* lpd_dev, hipStream_t stream);
 
 /*
  * The device special functions of the sweeps, elementwise: ln Phi(t) and

@@ -96,7 +96,9 @@ def lib():
     L.mds_lpd_accumulate.argtypes = [_c_i64, _vp, _vp, _vp, _c_i32, _vp, _c_i64, _vp, _vp, _c_i32,
                                      _vp]
     L.mds_lpd_finalize.restype = ctypes.c_int
-    L.mds_lpd_finalize.argtypes = [_c_i64, _vp, _c_i64, _vp, _vp]
+    L.mds_lpd_finalize.argtypes = [_c_i64, _vp, _c_i64, _vp, ctypes.c_size_t, _vp, _vp]
+    L.mds_lpd_workspace_bytes.restype = ctypes.c_int
+    L.mds_lpd_workspace_bytes.argtypes = [_c_i64, ctypes.POINTER(ctypes.c_size_t)]
     L.mds_check_symmetric.restype = ctypes.c_int
     L.mds_check_symmetric.argtypes = [_vp, _c_i32, _c_i64, _c_i64, _vp, _vp]
     L.mds_resolve_tiling.restype = ctypes.c_int
@@ -678,7 +680,13 @@ class HeldOutPairs:
         if self.draws == 0:
             raise ValueError("no posterior draw added")
         out = torch.empty((), dtype=torch.float64, device=self.device)
-        _check(lib().mds_lpd_finalize(self.m, _ptr(self.acc), self.draws, _ptr(out),
-                                      _stream(stream)), "mds_lpd_finalize")
+        if getattr(self, "_fin_ws", None) is None:
+            nb = ctypes.c_size_t()
+            _check(lib().mds_lpd_workspace_bytes(self.m, ctypes.byref(nb)),
+                   "mds_lpd_workspace_bytes")
+            self._fin_ws = alloc_workspace(nb.value, self.device)
+        _check(lib().mds_lpd_finalize(self.m, _ptr(self.acc), self.draws, _ptr(self._fin_ws),
+                                      self._fin_ws.numel(), _ptr(out), _stream(stream)),
+               "mds_lpd_finalize")
         return out
 

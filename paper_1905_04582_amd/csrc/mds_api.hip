@@ -46,7 +46,8 @@ hipError_t launch_heldout_fill(const void* y, int dt, int64_t ld_y, const uint8_
 hipError_t launch_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj,
                                  const double* py, int d, const double* x, int64_t ldx,
                                  const double* sigma, double* acc, int first, hipStream_t s);
-hipError_t launch_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* out,
+hipError_t launch_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* part,
+                               double* out,
                                hipStream_t s);
 hipError_t launch_log_phi(const double* t, double* lnphi, double* mills, int64_t count, int prec,
                           hipStream_t s);
@@ -735,14 +736,29 @@ int mds_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj, const do
     return MDS_OK;
 }
 
-int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* lpd_dev,
-                     hipStream_t stream)
+int mds_lpd_workspace_bytes(int64_t m, size_t* bytes)
+{
+    if (!bytes) return fail(MDS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    if (m < 0) return fail(MDS_ERR_INVALID_ARGUMENT, "m < 0");
+    *bytes = align_up((size_t)kLpdMaxParts * sizeof(double), 256);
+    return MDS_OK;
+}
+
+int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, void* workspace,
+                     size_t workspace_bytes, double* lpd_dev, hipStream_t stream)
 {
     if (m < 0 || n_draws < 1) return fail(MDS_ERR_INVALID_ARGUMENT, "m < 0 or n_draws < 1");
-    if ((m > 0 && !acc) || !lpd_dev) return fail(MDS_ERR_INVALID_ARGUMENT, "NULL pointer");
-    if (!aligned(acc, 8) || !aligned(lpd_dev, 8))
+    if ((m > 0 && !acc) || !lpd_dev || !workspace)
+        return fail(MDS_ERR_INVALID_ARGUMENT, "NULL pointer");
+    if (!aligned(acc, 8) || !aligned(lpd_dev, 8) || !aligned(workspace, MDS_WORKSPACE_ALIGN))
         return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
-    hipError_t e = launch_lpd_finalize(m, acc, n_draws, lpd_dev, stream);
+    size_t need = 0;
+    mds_lpd_workspace_bytes(m, &need);
+    if (workspace_bytes < need)
+        return fail(MDS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed",
+                    workspace_bytes, need);
+    hipError_t e = launch_lpd_finalize(m, acc, n_draws, static_cast<double*>(workspace), lpd_dev,
+                                       stream);
     if (e != hipSuccess) return hip_fail(e, "lpd finalize launch");
     return MDS_OK;
 }

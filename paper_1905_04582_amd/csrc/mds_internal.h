@@ -121,6 +121,9 @@ inline size_t sweep_lds_bytes(const Tiling& t, int d)
            (size_t)t.waves * sweep_stage_rows(d) * (kWave * d * sizeof(double) + kStagePadBytes);
 }
 
+// partial sums of the lpd finalize (its workspace holds this many doubles)
+constexpr int kLpdMaxParts = 512;
+
 struct SweepArgs {
     int64_t n;
     const double* x;

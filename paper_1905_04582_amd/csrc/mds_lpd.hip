@@ -17,6 +17,7 @@ namespace {
 
 constexpr int kRowThreads = 256;
 constexpr int kScanThreads = 1024;
+constexpr int kPartThreads = 256;
 
 template <typename S>
 __device__ __forceinline__ bool heldout_pair(const S* y, int64_t ld_y, const uint8_t* missing,
@@ -156,16 +157,19 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// lpd = sum_k [acc_max + ln(acc_sum) - ln S]: compensated per-thread sums,
-// then a fixed tree
-__global__ void __launch_bounds__(kScanThreads)
-    lpd_finalize_kernel(int64_t m, const double* __restrict__ acc, double log_draws,
-                        double* __restrict__ out)
+// lpd = sum_k [acc_max + ln(acc_sum) - ln S], in two passes of fixed
+// order: block b sums its contiguous share of the pairs (compensated
+// per-thread sums, then a tree) into part[b]; one block adds the parts
+__global__ void __launch_bounds__(kPartThreads)
+    lpd_partial_kernel(int64_t m, const double* __restrict__ acc, double log_draws,
+                       double* __restrict__ part)
 {
-    __shared__ double ps[kScanThreads];
+    __shared__ double ps[kPartThreads];
     const int t = threadIdx.x;
+    const int64_t chunk = (m + gridDim.x - 1) / gridDim.x;
+    const int64_t k0 = (int64_t)blockIdx.x * chunk, k1 = min(m, k0 + chunk);
     double s = 0.0, c = 0.0;
-    for (int64_t k = t; k < m; k += kScanThreads) {
+    for (int64_t k = k0 + t; k < k1; k += kPartThreads) {
         const double v = acc[2 * k] + log(acc[2 * k + 1]) - log_draws;
         const double u = s + v;
         c += (fabs(s) >= fabs(v)) ? (s - u) + v : (v - u) + s;
@@ -173,7 +177,21 @@ __global__ void __launch_bounds__(kScanThreads)
     }
     ps[t] = s + c;
     __syncthreads();
-    for (int h = kScanThreads / 2; h > 0; h >>= 1) {
+    for (int h = kPartThreads / 2; h > 0; h >>= 1) {
+        if (t < h) ps[t] += ps[t + h];
+        __syncthreads();
+    }
+    if (t == 0) part[blockIdx.x] = ps[0];
+}
+
+__global__ void __launch_bounds__(kLpdMaxParts)
+    lpd_sum_parts_kernel(int parts, const double* __restrict__ part, double* __restrict__ out)
+{
+    __shared__ double ps[kLpdMaxParts];
+    const int t = threadIdx.x;
+    ps[t] = t < parts ? part[t] : 0.0;
+    __syncthreads();
+    for (int h = kLpdMaxParts / 2; h > 0; h >>= 1) {
         if (t < h) ps[t] += ps[t + h];
         __syncthreads();
     }
@@ -244,11 +262,21 @@ hipError_t launch_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj
     return hipGetLastError();
 }
 
-hipError_t launch_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* out,
-                               hipStream_t s)
+static int lpd_parts(int64_t m)
 {
-    hipLaunchKernelGGL(lpd_finalize_kernel, dim3(1), dim3(kScanThreads), 0, s, m, acc,
-                       log((double)n_draws), out);
+    const int64_t p = (m + 8 * kPartThreads - 1) / (8 * kPartThreads);
+    return (int)max((int64_t)1, min((int64_t)kLpdMaxParts, p));
+}
+
+hipError_t launch_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* part,
+                               double* out, hipStream_t s)
+{
+    const int parts = lpd_parts(m);
+    hipLaunchKernelGGL(lpd_partial_kernel, dim3(parts), dim3(kPartThreads), 0, s, m, acc,
+                       log((double)n_draws), part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lpd_sum_parts_kernel, dim3(1), dim3(kLpdMaxParts), 0, s, parts, part, out);
     return hipGetLastError();
 }
 

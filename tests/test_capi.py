@@ -234,9 +234,25 @@ def test_heldout_and_lpd_reject():
     bad = list(acc)
     bad[7] = None                                    # no sigma
     assert L.mds_lpd_accumulate(*bad) == ERR_ARG
-    assert L.mds_lpd_finalize(10, _p(), 0, _p(), None) == ERR_ARG
-    assert L.mds_lpd_finalize(10, None, 1, _p(), None) == ERR_ARG
-    assert L.mds_lpd_finalize(10, _p(), 1, _p(FAKE + 4), None) == ERR_ARG
+    lb = ctypes.c_size_t()
+    assert L.mds_lpd_workspace_bytes(10, None) == ERR_ARG
+    assert L.mds_lpd_workspace_bytes(10, ctypes.byref(lb)) == 0 and lb.value % 256 == 0
+    fin = [10, _p(), 1, ws, lb.value, _p(), None]
+    bad = list(fin)
+    bad[2] = 0                                       # no draws
+    assert L.mds_lpd_finalize(*bad) == ERR_ARG
+    bad = list(fin)
+    bad[1] = None                                    # no accumulators
+    assert L.mds_lpd_finalize(*bad) == ERR_ARG
+    bad = list(fin)
+    bad[5] = _p(FAKE + 4)                            # misaligned output
+    assert L.mds_lpd_finalize(*bad) == ERR_ARG
+    bad = list(fin)
+    bad[4] = 8                                       # workspace too small
+    assert L.mds_lpd_finalize(*bad) == ERR_WS
+    bad = list(fin)
+    bad[3] = _p(FAKE + 65536 + 8)                    # misaligned workspace
+    assert L.mds_lpd_finalize(*bad) == ERR_ARG
 
 
 def test_model_flags():
