@@ -31,17 +31,13 @@
 #include "mds_math.h"
 
 // Build-time variants of the sweep (the defaults are the measured best):
-// rows per step, reduction form, x_i fetched with the Y prefetch, shared
-// special-function coefficient loads, rows of Y prefetched ahead, and a
+// rows per step, reduction form, shared special-function coefficient loads, rows of Y prefetched ahead, and a
 // diagnostic build that records each wave's start and end clock.
 #ifndef MDS_ROW_UNROLL
 #define MDS_ROW_UNROLL 2
 #endif
 #ifndef MDS_REDUCE_PER_OUTPUT
 #define MDS_REDUCE_PER_OUTPUT 1
-#endif
-#ifndef MDS_PREFETCH_X
-#define MDS_PREFETCH_X 0
 #endif
 #ifndef MDS_SHARED_COEF
 #define MDS_SHARED_COEF 1
@@ -251,32 +247,36 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     // into the tile, column into the matrix; lanes outside the triangle
     // discard the value through `ok`), so no branch splits the wave and the
     // wait before a row's first use leaves the two newer loads in flight.
-    // x_i is uniform across the wave and comes through scalar loads (X is
-    // read-only during the sweep, so the constant address space is valid);
-    // with MDS_PREFETCH_X it is fetched together with the row's Y values.
-    const int64_t jc = colok ? j : 0;
+    // Rows are loaded strictly in order, so the row's address is a uniform
+    // pointer that advances by ldy per load and stops at the tile's last row;
+    // each lane adds its 32-bit column offset.  Row and column indices fit
+    // 32 bits (N <= 2^30).
+    const uint32_t jc = colok ? (uint32_t)j : 0u;
+    const int j32 = (int)j;
+    const int last_row = (int)(row1 - 1);
+    const T* yrow = Y + ib0 * a.ldy;
+    int ynext = (int)ib0;
     struct RowIn {
         T y;
-        double x[D];
     };
-    auto load_y = [&](int64_t i) -> RowIn {
+    auto load_y = [&]() -> RowIn {
         RowIn r;
-        const int64_t ic = min(i, row1 - 1);
-        r.y = Y[ic * a.ldy + jc];
-#if MDS_PREFETCH_X
-        const const_f64_ptr xp = (const_f64_ptr)(a.x + ic * a.ldx);
-#pragma unroll
-        for (int d = 0; d < D; ++d) r.x[d] = xp[d];
-#endif
+        r.y = yrow[jc];
+        if (ynext < last_row) yrow += a.ldy;
+        ++ynext;
         return r;
     };
+    // x_i is uniform across the wave and comes through scalar loads (X is
+    // read-only during the sweep, so the constant address space is valid);
+    // rows are visited in order, so its address advances by ldx per row
+    const double* xrow = a.x + ib0 * a.ldx;
     // rows per iteration (UR) and rows prefetched ahead (PF); a batch of RB
     // staged rows holds whole iterations
     constexpr int UR = (MDS_ROW_UNROLL >= 4 && RB % 4 == 0) ? 4 : (MDS_ROW_UNROLL >= 2 ? 2 : 1);
     constexpr int PF = (UR < 2 ? 2 : UR) > MDS_PREFETCH_ROWS ? (UR < 2 ? 2 : UR) : MDS_PREFETCH_ROWS;
     RowIn pf[PF];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) pf[k] = load_y(ib0 + k);
+    for (int k = 0; k < PF; ++k) pf[k] = load_y();
     for (int64_t ib = ib0; ib < row1; ib += RB) {
         T gjb[D];
 #pragma unroll
@@ -286,14 +286,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
 
         // geometry of one pair row (row ib + q, this lane's column)
         auto geom = [&](const int q, const RowIn& rin, PairGeom<T, D>& g) {
-            const int64_t i = ib + q;
+            const int i = (int)(ib + q);
             const T yv = rin.y;
-#if MDS_PREFETCH_X
-            const double* xi = rin.x;
-#else
-            const const_f64_ptr xi = (const_f64_ptr)(a.x + i * a.ldx);
-#endif
-            g.ok = colok && (j < i) && !isnan(yv);
+            const const_f64_ptr xi = (const_f64_ptr)xrow;
+            xrow += a.ldx;
+            g.ok = colok && (j32 < i) && !isnan(yv);
             T s2 = T(0);
 #pragma unroll
             for (int d = 0; d < D; ++d) {
@@ -344,7 +341,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             const RowIn ya = pf[0];
 #pragma unroll
             for (int k = 0; k + 1 < PF; ++k) pf[k] = pf[k + 1];
-            pf[PF - 1] = load_y(ib + q + PF);
+            pf[PF - 1] = load_y();
             PairGeom<T, D> ga;
             geom(q, ya, ga);
             count_ok(ga);
@@ -366,7 +363,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
 #pragma unroll
                 for (int k = 0; k + 4 < PF; ++k) pf[k] = pf[k + 4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) pf[PF - 4 + k] = load_y(ib + q + PF + k);
+                for (int k = 0; k < 4; ++k) pf[PF - 4 + k] = load_y();
                 PairGeom<T, D> ga, gb, gc, gd;
                 geom(q, ya, ga);
                 geom(q + 1, yb, gb);
@@ -425,8 +422,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
 #pragma unroll
                     for (int k = 0; k < PF; k += 2) {
                         const RowIn ya = pf[k], yb = pf[k + 1];
-                        pf[k] = load_y(ib + q + k + PF);
-                        pf[k + 1] = load_y(ib + q + k + 1 + PF);
+                        pf[k] = load_y();
+                        pf[k + 1] = load_y();
                         two_rows(q + k, ya, yb);
                     }
                 }
@@ -436,8 +433,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 const RowIn ya = pf[0], yb = pf[1];
 #pragma unroll
                 for (int k = 0; k + 2 < PF; ++k) pf[k] = pf[k + 2];
-                pf[PF - 2] = load_y(ib + q + PF);
-                pf[PF - 1] = load_y(ib + q + PF + 1);
+                pf[PF - 2] = load_y();
+                pf[PF - 1] = load_y();
                 two_rows(q, ya, yb);
             }
         }
