@@ -22,6 +22,10 @@ LIB_PATH = os.environ.get("MDS_LIB_PATH", os.path.join(_PKG, "libmassivemds.so")
 
 MDS_OK = 0
 MDS_UNTRUNCATED = 0x100      # model flag: no truncation to y > 0 (plain normal errors)
+MDS_ERR_INVALID_ARGUMENT = -1
+MDS_ERR_UNSUPPORTED = -2
+MDS_ERR_WORKSPACE_TOO_SMALL = -3
+MDS_ERR_HIP = -4
 MDS_ERR_NOT_SYMMETRIC = -5
 MDS_F64 = 0
 MDS_F32 = 1

@@ -1,6 +1,6 @@
 """Build libmassivemds.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_1905_04582_amd.build
+    python -m paper_1905_04582_amd.build [-DMACRO=value ...] [--out other.so]
 
 Every translation unit under csrc/ is compiled for gfx950 only, with packed
 FP32 instructions disabled, then linked into paper_1905_04582_amd/libmassivemds.so.
@@ -65,4 +65,11 @@ def build(extra_flags=(), verbose: bool = False, out: str | None = None) -> str:
 
 
 if __name__ == "__main__":
-    build(sys.argv[1:], verbose=True)
+    # python -m paper_1905_04582_amd.build [-DMACRO=value ...] [--out path/to/lib.so]
+    argv = sys.argv[1:]
+    out = None
+    if "--out" in argv:
+        k = argv.index("--out")
+        out = os.path.abspath(argv[k + 1])
+        argv = argv[:k] + argv[k + 2:]
+    build(argv, verbose=True, out=out)

@@ -113,8 +113,10 @@ def test_fp64_every_tiling(tile):
     try:
         got, _ = gpu_eval(y, x, sigma, mask, tile=tile)
     except api.MDSError as e:
-        assert e.status == -2   # tile too large for the LDS budget at this D
-        pytest.skip(str(e))
+        # a tile too large for the LDS budget at this D is rejected up front
+        assert e.status == api.MDS_ERR_UNSUPPORTED, e
+        _log(f"tile={tile}: rejected as expected ({e})")
+        return
     check64(got, ref, f"tile={tile}")
 
 
