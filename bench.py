@@ -485,6 +485,18 @@ def main():
             "sweep_ms_mean": round(sweep64, 5), "sweep_ms_median": round(sweep64_med, 5),
             "sweep_ms_cold_median": round(cold64, 5),
         },
+        # the binding resource: issued FP64 VALU lane-operations (an FMA counts
+        # once) per second, from the counter run's instruction count of this
+        # kernel source, against 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz
+        "roofline_alu": {
+            "bound": "alu", "kernel": "sweep_kernel<double,2,true>",
+            "achieved": (round(c64["sq_insts_valu"] * 64 / (sweep64 * 1e-3) / 1e12, 3)
+                         if c64.get("sq_insts_valu") else None),
+            "peak": FP64_VALU_TOPS, "unit": "T lane-op/s",
+            "frac": (round(c64["sq_insts_valu"] * 64 / (sweep64 * 1e-3) / 1e12 / FP64_VALU_TOPS, 4)
+                     if c64.get("sq_insts_valu") else None),
+            "valu_insts_per_launch": c64.get("sq_insts_valu"),
+        },
         "fp32_form": {
             "value": round(1e3 / wall32, 3), "unit": "evals/s", "ms_per_step": round(wall32, 5),
             "speedup_vs_fp64": round(wall64 / wall32, 3), "sweep_ms_mean": round(sweep32, 5),
