@@ -48,7 +48,7 @@
  *     NaN or Inf in X or in observed entries of Y propagate to the outputs.
  *   - Results are deterministic: the same inputs on the same device give
  *     bitwise identical outputs (fixed-order reductions, no float atomics).
- *   - Pair tiling: `tile_rows` (rows per tile: 32, 64, 128 or 256) and
+ *   - Pair tiling: `tile_rows` (rows per tile: 8, 16, 32, 64, 128 or 256) and
  *     `tile_waves` (64-wide column groups per tile: 1, 2, 4 or 8) pick the
  *     tile shape; 0 selects the built-in default for (dtype, D, N).  One of
  *     tile_rows and 64*tile_waves must divide the other.  The workspace

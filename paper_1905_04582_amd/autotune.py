@@ -30,7 +30,7 @@ import torch
 from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
-ROW_TILES = (32, 64, 128, 256)
+ROW_TILES = (8, 16, 32, 64, 128, 256)
 WAVE_TILES = (1, 2, 4, 8)
 
 

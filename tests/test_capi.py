@@ -45,7 +45,7 @@ def test_workspace_query():
     assert 0 < a < b
     assert api.mds_workspace_bytes(0, 2, api.MDS_F64) == 0
     # explicit tilings: one of tile_rows and 64*tile_waves must divide the other
-    for br in (32, 64, 128, 256):
+    for br in (8, 16, 32, 64, 128, 256):
         for w in (1, 2, 4, 8):
             if (64 * w) % br == 0 or br % (64 * w) == 0:
                 try:
@@ -60,6 +60,7 @@ def test_workspace_query():
     ((10, 2, 7, 0, 0), ERR_UNSUP),        # bad dtype
     ((-1, 2, 0, 0, 0), ERR_ARG),          # n < 0
     ((10, 2, 0, 48, 0), ERR_UNSUP),       # tile_rows not in the set
+    ((10, 2, 0, 4, 0), ERR_UNSUP),        # tile_rows below the smallest
     ((10, 2, 0, 64, 3), ERR_UNSUP),       # tile_waves not in the set
 ])
 def test_workspace_query_rejects(args, code):
@@ -271,7 +272,9 @@ def test_model_flags():
 def test_resolve_tiling():
     L = api.lib()
     f64, f32 = api.MDS_F64, api.MDS_F32
-    assert api.mds_resolve_tiling(1000, 2, f64) == (32, 1)
+    assert api.mds_resolve_tiling(1000, 2, f64) == (8, 1)
+    assert api.mds_resolve_tiling(1000, 2, f32) == (16, 1)
+    assert api.mds_resolve_tiling(2500, 2, f64) == (16, 1)
     assert api.mds_resolve_tiling(5392, 2, f64) == (32, 4)
     assert api.mds_resolve_tiling(5392, 2, f32) == (32, 4)
     assert api.mds_resolve_tiling(20000, 6, f32) == (64, 4)

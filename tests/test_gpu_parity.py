@@ -99,7 +99,7 @@ def test_fp64_all_dims_ragged(n, d):
 
 def _valid_tilings():
     out = []
-    for br in (32, 64, 128, 256):
+    for br in (8, 16, 32, 64, 128, 256):
         for w in (1, 2, 4, 8):
             if (64 * w) % br == 0 or br % (64 * w) == 0:
                 out.append((br, w))
@@ -118,6 +118,20 @@ def test_fp64_every_tiling(tile):
         _log(f"tile={tile}: rejected as expected ({e})")
         return
     check64(got, ref, f"tile={tile}")
+
+
+@pytest.mark.parametrize("br,w", [(8, 1), (16, 1), (8, 4), (16, 2)])
+@pytest.mark.parametrize("d", [1, 2, 5, 8])
+def test_small_row_tiles(br, w, d):
+    # 8- and 16-row tiles (small N): one staged batch of rows per tile or
+    # two, every D, a ragged last row block
+    x, y, mask, sigma = _rand(333, d, seed=40 + d, sigma=0.7)
+    ref = oracle.evaluate(x, y, sigma, mask)
+    got, _ = gpu_eval(y, x, sigma, mask, tile=(br, w))
+    check64(got, ref, f"tile={br}x{64 * w} d={d}")
+    g32, _ = gpu_eval(y.astype(np.float32), x, sigma, mask, dtype=torch.float32, tile=(br, w))
+    ref32 = oracle.evaluate(x, y.astype(np.float32).astype(np.float64), sigma, mask)
+    assert abs(g32["loglik"] - ref32.loglik) <= TOL32_LOGLIK * abs(ref32.loglik)
 
 
 def test_fp64_small_preset():
