@@ -8,8 +8,16 @@ this module only marshals numpy arrays into it.
 Functions follow Holbrook et al., "Massive parallelization boosts big
 Bayesian multidimensional scaling":
   * ``log_phi``/``mills``   -- ln Phi(t) and phi(t)/Phi(t) (Eq. 2, Eq. 9)
-  * ``evaluate``            -- L, dL/dX, dL/dsigma (Eq. 2, Eq. 9)
+  * ``evaluate``            -- L, dL/dX, dL/dsigma (Eq. 2, Eq. 9); with
+                               ``truncated=False`` the model without the
+                               truncation to y > 0 (the scaling appendix)
+  * ``grad_rows``/``grad_rows_given`` -- listed gradient rows of Eq. (9)
   * ``leapfrog``            -- one HMC leapfrog trajectory (Section 2.3)
+  * ``philox4x32_10``, ``uniform_open``, ``momentum``, ``accept_uniform``,
+    ``hmc_step``            -- the random draws and one HMC transition
+                               (Section 2.3, Eqs. 6-8)
+  * ``lpd``                 -- log pointwise predictive density of held-out
+                               pairs (model selection, Section 2)
 """
 from __future__ import annotations
 

@@ -26,6 +26,12 @@
  *   - Leapfrog follows Section 2.3 (Eqs. 6-8) with xdot = M^{-1} p (the
  *     printed factor 1/2 in Eq. 7 is read as a typesetting error) and an
  *     optional isotropic Gaussian prior -(lambda/2)||X||^2 in the target.
+ *   - The HMC transition draws p ~ N(0, M) and the acceptance uniform from
+ *     Philox4x32-10 (Salmon et al., SC 2011) counted by (draw, transition)
+ *     and keyed by the seed; accept when ln u < H_start - H_end.
+ *   - The model without truncation drops ln Phi from L and phi/Phi from the
+ *     derivatives; the held-out predictive density averages the full
+ *     truncated-normal density (with its 2 pi constant) over the draws.
  *
  * Every sum uses Neumaier's compensated summation, so the oracle's own
  * rounding error stays far below the 1e-12 parity tolerance even for tens of
