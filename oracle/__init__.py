@@ -77,7 +77,7 @@ def _load():
     lib.oracle_leapfrog.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, _dp, _dp,
                                     ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
                                     _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                    _dp, _dp, _dp, _dp, _dp]
+                                    _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
     lib.oracle_grad_rows_given.restype = ctypes.c_int
     lib.oracle_grad_rows_given.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
                                            ctypes.c_int64, ctypes.c_double, _i64p, ctypes.c_int64,
@@ -97,7 +97,7 @@ def _load():
                                     ctypes.c_int64, ctypes.c_double, _dp, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, ctypes.c_uint64,
                                     ctypes.c_uint64, _dp, _dp, _dp, _dp, _dp, _dp,
-                                    ctypes.POINTER(ctypes.c_int)]
+                                    ctypes.POINTER(ctypes.c_int), ctypes.c_int]
     lib.oracle_grad_rows.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int64, _dp,
                                      ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_double,
                                      _i64p, ctypes.c_int64, _dp, _dp, _dp]
@@ -239,8 +239,9 @@ class Trajectory:
 
 
 def leapfrog(x, p, y, sigma: float, eps: float, n_steps: int, mask=None,
-             inv_mass=None, prior_precision: float = 0.0) -> Trajectory:
-    """One leapfrog trajectory (Section 2.3); returns copies, inputs untouched."""
+             inv_mass=None, prior_precision: float = 0.0, truncated: bool = True) -> Trajectory:
+    """One leapfrog trajectory (Section 2.3); returns copies, inputs untouched.
+    ``truncated=False`` targets the model without the truncation to y > 0."""
     lib = _load()
     x = np.array(x, dtype=np.float64, copy=True, order="C")
     p = np.array(p, dtype=np.float64, copy=True, order="C")
@@ -259,7 +260,7 @@ def leapfrog(x, p, y, sigma: float, eps: float, n_steps: int, mask=None,
                              ctypes.cast(ctypes.byref(out, 0), _dp),
                              ctypes.cast(ctypes.byref(out, 8), _dp),
                              ctypes.cast(ctypes.byref(out, 16), _dp),
-                             ctypes.cast(ctypes.byref(out, 24), _dp))
+                             ctypes.cast(ctypes.byref(out, 24), _dp), 1 if truncated else 0)
     if rc != 0:
         raise ValueError("oracle_leapfrog rejected its arguments")
     return Trajectory(x, p, g, out[0], out[1], out[2], out[3])
@@ -307,7 +308,8 @@ class HMCStep:
 
 
 def hmc_step(x, y, sigma: float, eps: float, n_steps: int, seed: int, iteration: int,
-             mask=None, inv_mass=None, prior_precision: float = 0.0) -> HMCStep:
+             mask=None, inv_mass=None, prior_precision: float = 0.0,
+             truncated: bool = True) -> HMCStep:
     """One HMC transition (Section 2.3) from state x; inputs untouched."""
     lib = _load()
     x = np.array(x, dtype=np.float64, copy=True, order="C")
@@ -325,7 +327,8 @@ def hmc_step(x, y, sigma: float, eps: float, n_steps: int, seed: int, iteration:
                              _ptr(p), _ptr(g), ctypes.cast(ctypes.byref(out, 0), _dp),
                              ctypes.cast(ctypes.byref(out, 8), _dp),
                              ctypes.cast(ctypes.byref(out, 16), _dp),
-                             ctypes.cast(ctypes.byref(out, 24), _dp), ctypes.byref(acc))
+                             ctypes.cast(ctypes.byref(out, 24), _dp), ctypes.byref(acc),
+                             1 if truncated else 0)
     if rc != 0:
         raise ValueError("oracle_hmc_step rejected its arguments")
     return HMCStep(x, p, g, out[0], out[1], out[2], out[3], bool(acc.value))

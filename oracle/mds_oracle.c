@@ -330,10 +330,12 @@ int oracle_lpd(int64_t n, int d, int64_t n_draws, const double* xs, const double
 /* gradient of the HMC target log pi(x) = L(x) - (lambda/2)||x||^2 */
 static int target_grad(int64_t n, int d, const double* x, const double* y, int64_t ldy,
                        const unsigned char* mask, int64_t ldm, double sigma, double lambda,
-                       double* g, double* loglik)
+                       int truncated, double* g, double* loglik)
 {
-    int rc = oracle_eval(n, d, x, d, y, ldy, mask, ldm, sigma, loglik, g, NULL, NULL, NULL,
-                         NULL, NULL, NULL);
+    int rc = truncated ? oracle_eval(n, d, x, d, y, ldy, mask, ldm, sigma, loglik, g, NULL, NULL,
+                                     NULL, NULL, NULL, NULL)
+                       : oracle_eval_normal(n, d, x, d, y, ldy, mask, ldm, sigma, loglik, g, NULL,
+                                            NULL, NULL, NULL, NULL, NULL);
     if (rc) return rc;
     if (lambda != 0.0)
         for (int64_t k = 0; k < n * d; ++k) g[k] -= lambda * x[k];
@@ -350,20 +352,21 @@ static int target_grad(int64_t n, int d, const double* x, const double* y, int64
  * Outputs (each may be NULL): grad_end = grad log pi at the final x,
  * loglik_start / loglik_end = L at the first and final x, and
  * energy_start / energy_end = H = -log pi(x) + p^T M^{-1} p / 2 (Eq. 6)
- * before and after the trajectory.
+ * before and after the trajectory.  truncated = 0 targets the model without
+ * the truncation to y > 0.
  */
 int oracle_leapfrog(int64_t n, int d, double* x, double* p, const double* y, int64_t ldy,
                     const unsigned char* mask, int64_t ldm, double sigma,
                     const double* inv_mass, double eps, double lambda, int n_steps,
                     double* grad_end, double* loglik_start, double* loglik_end,
-                    double* energy_start, double* energy_end)
+                    double* energy_start, double* energy_end, int truncated)
 {
     if (n < 0 || d < 1 || n_steps < 0) return -1;
     const int64_t nd = n * d;
     double* g = (double*)malloc(sizeof(double) * (size_t)(nd > 0 ? nd : 1));
     if (!g) return -1;
     double L = 0.0;
-    int rc = target_grad(n, d, x, y, ldy, mask, ldm, sigma, lambda, g, &L);
+    int rc = target_grad(n, d, x, y, ldy, mask, ldm, sigma, lambda, truncated, g, &L);
     if (rc) {
         free(g);
         return rc;
@@ -383,7 +386,7 @@ int oracle_leapfrog(int64_t n, int d, double* x, double* p, const double* y, int
         for (int64_t k = 0; k < nd; ++k) p[k] += 0.5 * eps * g[k];
         for (int s = 1; s <= n_steps; ++s) {
             for (int64_t k = 0; k < nd; ++k) x[k] += eps * (inv_mass ? inv_mass[k] : 1.0) * p[k];
-            rc = target_grad(n, d, x, y, ldy, mask, ldm, sigma, lambda, g, &L);
+            rc = target_grad(n, d, x, y, ldy, mask, ldm, sigma, lambda, truncated, g, &L);
             if (rc) {
                 free(g);
                 return rc;
@@ -500,7 +503,7 @@ int oracle_hmc_step(int64_t n, int d, double* x, const double* y, int64_t ldy,
                     const double* inv_mass, double eps, double lambda, int n_steps,
                     uint64_t seed, uint64_t it, double* p_out, double* grad_out,
                     double* loglik_out, double* h_start, double* h_end, double* log_u,
-                    int* accepted)
+                    int* accepted, int truncated)
 {
     if (n < 0 || d < 1 || n_steps < 0 || !p_out || !grad_out) return -1;
     const int64_t nd = n * d;
@@ -510,7 +513,7 @@ int oracle_hmc_step(int64_t n, int d, double* x, const double* y, int64_t ldy,
     oracle_momentum(n, d, inv_mass, seed, it, p_out);
     double hs = 0.0, he = 0.0, L = 0.0;
     int rc = oracle_leapfrog(n, d, x, p_out, y, ldy, mask, ldm, sigma, inv_mass, eps, lambda,
-                             n_steps, grad_out, NULL, &L, &hs, &he);
+                             n_steps, grad_out, NULL, &L, &hs, &he, truncated);
     if (rc) {
         free(x0);
         return rc;
@@ -519,7 +522,7 @@ int oracle_hmc_step(int64_t n, int d, double* x, const double* y, int64_t ldy,
     const int acc = lu < hs - he;
     if (!acc) {
         memcpy(x, x0, sizeof(double) * (size_t)nd);
-        rc = target_grad(n, d, x, y, ldy, mask, ldm, sigma, lambda, grad_out, &L);
+        rc = target_grad(n, d, x, y, ldy, mask, ldm, sigma, lambda, truncated, grad_out, &L);
     }
     free(x0);
     if (loglik_out) *loglik_out = L;

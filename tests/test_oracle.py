@@ -434,6 +434,42 @@ def test_truncation_term_is_the_only_difference():
     assert np.abs(b.grad.sum(0)).max() <= 1e-12 * np.abs(b.grad).max()
 
 
+def test_untruncated_leapfrog_step_by_hand_and_order():
+    """The leapfrog on the model without truncation: one step written out
+    from the normal model's gradient (pinned above against mpmath), and the
+    energy error of a trajectory falling as eps^2."""
+    x, y, mask = _rand_problem(12, 2, 0.8, 31, missing=0.1)
+    p = np.random.default_rng(5).standard_normal((12, 2))
+    eps = 1e-3
+    tr = oracle.leapfrog(x, p, y, 0.8, eps, 1, mask=mask, truncated=False)
+    g0 = oracle.evaluate(x, y, 0.8, mask, truncated=False).grad
+    ph = p + 0.5 * eps * g0
+    x1 = x + eps * ph
+    g1 = oracle.evaluate(x1, y, 0.8, mask, truncated=False).grad
+    assert np.abs(tr.x - x1).max() <= 1e-15 * np.abs(x1).max()
+    assert np.abs(tr.p - (ph + 0.5 * eps * g1)).max() <= 1e-13 * np.abs(p).max()
+    # the truncated model's trajectory differs (the phi/Phi term acts)
+    trt = oracle.leapfrog(x, p, y, 0.8, eps, 1, mask=mask)
+    assert np.abs(trt.p - tr.p).max() > 1e-9
+    errs = []
+    for e in (4e-3, 2e-3, 1e-3):
+        t = oracle.leapfrog(x, p, y, 0.8, e, int(round(0.04 / e)), mask=mask, truncated=False)
+        errs.append(abs(t.energy_end - t.energy_start))
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_untruncated_hmc_step_is_its_leapfrog():
+    # an accepted transition of the model without truncation ends where the
+    # leapfrog from its momentum draw ends
+    x, y, mask = _rand_problem(10, 2, 0.9, 32)
+    st = oracle.hmc_step(x, y, 0.9, 1e-3, 5, seed=9, iteration=2, mask=mask, truncated=False)
+    assert st.accepted
+    mom = oracle.momentum(10, 2, 9, 2)
+    tr = oracle.leapfrog(x, mom, y, 0.9, 1e-3, 5, mask=mask, truncated=False)
+    assert np.array_equal(st.x, tr.x)
+    assert st.loglik == tr.loglik_end
+
+
 # --------------------------------------------- held-out predictive density ----
 
 def _heldout_case(seed, n=7, d=2, frac=0.4):
