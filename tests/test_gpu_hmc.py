@@ -116,6 +116,29 @@ def test_rejection_restores_state_bitwise():
     assert torch.equal(x, x0) and torch.equal(g, g0) and torch.equal(L, L0)
 
 
+def test_chain_untruncated_matches_oracle():
+    """Transitions of the model without truncation (the MDS_UNTRUNCATED flag
+    of mds_hmc_step) against the oracle's, in the spatial labelling."""
+    pr = synth.preset("small_fp64", missing=0.1)
+    P = api.MDSProblem(pr.y, pr.d, pr.mask, torch.float64, DEV, order=pr.x, truncated=False)
+    x, y, mask = _labelled(P, pr)
+    seed, its, eps, steps = 78, list(range(10, 14)), 0.02, 8
+    got = _gpu_chain(P, x, pr.sigma, eps, steps, seed, its)
+    for k, it in enumerate(its):
+        ref = oracle.hmc_step(x, y, pr.sigma, eps, steps, seed, it, mask=mask, truncated=False)
+        h0, h1, lu, acc = got[k]["stats"]
+        margin = abs(ref.log_u - (ref.energy_start - ref.energy_end))
+        _log(f"untruncated transition {it}: accepted {ref.accepted}/{bool(acc)} "
+             f"margin {margin:.2e}")
+        assert abs(h0 - ref.energy_start) <= 1e-11 * abs(ref.energy_start)
+        assert abs(h1 - ref.energy_end) <= 1e-11 * abs(ref.energy_end)
+        if margin >= 1e-8 * abs(ref.energy_start):
+            assert bool(acc) == ref.accepted
+            assert np.abs(got[k]["x"] - ref.x).max() <= 1e-12 * np.abs(ref.x).max()
+            assert abs(got[k]["L"] - ref.loglik) <= 1e-11 * abs(ref.loglik)
+        x = got[k]["x"]          # continue from the device's state
+
+
 def test_chain_graph_replays_match_eager():
     pr = synth.make_problem(400, 2, 0.6, seed=9, missing=0.1)
     P = api.MDSProblem(pr.y, 2, pr.mask, torch.float64, DEV, order=pr.x)

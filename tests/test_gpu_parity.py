@@ -363,6 +363,33 @@ def test_leapfrog_small_preset_parity():
     assert abs(got["e1"] - ref.energy_end) <= 1e-11 * abs(ref.energy_end)
 
 
+@pytest.mark.parametrize("ordered", [False, True])
+def test_leapfrog_untruncated_parity(ordered):
+    """The leapfrog on the model without truncation (the MDS_UNTRUNCATED flag
+    of mds_leapfrog), in both labellings, against the oracle's."""
+    p = synth.preset("small_fp64", missing=0.1)
+    mom = np.random.default_rng(31).standard_normal((p.n, p.d))
+    ref = oracle.leapfrog(p.x, mom, p.y, p.sigma, eps=1e-3, n_steps=20, mask=p.mask,
+                          truncated=False)
+    P = api.MDSProblem(p.y, p.d, p.mask, torch.float64, DEV, truncated=False,
+                       order=p.x if ordered else None)
+    xr = P.relabel(p.x).cpu().numpy()
+    mr = P.relabel(mom).cpu().numpy()
+    got = _lf_gpu(P, xr, mr, p.sigma, 1e-3, 20, energies=True)
+    unl = (lambda a: P.unlabel(torch.as_tensor(a, device=DEV)).cpu().numpy())
+    gx, gp, gg = unl(got["x"]), unl(got["p"]), unl(got["g"])
+    ev = oracle.evaluate(ref.x, p.y, p.sigma, p.mask, truncated=False)
+    ptol = TOL64 * 1e-3 * 21 * np.max(ev.condrow)
+    _log(f"untruncated leapfrog ordered={ordered}: max |dx| {np.abs(gx - ref.x).max():.2e} "
+         f"max |dp| {np.abs(gp - ref.p).max():.2e} (tol {ptol:.2e})")
+    assert np.abs(gx - ref.x).max() <= 1e-12 * np.abs(ref.x).max()
+    assert np.abs(gp - ref.p).max() <= ptol
+    assert np.all(np.max(np.abs(gg - ref.grad_end), axis=1) <= 1e-10 * ev.condrow)
+    assert abs(got["L"] - ref.loglik_end) <= 1e-11 * abs(ref.loglik_end)
+    assert abs(got["e0"] - ref.energy_start) <= 1e-11 * abs(ref.energy_start)
+    assert abs(got["e1"] - ref.energy_end) <= 1e-11 * abs(ref.energy_end)
+
+
 def test_leapfrog_cache_and_prior_and_mass():
     x, y, mask, sigma = _rand(300, 3, seed=31, nan_frac=0)
     mom = np.random.default_rng(31).standard_normal((300, 3))
