@@ -350,8 +350,8 @@ int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count,
 typedef struct mds_problem_desc {
     int64_t n;             /* locations */
     int32_t d;             /* latent dimension, 1..MDS_MAX_DIM */
-    int32_t tile_rows;     /* rows per tile (32/64/128/256), 0 = default for (dtype, d, n) */
-    const double* x;       /* N x D FP64, leading dimension ldx */
+    int32_t tile_rows;     /* rows per tile (8/16/32/64/128/256), 0 = default for (dtype, d, n) */
+    const double* x;       /* N x D FP64, leading dimension ldx (moved by mds_batch_leapfrog) */
     int64_t ldx;
     const void* y;         /* prepared Y, the batch's y_dtype, leading dimension ldy */
     int64_t ldy;
@@ -362,6 +362,12 @@ typedef struct mds_problem_desc {
     double* loglik;        /* optional device doubles */
     double* dsigma;
     double* dlogsigma;
+    /* leapfrog (mds_batch_leapfrog only; NULL otherwise): momenta N x D FP64
+       (leading dimension ldp, updated in place) and the step size eps as a
+       device double */
+    double* p;
+    int64_t ldp;
+    const double* step;
 } mds_problem_desc;
 
 /* What mds_batch_init leaves for mds_batch_eval: plain sizes and the
@@ -372,7 +378,7 @@ typedef struct mds_batch_plan {
     int32_t tile_waves;
     int32_t grid;            /* persistent work-groups */
     int32_t max_d;           /* largest D of the batch */
-    int32_t reserved;
+    int32_t flags;           /* bit 0: every problem has momenta, step, grad and loglik */
     int64_t total_tiles;
     int64_t elem_blocks;
     size_t lds_bytes;
@@ -401,6 +407,22 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
                    int32_t tile_waves, void* workspace, size_t workspace_bytes,
                    mds_batch_plan* plan, hipStream_t stream);
 int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t stream);
+
+/*
+ * Leapfrog trajectories (Section 2.3, Eqs. 6-8; unit mass, no prior) of
+ * n_steps steps for every problem of the batch at once: each step is one
+ * persistent batched sweep and one batched finalize that applies the kick
+ * p += c eps grad and the drift x += eps p.  Every problem needs p, ldp >= d,
+ * step, grad and loglik in its descriptor (plan->flags bit 0), else
+ * MDS_ERR_INVALID_ARGUMENT.  x and p move in place; grad and loglik end at
+ * the final x.  cache_valid != 0: grad holds grad L at the incoming x (the
+ * previous trajectory's end) and the first evaluation is skipped.  Each
+ * problem's x, p and gradient match mds_leapfrog on that problem alone with
+ * the same tiling (unit mass, no prior), bit for bit.  Launches only: can be
+ * captured in a graph.
+ */
+int mds_batch_leapfrog(const mds_batch_plan* plan, int32_t n_steps, int32_t cache_valid,
+                       hipStream_t stream);
 
 /*
  * Diagnostics for benchmarks: while set (non-NULL), every single-problem

@@ -42,13 +42,14 @@ class ProblemDesc(ctypes.Structure):
     """mirror of mds_problem_desc"""
     _fields_ = [("n", _c_i64), ("d", _c_i32), ("tile_rows", _c_i32), ("x", _vp), ("ldx", _c_i64),
                 ("y", _vp), ("ldy", _c_i64), ("sigma", _vp), ("scale", _vp), ("grad", _vp),
-                ("ldg", _c_i64), ("loglik", _vp), ("dsigma", _vp), ("dlogsigma", _vp)]
+                ("ldg", _c_i64), ("loglik", _vp), ("dsigma", _vp), ("dlogsigma", _vp),
+                ("p", _vp), ("ldp", _c_i64), ("step", _vp)]
 
 
 class BatchPlan(ctypes.Structure):
     """mirror of mds_batch_plan"""
     _fields_ = [("count", _c_i32), ("y_dtype", _c_i32), ("tile_waves", _c_i32), ("grid", _c_i32),
-                ("max_d", _c_i32), ("reserved", _c_i32), ("total_tiles", _c_i64), ("elem_blocks", _c_i64), ("lds_bytes", ctypes.c_size_t),
+                ("max_d", _c_i32), ("flags", _c_i32), ("total_tiles", _c_i64), ("elem_blocks", _c_i64), ("lds_bytes", ctypes.c_size_t),
                 ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -137,6 +138,8 @@ def lib():
                                  ctypes.c_size_t, ctypes.POINTER(BatchPlan), _vp]
     L.mds_batch_eval.restype = ctypes.c_int
     L.mds_batch_eval.argtypes = [ctypes.POINTER(BatchPlan), _c_i32, _vp]
+    L.mds_batch_leapfrog.restype = ctypes.c_int
+    L.mds_batch_leapfrog.argtypes = [ctypes.POINTER(BatchPlan), _c_i32, _c_i32, _vp]
     _lib = L
     return L
 
@@ -535,9 +538,10 @@ class MDSBatch:
     dtype     Y storage/arithmetic (float32 or float64), common to the batch
 
     The batch owns static device buffers that the kernels read and write:
-    ``x[k]`` (N_k x D_k, write your positions there), ``grad[k]``, and the
-    per-problem scalars ``sigma``, ``scale``, ``loglik``, ``dsigma``,
-    ``dlogsigma`` (float64 tensors of length count).
+    ``x[k]`` (N_k x D_k, write your positions there), ``grad[k]``, the
+    momenta ``p[k]`` of ``leapfrog``, and the per-problem scalars ``sigma``,
+    ``scale``, ``loglik``, ``dsigma``, ``dlogsigma`` and ``step`` (float64
+    tensors of length count).
     """
 
     def __init__(self, problems, dtype=torch.float32, device="cuda", tile_waves: int = 0,
@@ -550,10 +554,12 @@ class MDSBatch:
         count = len(problems)
         self.count = count
         self.ys, self.m_obs, self.x, self.grad = [], [], [], []
-        self._scal = torch.zeros((5, count), **f64)
-        self.sigma, self.scale, self.loglik, self.dsigma, self.dlogsigma = self._scal
+        self._scal = torch.zeros((6, count), **f64)
+        self.sigma, self.scale, self.loglik, self.dsigma, self.dlogsigma, self.step = self._scal
         self.sigma.fill_(1.0)
         self.scale.fill_(1.0)
+        self.step.fill_(1e-3)
+        self.p = []
         descs = (ProblemDesc * count)()
         for k, pr in enumerate(problems):
             y = torch.as_tensor(pr["y"])
@@ -567,10 +573,12 @@ class MDSBatch:
             n, d = y.shape[0], int(pr["d"])
             xk = torch.zeros((n, d), **f64)
             gk = torch.zeros((n, d), **f64)
+            pk = torch.zeros((n, d), **f64)
             self.ys.append(yp)
             self.m_obs.append(mo)
             self.x.append(xk)
             self.grad.append(gk)
+            self.p.append(pk)
             q = descs[k]
             q.n, q.d, q.tile_rows = n, d, int(pr.get("tile_rows", 0))
             q.x, q.ldx = xk.data_ptr(), max(d, 1)
@@ -581,6 +589,8 @@ class MDSBatch:
             q.loglik = self.loglik.data_ptr() + 8 * k
             q.dsigma = self.dsigma.data_ptr() + 8 * k
             q.dlogsigma = self.dlogsigma.data_ptr() + 8 * k
+            q.p, q.ldp = pk.data_ptr(), max(d, 1)
+            q.step = self.step.data_ptr() + 8 * k
         self._descs = descs
         code = _dtype_code(dtype) | (0 if truncated else MDS_UNTRUNCATED)
         nb = ctypes.c_size_t(0)
@@ -598,6 +608,14 @@ class MDSBatch:
     def eval(self, want_grad: bool = True, stream=None):
         _check(lib().mds_batch_eval(ctypes.byref(self.plan), 1 if want_grad else 0,
                                     _stream(stream)), "mds_batch_eval")
+
+    def leapfrog(self, n_steps: int, cache_valid: bool = False, stream=None):
+        """Leapfrog trajectories of n_steps steps for every problem at once
+        (``mds_batch_leapfrog``): x[k] and p[k] move in place, grad[k] and
+        loglik[k] end at the final positions; step[k] is eps."""
+        _check(lib().mds_batch_leapfrog(ctypes.byref(self.plan), int(n_steps),
+                                        1 if cache_valid else 0, _stream(stream)),
+               "mds_batch_leapfrog")
 
 
 def _autotuned_batch(problems, dtype, device, tile_waves):

@@ -786,6 +786,7 @@ int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count, in
 namespace {
 
 constexpr int kFinElemsPerBlock = 64;  // finalize element block (one wave wide)
+constexpr int32_t kBatchLeapfrogReady = 1;  // mds_batch_plan.flags bit 0
 
 struct BatchLayout {
     size_t table;   // BatchProblem[count]
@@ -817,8 +818,12 @@ static int batch_layout(const mds_problem_desc* descs, int32_t count, int32_t y_
         if (st) return fail(st, "problem %d: %s", k, std::string(g_last_error).c_str());
         if (q.grad && q.ldg < q.d) return fail(MDS_ERR_INVALID_ARGUMENT, "problem %d: ldg < d", k);
         if (!aligned(q.grad, 8) || !aligned(q.loglik, 8) || !aligned(q.dsigma, 8) ||
-            !aligned(q.dlogsigma, 8) || !aligned(q.scale, 8))
+            !aligned(q.dlogsigma, 8) || !aligned(q.scale, 8) || !aligned(q.p, 8) ||
+            !aligned(q.step, 8))
             return fail(MDS_ERR_INVALID_ARGUMENT, "problem %d: misaligned pointer", k);
+        if (q.p && q.ldp < q.d) return fail(MDS_ERR_INVALID_ARGUMENT, "problem %d: ldp < d", k);
+        if (q.n > 0 && q.p && (q.p == q.x || q.p == q.grad || q.x == q.grad))
+            return fail(MDS_ERR_INVALID_ARGUMENT, "problem %d: x, p and grad must not alias", k);
         Tiling t;
         if ((st = resolve_tiling(q.n, q.d, y_dtype, q.tile_rows, waves, &t)))
             return fail(st, "problem %d: %s", k, std::string(g_last_error).c_str());
@@ -889,6 +894,7 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
     BatchProblem* tab = reinterpret_cast<BatchProblem*>(img.data());
     char* base = static_cast<char*>(workspace);
     int64_t tiles = 0, blocks = 0;
+    int leapfrog_ready = 1;
     for (int32_t k = 0; k < count; ++k) {
         const mds_problem_desc& q = descs[k];
         const Tiling& t = L.tilings[k];
@@ -906,7 +912,12 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
         P.loglik = q.loglik;
         P.dsigma = q.dsigma;
         P.dlogsigma = q.dlogsigma;
+        P.x = const_cast<double*>(q.x);
+        P.p = q.p;
+        P.ldp = q.ldp;
+        P.step = q.step;
         tab[k] = P;
+        if (!q.step || !q.loglik || (q.n > 0 && (!q.p || !q.grad))) leapfrog_ready = 0;
         tiles += t.ntiles;
         blocks += P.nblk;
     }
@@ -921,7 +932,7 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
     const int per_cu = batch_sweep_blocks_per_cu(y_dtype, true, max_d, waves, max_lds);
     plan->count = count;
     plan->max_d = max_d;
-    plan->reserved = 0;
+    plan->flags = leapfrog_ready ? kBatchLeapfrogReady : 0;
     plan->y_dtype = y_dtype;
     plan->tile_waves = waves;
     plan->grid = cus * per_cu;
@@ -950,9 +961,50 @@ int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t st
     if (e != hipSuccess) return hip_fail(e, "batch sweep launch");
     if (g_ev_after && (e = hipEventRecord(g_ev_after, stream)) != hipSuccess)
         return hip_fail(e, "event record");
-    e = launch_batch_finalize(probs, plan->count, want_grad ? plan->elem_blocks : 0, cursor,
-                              stream);
+    e = launch_batch_finalize(probs, plan->count, want_grad ? plan->elem_blocks : 0, cursor, 0.0,
+                              0, 0, stream);
     if (e != hipSuccess) return hip_fail(e, "batch finalize launch");
+    return MDS_OK;
+}
+
+int mds_batch_leapfrog(const mds_batch_plan* plan, int32_t n_steps, int32_t cache_valid,
+                       hipStream_t stream)
+{
+    if (!plan || !plan->workspace || plan->count < 1)
+        return fail(MDS_ERR_INVALID_ARGUMENT, "plan is not initialised");
+    if (!(plan->flags & kBatchLeapfrogReady))
+        return fail(MDS_ERR_INVALID_ARGUMENT,
+                    "every problem needs p, step, grad and loglik for the leapfrog");
+    if (n_steps < 0) return fail(MDS_ERR_INVALID_ARGUMENT, "n_steps=%d < 0", n_steps);
+    char* base = static_cast<char*>(plan->workspace);
+    const BatchProblem* probs = reinterpret_cast<const BatchProblem*>(base);
+    unsigned long long* cursor = reinterpret_cast<unsigned long long*>(
+        base + align_up(sizeof(BatchProblem) * (size_t)plan->count, 256));
+    // grad L and L at the current x of every problem, then the fused update
+    auto evaluate = [&](double mult, int kick, int drift) -> int {
+        hipError_t err = launch_batch_sweep(plan->y_dtype, true, plan->max_d, probs, plan->count,
+                                            plan->total_tiles, cursor, plan->tile_waves,
+                                            plan->lds_bytes, plan->grid, stream);
+        if (err != hipSuccess) return hip_fail(err, "batch sweep launch");
+        err = launch_batch_finalize(probs, plan->count, plan->elem_blocks, cursor, mult, kick,
+                                    drift, stream);
+        if (err != hipSuccess) return hip_fail(err, "batch finalize launch");
+        return MDS_OK;
+    };
+    int st;
+    // the same sequence as mds_leapfrog: half kick and drift (fused into the
+    // first evaluation unless the gradient is cached), full steps, half kick
+    const bool fuse_first = !cache_valid && n_steps > 0;
+    if (!cache_valid && (st = evaluate(0.5, fuse_first ? 1 : 0, fuse_first ? 1 : 0))) return st;
+    if (n_steps > 0 && !fuse_first) {
+        hipError_t e = launch_batch_kick_drift(probs, plan->count, plan->elem_blocks, 0.5, 1,
+                                               stream);
+        if (e != hipSuccess) return hip_fail(e, "batch kick launch");
+    }
+    for (int s = 1; s <= n_steps; ++s) {
+        const bool last = (s == n_steps);
+        if ((st = evaluate(last ? 0.5 : 1.0, 1, last ? 0 : 1))) return st;
+    }
     return MDS_OK;
 }
 

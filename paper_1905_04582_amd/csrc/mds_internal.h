@@ -185,6 +185,10 @@ struct BatchProblem {
     double* loglik;
     double* dsigma;
     double* dlogsigma;
+    double* x;            // the problem's positions (drifted by the leapfrog)
+    double* p;            // momenta (leapfrog only)
+    int64_t ldp;
+    const double* step;   // eps (leapfrog only)
 };
 
 // launchers (return hipError_t of the launch)
@@ -197,7 +201,14 @@ hipError_t launch_batch_sweep(int y_dtype, bool grad, int maxd, const BatchProbl
                               int32_t count, int64_t total_tiles, unsigned long long* cursor,
                               int waves, size_t lds, int grid, hipStream_t s);
 int batch_sweep_blocks_per_cu(int y_dtype, bool grad, int maxd, int waves, size_t lds);
+// kick_mult / kick / drift: the leapfrog update fused into the finalize
+// (p += kick_mult eps g when kick, then x += eps p when drift); 0, 0, 0 for
+// a plain evaluation
 hipError_t launch_batch_finalize(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
-                                 unsigned long long* cursor, hipStream_t s);
+                                 unsigned long long* cursor, double kick_mult, int kick, int drift,
+                                 hipStream_t s);
+// p += kick_mult eps g, then x += eps p (drift != 0), every problem's elements
+hipError_t launch_batch_kick_drift(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
+                                   double kick_mult, int drift, hipStream_t s);
 
 }  // namespace mds

@@ -233,7 +233,8 @@ __global__ void __launch_bounds__(kWave * kFinChunks) finalize_kernel(FinalizeAr
 // call (this kernel runs after the sweep on the same stream).
 __global__ void __launch_bounds__(kWave * kFinChunks)
     batch_finalize_kernel(const BatchProblem* __restrict__ probs, int32_t count,
-                          int64_t elem_blocks, unsigned long long* cursor)
+                          int64_t elem_blocks, unsigned long long* cursor, double kick_mult,
+                          int kick, int drift)
 {
     int64_t b = blockIdx.x;
     int k;
@@ -268,6 +269,15 @@ __global__ void __launch_bounds__(kWave * kFinChunks)
     a.loglik = P.loglik;
     a.dsigma = P.dsigma;
     a.dlogsigma = P.dlogsigma;
+    if (kick) {
+        a.x = P.x;
+        a.ldx = P.sweep.ldx;
+        a.p = P.p;
+        a.ldp = P.ldp;
+        a.step = P.step;
+        a.kick_mult = kick_mult;
+        a.drift = drift;
+    }
     const double scale = P.scale ? *P.scale : 1.0;
     if (b < elem_blocks)
         finalize_elements(a, P.d, b - P.blk_base, scale);
@@ -276,11 +286,49 @@ __global__ void __launch_bounds__(kWave * kFinChunks)
 }
 
 hipError_t launch_batch_finalize(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
-                                 unsigned long long* cursor, hipStream_t s)
+                                 unsigned long long* cursor, double kick_mult, int kick, int drift,
+                                 hipStream_t s)
 {
     const unsigned nblk = (unsigned)(elem_blocks + count);
     hipLaunchKernelGGL(batch_finalize_kernel, dim3(nblk), dim3(kWave * kFinChunks), 0, s, probs,
-                       count, elem_blocks, cursor);
+                       count, elem_blocks, cursor, kick_mult, kick, drift);
+    return hipGetLastError();
+}
+
+// one work-group of 64 threads per finalize element block (64 consecutive
+// elements of one problem): p += kick_mult eps g, then x += eps p
+__global__ void __launch_bounds__(kWave)
+    batch_kick_drift_kernel(const BatchProblem* __restrict__ probs, int32_t count,
+                            double kick_mult, int drift)
+{
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].blk_base <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchProblem& P = probs[lo];
+    const int D = P.d;
+    const int64_t e = (b - P.blk_base) * kWave + threadIdx.x;
+    if (e >= P.sweep.n * D) return;
+    const int64_t k = e / D;
+    const int d = (int)(e - k * D);
+    const double eps = *P.step;
+    double* pp = P.p + k * P.ldp + d;
+    const double pn = *pp + kick_mult * eps * P.grad[k * P.ldg + d];
+    *pp = pn;
+    if (drift) P.x[k * P.sweep.ldx + d] += eps * pn;
+}
+
+hipError_t launch_batch_kick_drift(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
+                                   double kick_mult, int drift, hipStream_t s)
+{
+    if (elem_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_kick_drift_kernel, dim3((unsigned)elem_blocks), dim3(kWave), 0, s,
+                       probs, count, kick_mult, drift);
     return hipGetLastError();
 }
 

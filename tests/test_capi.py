@@ -352,3 +352,23 @@ def test_batch_rejects():
     assert L.mds_batch_init(d, 2, 0, 0, _p(), 1 << 30, None, None) == ERR_ARG
     assert L.mds_batch_eval(None, 1, None) == ERR_ARG
     assert L.mds_batch_eval(ctypes.byref(api.BatchPlan()), 1, None) == ERR_ARG
+    # leapfrog fields
+    d[1].grad = FAKE + 8192
+    d[1].p, d[1].ldp = FAKE + 4096, 1                 # ldp < d
+    assert L.mds_batch_workspace_bytes(d, 2, 0, 0, ctypes.byref(nb)) == ERR_ARG
+    d[1].ldp = 2
+    d[1].step = FAKE + 3                              # misaligned step
+    assert L.mds_batch_workspace_bytes(d, 2, 0, 0, ctypes.byref(nb)) == ERR_ARG
+    d[1].step = FAKE + 8
+    d[1].p = d[1].grad                                # momenta alias the gradient
+    assert L.mds_batch_workspace_bytes(d, 2, 0, 0, ctypes.byref(nb)) == ERR_ARG
+    d[1].p = FAKE + 4096
+    assert L.mds_batch_workspace_bytes(d, 2, 0, 0, ctypes.byref(nb)) == 0
+    assert L.mds_batch_leapfrog(None, 20, 0, None) == ERR_ARG
+    assert L.mds_batch_leapfrog(ctypes.byref(api.BatchPlan()), 20, 0, None) == ERR_ARG
+    # an initialised plan without momenta in every problem is rejected
+    pl = api.BatchPlan()
+    pl.count, pl.workspace, pl.flags = 2, FAKE, 0
+    assert L.mds_batch_leapfrog(ctypes.byref(pl), 20, 0, None) == ERR_ARG
+    pl.flags = 1
+    assert L.mds_batch_leapfrog(ctypes.byref(pl), -1, 0, None) == ERR_ARG

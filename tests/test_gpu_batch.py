@@ -120,3 +120,94 @@ def test_batched_workload_64_problems():
                                p.mask)
     err = np.max(np.abs(B.grad[small].cpu().numpy()[rows] - g), axis=1) / b
     assert err.max() < 1e-5
+
+
+# ------------------------------------------------------------ leapfrog ----
+
+def _start(B, probs, seed):
+    rng = np.random.default_rng(seed)
+    moms = []
+    for k, p in enumerate(probs):
+        m = rng.standard_normal((p.n, p.d))
+        B.p[k].copy_(torch.as_tensor(m))
+        B.step[k] = float(rng.uniform(5e-4, 2e-3))
+        moms.append(m)
+    return moms
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_leapfrog_equals_single_calls_bitwise(dtype):
+    probs, B = _build(_mixed_specs(5, 9), dtype)
+    moms = _start(B, probs, 5)
+    B.leapfrog(7)
+    B.leapfrog(4, cache_valid=True)
+    torch.cuda.synchronize()
+    for k, p in enumerate(probs):
+        P = api.MDSProblem(p.y.astype(np.float32) if dtype == torch.float32 else p.y, p.d,
+                           p.mask, dtype, DEV, 0, 4)
+        x = torch.as_tensor(p.x, dtype=torch.float64, device=DEV).clone()
+        pm = torch.as_tensor(moms[k], dtype=torch.float64, device=DEV).clone()
+        g = torch.empty_like(x)
+        L = torch.empty((), dtype=torch.float64, device=DEV)
+        st = B.step[k].clone()
+        P.leapfrog(x, pm, p.sigma, st, 7, g, L)
+        P.leapfrog(x, pm, p.sigma, st, 4, g, L, cache_valid=True)
+        torch.cuda.synchronize()
+        assert torch.equal(x, B.x[k]) and torch.equal(pm, B.p[k]), k
+        assert torch.equal(g, B.grad[k]) and L.item() == B.loglik[k].item(), k
+
+
+def test_batch_leapfrog_vs_oracle():
+    probs, B = _build(_mixed_specs(6, 8), torch.float64)
+    moms = _start(B, probs, 6)
+    B.leapfrog(20)
+    torch.cuda.synchronize()
+    for k, p in enumerate(probs):
+        eps = B.step[k].item()
+        ref = oracle.leapfrog(p.x, moms[k], p.y, p.sigma, eps=eps, n_steps=20, mask=p.mask)
+        gx, gp = B.x[k].cpu().numpy(), B.p[k].cpu().numpy()
+        if p.n == 0:
+            continue
+        ev = oracle.evaluate(ref.x, p.y, p.sigma, p.mask)
+        ptol = 1e-12 * eps * 21 * max(np.max(ev.condrow), 1e-300) + 1e-300
+        assert np.abs(gx - ref.x).max() <= 1e-12 * max(np.abs(ref.x).max(), 1e-300), k
+        assert np.abs(gp - ref.p).max() <= ptol, k
+        assert abs(B.loglik[k].item() - ref.loglik_end) <= \
+            1e-11 * max(abs(ref.loglik_end), 1e-300) + 1e-300, k
+
+
+def test_batch_leapfrog_graph_replays():
+    # 20-step trajectories of the whole batch captured once, replayed; each
+    # replay continues from the last (cached gradient) and equals the eager
+    # batch run step for step
+    probs, B = _build(_mixed_specs(7, 8), torch.float32)
+    _start(B, probs, 7)
+    B.leapfrog(0)                                  # gradient at the start
+    probs2, E = _build(_mixed_specs(7, 8), torch.float32)
+    _start(E, probs2, 7)
+    E.leapfrog(0)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    G = torch.cuda.CUDAGraph()
+    x0 = [x.clone() for x in B.x]
+    p0 = [p.clone() for p in B.p]
+    with torch.cuda.stream(side):
+        B.leapfrog(20, cache_valid=True)           # warm the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for k in range(B.count):                       # back to the start
+        B.x[k].copy_(x0[k])
+        B.p[k].copy_(p0[k])
+    B.leapfrog(0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(G):
+        B.leapfrog(20, cache_valid=True)
+    for rep in range(3):
+        G.replay()
+        E.leapfrog(20, cache_valid=True)
+        torch.cuda.synchronize()
+        for k in range(B.count):
+            assert torch.equal(B.x[k], E.x[k]) and torch.equal(B.p[k], E.p[k]), (rep, k)
+            assert torch.equal(B.grad[k], E.grad[k]), (rep, k)
+        assert torch.equal(B.loglik, E.loglik), rep
