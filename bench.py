@@ -14,6 +14,9 @@ lets most wavefronts skip the truncation terms; the outputs are the same up
 to rounding, with the gradient rows in the new labelling.  Besides the FP64
 figure (the headline `value`) the line carries the FP32 form on the same
 data, both forms in the original labelling, one 20-step leapfrog trajectory,
+100 HMC transitions, the held-out predictive density, the model without
+truncation, the batched form (64 problems of uneven N and D, one persistent
+launch per evaluation, graph-captured 20-step trajectories of the batch),
 the sweep kernel's roofline (each launch of a second pass of the same K
 steps timed by HIP events attached to the kernel's own start and end; the
 events stay out of the wall-clock pass, whose steps they would slow) and the
@@ -428,6 +431,82 @@ def main():
                "ms_per_draw": round(lpd_draw_ms, 5),
                "pairs_per_s": round(H.m / (lpd_draw_ms * 1e-3), 1), "lpd": lpd_val}
 
+    # batched form: 64 independent problems, N ~ U[500, 8000], D in {2, 4, 6},
+    # sigma ~ U(0.2, 1), 10% missing, FP32 Y drawn in device memory; one
+    # persistent sweep and one finalize per evaluation of the whole batch, and
+    # 20-step leapfrog trajectories of every problem captured as one graph
+    specs = synth.batch_specs(64, seed=64)
+    ys, xs = [], []
+    for sp in specs:
+        _, xk, yk = synth.device_problem(sp["n"], sp["d"], sp["sigma"], seed=sp["seed"], device=dev,
+                                         dtype=torch.float32, missing=sp["missing"])
+        ys.append(yk)
+        xs.append(xk)
+    B = api.MDSBatch([dict(y=yk, d=sp["d"], order=xk) for yk, xk, sp in zip(ys, xs, specs)],
+                     torch.float32, dev)
+    del ys
+    torch.cuda.empty_cache()
+    for k, sp in enumerate(specs):
+        B.set_x(k, xs[k])
+        B.sigma[k] = sp["sigma"]
+    bpairs = sum(sp["n"] * (sp["n"] - 1) // 2 for sp in specs)
+    for _ in range(3):
+        B.eval()
+    torch.cuda.synchronize()
+    breps = 20
+    t0 = time.perf_counter()
+    for _ in range(breps):
+        B.eval()
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) * 1e3 / breps
+    ev_pairs = [(events.create(), events.create()) for _ in range(breps)]
+    for a, b in ev_pairs:
+        api.mds_set_sweep_events(a, b)
+        B.eval()
+    api.mds_set_sweep_events(None, None)
+    torch.cuda.synchronize()
+    bsweep = sorted(events.elapsed_ms(a, b) for a, b in ev_pairs)
+    bsweep_mean = sum(bsweep) / len(bsweep)
+    for a, b in ev_pairs:
+        events.destroy(a)
+        events.destroy(b)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    for k in range(B.count):
+        B.p[k].copy_(torch.randn(B.p[k].shape, generator=gen, dtype=torch.float64, device=dev))
+    B.step.fill_(1e-3)
+    B.leapfrog(0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.leapfrog(20, cache_valid=True)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    G = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(G):
+        B.leapfrog(20, cache_valid=True)
+    G.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        G.replay()
+    torch.cuda.synchronize()
+    btraj_ms = (time.perf_counter() - t0) * 1e3 / 5
+    batched = {
+        "problems": B.count, "pairs": bpairs, "dtype": "f32",
+        "ms_per_batch_eval": round(batch_ms, 4),
+        "sweep_ms_mean": round(bsweep_mean, 4),
+        "gpairs_per_s": round(bpairs / (batch_ms * 1e-3) / 1e9, 2),
+        "y_stream_gbs": round(bpairs * 4 / (bsweep_mean * 1e-3) / 1e9, 1),
+        "y_stream_frac": round(bpairs * 4 / (bsweep_mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "leapfrog_20_steps_graph_ms": round(btraj_ms, 3),
+        "workload": "64 problems, N ~ U[500, 8000], D in {2,4,6}, sigma ~ U(0.2,1), 10% "
+                    "missing, FP32 Y drawn in device memory; each problem relabelled in "
+                    "the spatial order of its locations",
+    }
+    del B, G, xs
+    torch.cuda.empty_cache()
+
     # the model without truncation (the paper's comparison of the two): the
     # same sweep with the special functions left out, and the oracle's time
     # for it on one core
@@ -517,6 +596,7 @@ def main():
         "original_labelling": plain,
         "untruncated_model": abl,
         "heldout_lpd": heldout,
+        "batched_form": batched,
         "leapfrog": {"steps": 20, "step_size": 1e-3, "ms_per_trajectory": round(traj_ms, 4),
                      "gradient_evals": 20},
         "hmc": {"transitions": 100, "leapfrog_steps": 20, "step_size": 1e-3,

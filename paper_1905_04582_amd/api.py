@@ -542,6 +542,11 @@ class MDSBatch:
     momenta ``p[k]`` of ``leapfrog``, and the per-problem scalars ``sigma``,
     ``scale``, ``loglik``, ``dsigma``, ``dlogsigma`` and ``step`` (float64
     tensors of length count).
+
+    A problem dict may carry ``order`` (N x D locations, e.g. the starting
+    X): that problem is then stored relabelled in their spatial order
+    (``perm[k]``), and x[k], p[k], grad[k] are in that labelling --
+    ``relabel(k, a)`` / ``unlabel(k, a)`` convert N x D arrays.
     """
 
     def __init__(self, problems, dtype=torch.float32, device="cuda", tile_waves: int = 0,
@@ -553,7 +558,7 @@ class MDSBatch:
         f64 = dict(dtype=torch.float64, device=self.device)
         count = len(problems)
         self.count = count
-        self.ys, self.m_obs, self.x, self.grad = [], [], [], []
+        self.ys, self.m_obs, self.x, self.grad, self.perm = [], [], [], [], []
         self._scal = torch.zeros((6, count), **f64)
         self.sigma, self.scale, self.loglik, self.dsigma, self.dlogsigma, self.step = self._scal
         self.sigma.fill_(1.0)
@@ -568,7 +573,13 @@ class MDSBatch:
             m = pr.get("mask")
             if m is not None:
                 m = (torch.as_tensor(m) != 0).to(device=self.device, dtype=torch.uint8).contiguous()
-            yp, mo = mds_prepare_y(src, dtype, m, stream=stream)
+            perm = None
+            if pr.get("order") is not None:
+                xo = torch.as_tensor(pr["order"]).to(device=self.device,
+                                                     dtype=torch.float64).contiguous()
+                perm = mds_spatial_order(xo, stream=stream)
+            self.perm.append(perm)
+            yp, mo = mds_prepare_y(src, dtype, m, perm=perm, stream=stream)
             del src, m
             n, d = y.shape[0], int(pr["d"])
             xk = torch.zeros((n, d), **f64)
@@ -603,7 +614,17 @@ class MDSBatch:
                                     _stream(stream)), "mds_batch_init")
 
     def set_x(self, k, x):
-        self.x[k].copy_(torch.as_tensor(x, dtype=torch.float64))
+        """x in the problem's own (original) labelling."""
+        self.x[k].copy_(self.relabel(k, x))
+
+    def relabel(self, k, a):
+        """N x D array in problem k's original labelling -> its stored labelling."""
+        a = torch.as_tensor(a).to(device=self.device, dtype=torch.float64).contiguous()
+        return a if self.perm[k] is None else mds_permute_rows(a, self.perm[k], False)
+
+    def unlabel(self, k, a):
+        """N x D array in problem k's stored labelling -> its original labelling."""
+        return a.clone() if self.perm[k] is None else mds_permute_rows(a, self.perm[k], True)
 
     def eval(self, want_grad: bool = True, stream=None):
         _check(lib().mds_batch_eval(ctypes.byref(self.plan), 1 if want_grad else 0,

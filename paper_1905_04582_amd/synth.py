@@ -140,7 +140,8 @@ def make_problem(n: int, d: int, sigma: float, *, seed: int = 0, missing: float 
 
 
 def device_problem(n: int, d: int, sigma: float, *, seed: int = 0, dtype=None,
-                   device="cuda", eval_noise: float = 0.1, block_rows: int = 1024):
+                   device="cuda", eval_noise: float = 0.1, block_rows: int = 1024,
+                   missing: float = 0.0):
     """A problem of the same recipe (no missing pairs, no duplicates) whose
     symmetric Y is drawn directly in device memory, for sizes where the host
     recipe would take minutes (N = 10^5: 10^10 entries, 80 GB in FP64).
@@ -150,9 +151,11 @@ def device_problem(n: int, d: int, sigma: float, *, seed: int = 0, dtype=None,
     transform in FP64 (torch's ndtr/ndtri) with uniforms from torch's device
     generator seeded with ``seed + 1`` (one (rows x columns) draw per block of
     ``block_rows`` rows, lower triangle used), so Y follows the same
-    distribution as the host recipe but not the same values.  Returns
-    (x_true, x) as host arrays and Y as an N x N device tensor of ``dtype``
-    (float64 by default).
+    distribution as the host recipe but not the same values.  ``missing``
+    marks that fraction of the pairs missing (a symmetric Bernoulli draw from
+    a device generator seeded with ``seed + 2``) by setting them to NaN, which
+    the library reads as missing.  Returns (x_true, x) as host arrays and Y as
+    an N x N device tensor of ``dtype`` (float64 by default).
     """
     import torch
 
@@ -177,6 +180,13 @@ def device_problem(n: int, d: int, sigma: float, *, seed: int = 0, dtype=None,
         z = torch.special.ndtri((lo + u * (1.0 - lo)).clamp_(1e-300, hi))
         y[i0:i1, :i1] = (delta + sigma * z).clamp_(min=np.finfo(np.float64).tiny)
         del delta, u, lo, z
+    if missing > 0.0:
+        gm = torch.Generator(device=device)
+        gm.manual_seed(seed + 2)
+        for i0 in range(0, n, block_rows):
+            i1 = min(n, i0 + block_rows)
+            drop = torch.rand((i1 - i0, i1), generator=gm, device=device) < missing
+            y[i0:i1, :i1].masked_fill_(drop, float("nan"))
     # mirror the strict lower triangle, zero diagonal
     for i0 in range(0, n, block_rows):
         i1 = min(n, i0 + block_rows)

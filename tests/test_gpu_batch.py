@@ -47,6 +47,33 @@ def test_batch_equals_single_calls_bitwise(dtype):
         assert L.item() == B.loglik[k].item() and ds.item() == B.dsigma[k].item(), k
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_relabelled_batch_equals_single_calls_bitwise(dtype):
+    # problems stored in the spatial order of their locations: every problem
+    # equals its relabelled single-problem call, and the oracle in the
+    # original labelling
+    specs = _mixed_specs(11, 8)
+    probs = [synth.make_problem(**sp) for sp in specs]
+    yv = [p.y.astype(np.float32) if dtype == torch.float32 else p.y for p in probs]
+    B = api.MDSBatch([dict(y=y, d=p.d, mask=p.mask, order=p.x) for y, p in zip(yv, probs)],
+                     dtype, DEV)
+    for k, p in enumerate(probs):
+        B.set_x(k, p.x)
+        B.sigma[k] = p.sigma
+    B.eval()
+    torch.cuda.synchronize()
+    for k, p in enumerate(probs):
+        P = api.MDSProblem(yv[k], p.d, p.mask, dtype, DEV, 0, 4, order=p.x)
+        g, L, _ = P.gradient(P.relabel(p.x), p.sigma)
+        torch.cuda.synchronize()
+        assert torch.equal(B.perm[k], P.perm), k
+        assert torch.equal(g, B.grad[k]) and L.item() == B.loglik[k].item(), k
+        if dtype == torch.float64 and p.n > 1:
+            ref = oracle.evaluate(p.x, p.y, p.sigma, p.mask)
+            got = B.unlabel(k, B.grad[k]).cpu().numpy()
+            assert np.all(np.max(np.abs(got - ref.grad), axis=1) <= 1e-12 * ref.condrow), k
+
+
 def test_batch_fp64_vs_oracle_and_repeat():
     probs, B = _build(_mixed_specs(2, 12), torch.float64)
     B.eval()

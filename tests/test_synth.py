@@ -88,3 +88,13 @@ def test_device_problem_same_recipe():
     assert torch.equal(y, y2)
     _, _, y32 = synth.device_problem(300, 2, 0.5, seed=1, device="cpu", dtype=torch.float32)
     assert y32.dtype == torch.float32
+
+
+def test_device_problem_missing_pairs():
+    _, _, y = synth.device_problem(800, 2, 0.5, seed=3, device="cpu", missing=0.15)
+    yn = y.numpy()
+    i, j = np.tril_indices(800, -1)
+    miss = np.isnan(yn[i, j])
+    assert abs(miss.mean() - 0.15) < 0.01
+    assert np.array_equal(np.isnan(yn), np.isnan(yn.T)) and not np.isnan(np.diag(yn)).any()
+    assert (yn[i, j][~miss] > 0).all()
