@@ -14,7 +14,8 @@ lets most wavefronts skip the truncation terms; the outputs are the same up
 to rounding, with the gradient rows in the new labelling.  Besides the FP64
 figure (the headline `value`) the line carries the FP32 form on the same
 data, both forms in the original labelling, one 20-step leapfrog trajectory,
-100 HMC transitions, the held-out predictive density, the model without
+100 HMC transitions, a 10-step MAP loop through the autograd Function, the
+held-out predictive density, the model without
 truncation, the batched form (64 problems of uneven N and D, one persistent
 launch per evaluation, graph-captured 20-step trajectories of the batch),
 the sweep kernel's roofline (each launch of a second pass of the same K
@@ -401,6 +402,23 @@ def main():
     hmc_ms = (time.perf_counter() - t0) * 1e3 / 100
     hmc_acc = chain.accepted.item() / 110
 
+    # differentiation form: the torch.autograd.Function over (X, ln sigma),
+    # a 10-step gradient-ascent MAP loop (forward = loglik-only sweep,
+    # backward = one gradient sweep scaled by the upstream gradient)
+    from paper_1905_04582_amd import autograd
+    ls0 = torch.tensor(float(np.log(sigma)), dtype=torch.float64, device=dev)
+    # step sizes for this workload's gradient scale (rows ~ 1e3-1e4, dL/d ln sigma ~ 1e6)
+    autograd.map_ascent(P64, xr, ls0, steps=2, lr_x=1e-6, lr_s=1e-9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, map_trace = autograd.map_ascent(P64, xr, ls0, steps=10, lr_x=1e-6, lr_s=1e-9)
+    torch.cuda.synchronize()
+    map_ms = (time.perf_counter() - t0) * 1e3 / 10
+    map_l = map_trace.cpu().numpy()
+    autograd_map = {"steps": 10, "ms_per_step": round(map_ms, 4),
+                    "loglik_first_last": [float(map_l[0]), float(map_l[-1])],
+                    "step": "forward loglik sweep + backward gradient sweep + torch update"}
+
     # held-out predictive density: 10% of the pairs held out (symmetric
     # Bernoulli), compacted once, then one accumulation pass per posterior
     # draw (the chain's states stand in for draws) and one finalize
@@ -595,6 +613,7 @@ def main():
         },
         "original_labelling": plain,
         "untruncated_model": abl,
+        "autograd_map": autograd_map,
         "heldout_lpd": heldout,
         "batched_form": batched,
         "leapfrog": {"steps": 20, "step_size": 1e-3, "ms_per_trajectory": round(traj_ms, 4),

@@ -1,7 +1,7 @@
 """Tile-shape autotuner for the pair sweep.
 
 For a (Y dtype, D, N bucket) it times every feasible tiling -- rows per tile
-(32/64/128/256) x 64-column groups per tile (1/2/4/8), one dividing the
+(8/16/32/64/128/256) x 64-column groups per tile (1/2/4/8), one dividing the
 other, within the LDS budget -- on a problem of that size and keeps the
 fastest in a JSON cache keyed by GPU architecture, dtype, D and bucket.
 
