@@ -104,7 +104,8 @@ constexpr size_t kMaxSweepLds = 64 * 1024;
 void default_tiling(int64_t n, int d, int dtype, int* br, int* waves)
 {
     (void)d;
-    if (n <= 1536 && dtype == MDS_F64) {
+    (void)dtype;
+    if (n <= 1536) {
         *br = 8;
         *waves = 1;
     } else if (n <= 3072) {

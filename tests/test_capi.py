@@ -273,7 +273,7 @@ def test_resolve_tiling():
     L = api.lib()
     f64, f32 = api.MDS_F64, api.MDS_F32
     assert api.mds_resolve_tiling(1000, 2, f64) == (8, 1)
-    assert api.mds_resolve_tiling(1000, 2, f32) == (16, 1)
+    assert api.mds_resolve_tiling(1000, 2, f32) == (8, 1)
     assert api.mds_resolve_tiling(2500, 2, f64) == (16, 1)
     assert api.mds_resolve_tiling(5392, 2, f64) == (32, 4)
     assert api.mds_resolve_tiling(5392, 2, f32) == (32, 4)
