@@ -64,6 +64,30 @@ def build(extra_flags=(), verbose: bool = False, out: str | None = None) -> str:
     return lib
 
 
+NATIVE_SRC = os.path.join(ROOT, "tests", "native", "capi_roundtrip.c")
+NATIVE_BIN = os.path.join(ROOT, "tests", "native", "capi_roundtrip")
+
+
+def build_native_check(out: str = NATIVE_BIN) -> str:
+    """Compile the plain C program that drives the library through its C ABI
+    alone (host C compiler; links libmassivemds and the HIP runtime)."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        raise RuntimeError("no C compiler for the native C-ABI check")
+    rocm = os.path.dirname(os.path.dirname(hipcc()))
+    cmd = [cc, "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+           NATIVE_SRC, "-o", out, "-L", PKG, "-lmassivemds", "-L", os.path.join(rocm, "lib"),
+           "-lamdhip64", f"-Wl,-rpath,{PKG}", f"-Wl,-rpath,{os.path.join(rocm, 'lib')}"]
+    if os.path.abspath(out) == NATIVE_BIN:
+        # the in-tree program finds the library next to it wherever the tree is copied
+        cmd.insert(-3, "-Wl,-rpath,$ORIGIN/../../paper_1905_04582_amd")
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"native C-ABI check failed to build:\n{r.stderr}")
+    return out
+
+
 if __name__ == "__main__":
     # python -m paper_1905_04582_amd.build [-DMACRO=value ...] [--out path/to/lib.so]
     argv = sys.argv[1:]

@@ -372,3 +372,14 @@ def test_batch_rejects():
     assert L.mds_batch_leapfrog(ctypes.byref(pl), 20, 0, None) == ERR_ARG
     pl.flags = 1
     assert L.mds_batch_leapfrog(ctypes.byref(pl), -1, 0, None) == ERR_ARG
+
+
+def test_native_c_program_uses_the_abi_alone(tmp_path):
+    # a plain C program (no Python, no torch) compiled against include/ and
+    # linked to the library runs the host-side entry points and rejects
+    import subprocess
+    from paper_1905_04582_amd import build
+    exe = build.build_native_check(str(tmp_path / "capi_roundtrip"))
+    r = subprocess.run([exe, "cpu"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert "capi host checks ok" in r.stdout

@@ -1,0 +1,41 @@
+"""GPU: a plain C program drives one fused evaluation through the C ABI alone
+(hipMalloc'd buffers, mds_prepare_y, mds_gradient; no Python, no torch in
+that process), checked against the oracle on the same inputs."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_04582_amd import build, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_c_program_matches_oracle(tmp_path):
+    exe = build.NATIVE_BIN
+    assert os.path.exists(exe), "build() compiles tests/native/capi_roundtrip"
+    p = synth.make_problem(400, 3, 0.6, seed=77, missing=0.1)
+    y = p.y.copy()
+    y[p.mask != 0] = np.nan                      # missing pairs travel as NaN
+    inp, out = tmp_path / "in.bin", tmp_path / "out.bin"
+    with open(inp, "wb") as f:
+        np.array([p.n], np.int64).tofile(f)
+        np.array([p.d, 0], np.int32).tofile(f)
+        np.array([p.sigma], np.float64).tofile(f)
+        np.ascontiguousarray(p.x, np.float64).tofile(f)
+        np.ascontiguousarray(y, np.float64).tofile(f)
+    print(f"native C-ABI run: n={p.n} d={p.d}", flush=True)
+    r = subprocess.run([exe, "gpu", str(inp), str(out)], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    raw = np.fromfile(out, np.uint8)
+    L, ds = raw[:16].view(np.float64)
+    m = int(raw[16:24].view(np.int64)[0])
+    g = raw[24:].view(np.float64).reshape(p.n, p.d)
+    ref = oracle.evaluate(p.x, p.y, p.sigma, p.mask)
+    assert m == ref.m_obs
+    assert abs(L - ref.loglik) <= 1e-12 * abs(ref.loglik)
+    assert abs(ds - ref.dsigma) <= 1e-12 * ref.abs_dsigma
+    assert np.all(np.max(np.abs(g - ref.grad), axis=1) <= 1e-12 * ref.condrow)
