@@ -137,7 +137,9 @@ int resolve_tiling(int64_t n, int d, int dtype, int tile_rows, int tile_waves, T
     if (!(br % cw == 0 || cw % br == 0))
         return fail(MDS_ERR_UNSUPPORTED, "tile_rows=%d and 64*tile_waves=%d: neither divides the other",
                     br, cw);
-    *out = make_tiling(n, br, waves);
+    // staged rows hold Y's element type; a model flag in dtype's high bits
+    // does not change it
+    *out = make_tiling(n, br, waves, (dtype & 0xff) == MDS_F32 ? 4 : 8);
     if (sweep_lds_bytes(*out, d) > kMaxSweepLds)
         return fail(MDS_ERR_UNSUPPORTED, "tile %dx%d with D=%d needs %zu B of LDS (max %zu)", br,
                     cw, d, sweep_lds_bytes(*out, d), kMaxSweepLds);

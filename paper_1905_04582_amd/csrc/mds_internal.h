@@ -25,6 +25,7 @@ struct Tiling {
     int waves;  // cw / 64
     int nrb;    // number of row blocks
     int64_t ntiles;
+    int elem;   // bytes of one Y element (8 in FP64, 4 in FP32): the staged rows' type
 };
 
 __host__ __device__ inline int64_t tiles_in_row_block(int r, int br, int cw)
@@ -52,9 +53,10 @@ __host__ __device__ inline int first_row_block_of_column(int c, int br, int cw)
     return c * (cw / br);
 }
 
-inline Tiling make_tiling(int64_t n, int br, int waves)
+inline Tiling make_tiling(int64_t n, int br, int waves, int elem)
 {
     Tiling t;
+    t.elem = elem;
     t.n = n;
     t.br = br;
     t.waves = waves;
@@ -114,11 +116,12 @@ __host__ __device__ constexpr int sweep_stage_rows(int d)
 constexpr int kStagePadBytes = MDS_STAGE_PAD_BYTES;
 
 // LDS bytes used by one sweep work-group: tile row sums, per-wave scalars
-// and the per-wave row staging buffer (rows padded by kStagePadBytes)
+// and the per-wave row staging buffer (rows of Y's element type, padded by
+// kStagePadBytes)
 inline size_t sweep_lds_bytes(const Tiling& t, int d)
 {
     return (size_t)t.waves * t.br * d * sizeof(double) + (size_t)t.waves * 4 * sizeof(double) +
-           (size_t)t.waves * sweep_stage_rows(d) * (kWave * d * sizeof(double) + kStagePadBytes);
+           (size_t)t.waves * sweep_stage_rows(d) * ((size_t)kWave * d * t.elem + kStagePadBytes);
 }
 
 // partial sums of the lpd finalize (its workspace holds this many doubles)
