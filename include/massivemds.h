@@ -62,6 +62,10 @@
 
 #include <hip/hip_runtime_api.h>
 
+/* The library is built with hidden visibility; these entry points are its
+   only exported symbols. */
+#define MDS_API __attribute__((visibility("default")))
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -95,20 +99,20 @@ enum mds_dtype { MDS_F64 = 0, MDS_F32 = 1 };
 #define MDS_WORKSPACE_ALIGN 256
 
 /* Human-readable name of a status code (static string). */
-const char* mds_status_string(int status);
+MDS_API const char* mds_status_string(int status);
 
 /* Detail of the last failed call on this thread ("" if none). */
-const char* mds_last_error(void);
+MDS_API const char* mds_last_error(void);
 
 /* Library version, major*10000 + minor*100 + patch. */
-int mds_version(void);
+MDS_API int mds_version(void);
 
 /*
  * Workspace size, in bytes, for mds_loglik / mds_gradient / mds_leapfrog on
  * an N-point, D-dimensional problem with the given Y dtype and tiling
  * (0 = default).  Writes *bytes; returns a status.
  */
-int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
+MDS_API int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
                         int32_t tile_waves, size_t* bytes);
 
 /*
@@ -118,7 +122,7 @@ int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows
  * *waves_out (64-column groups per tile); returns a status (an unsupported
  * tiling is MDS_ERR_UNSUPPORTED, as in the evaluation calls).
  */
-int mds_resolve_tiling(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
+MDS_API int mds_resolve_tiling(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
                        int32_t tile_waves, int32_t* rows_out, int32_t* waves_out);
 
 /*
@@ -138,7 +142,7 @@ int mds_resolve_tiling(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
  * Missing data are not part of the paper's model; they are excluded from
  * every sum and from M.
  */
-int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src,
+MDS_API int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src,
                   const uint8_t* missing, int64_t ld_mask, void* y_out, int32_t out_dtype,
                   int64_t ldy, int64_t n, const int64_t* perm, int64_t* m_obs_dev,
                   hipStream_t stream);
@@ -153,7 +157,7 @@ int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src,
  *   y               N x N, dtype y_dtype, leading dimension ldy
  *   mismatches_dev  device int64 receiving the count (0 = symmetric)
  */
-int mds_check_symmetric(const void* y, int32_t y_dtype, int64_t ldy, int64_t n,
+MDS_API int mds_check_symmetric(const void* y, int32_t y_dtype, int64_t ldy, int64_t n,
                         int64_t* mismatches_dev, hipStream_t stream);
 
 /*
@@ -174,8 +178,8 @@ int mds_check_symmetric(const void* y, int32_t y_dtype, int64_t ldy, int64_t n,
  *   workspace  device scratch of mds_order_workspace_bytes(n) bytes
  *              (MDS_WORKSPACE_ALIGN-aligned)
  */
-int mds_order_workspace_bytes(int64_t n, size_t* bytes);
-int mds_spatial_order(int64_t n, int32_t d, const double* x, int64_t ldx, int64_t* perm,
+MDS_API int mds_order_workspace_bytes(int64_t n, size_t* bytes);
+MDS_API int mds_spatial_order(int64_t n, int32_t d, const double* x, int64_t ldx, int64_t* perm,
                       void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
@@ -186,7 +190,7 @@ int mds_spatial_order(int64_t n, int32_t d, const double* x, int64_t ldx, int64_
  * src and dst must not overlap.  An out-of-range perm entry writes a NaN row
  * (inverse == 0) or nothing (inverse != 0).
  */
-int mds_permute_rows(int64_t n, int32_t d, const double* src, int64_t ld_src, double* dst,
+MDS_API int mds_permute_rows(int64_t n, int32_t d, const double* src, int64_t ld_src, double* dst,
                      int64_t ld_dst, const int64_t* perm, int32_t inverse, hipStream_t stream);
 
 /*
@@ -196,7 +200,7 @@ int mds_permute_rows(int64_t n, int32_t d, const double* src, int64_t ld_src, do
  *   sigma_dev  device double, sigma > 0
  *   loglik_dev device double receiving L
  */
-int mds_loglik(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
+MDS_API int mds_loglik(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
                int32_t y_dtype, int64_t ldy, const double* sigma_dev, double* loglik_dev,
                void* workspace, size_t workspace_bytes, int32_t tile_rows, int32_t tile_waves,
                hipStream_t stream);
@@ -213,7 +217,7 @@ int mds_loglik(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y
  *   dlogsigma_dev optional device double: s * dL/d(ln sigma) = s * sigma * dL/dsigma
  *              (the derivative a caller parametrising sigma by its log needs)
  */
-int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
+MDS_API int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
                  int32_t y_dtype, int64_t ldy, const double* sigma_dev, const double* scale_dev,
                  double* grad, int64_t ldg, double* loglik_dev, double* dsigma_dev,
                  double* dlogsigma_dev, void* workspace, size_t workspace_bytes,
@@ -240,7 +244,7 @@ int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void*
  *                  (Eq. 6) before and after the trajectory
  * The workspace is the one of mds_gradient for the same (n, d, y_dtype, tiling).
  */
-int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_t ldp,
+MDS_API int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_t ldp,
                  const void* y, int32_t y_dtype, int64_t ldy, const double* sigma_dev,
                  const double* inv_mass, const double* step_dev, const double* prior_dev,
                  int32_t n_steps, double* grad_io, double* loglik_io, int32_t cache_valid,
@@ -279,9 +283,9 @@ int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_
  * Every step runs on the device and reads its scalars from device memory, so
  * transitions can be captured in a graph and replayed as a chain.
  */
-int mds_hmc_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
+MDS_API int mds_hmc_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
                             int32_t tile_waves, size_t* bytes);
-int mds_hmc_step(int64_t n, int32_t d, double* x, int64_t ldx, const void* y, int32_t y_dtype,
+MDS_API int mds_hmc_step(int64_t n, int32_t d, double* x, int64_t ldx, const void* y, int32_t y_dtype,
                  int64_t ldy, const double* sigma_dev, const double* inv_mass,
                  const double* step_dev, const double* prior_dev, int32_t n_steps,
                  uint64_t seed, uint64_t* iteration_dev, double* p, int64_t ldp,
@@ -293,7 +297,7 @@ int mds_hmc_step(int64_t n, int32_t d, double* x, int64_t ldx, const void* y, in
  * The momentum draw of mds_hmc_step alone: p (N x D, ldp) = the momentum of
  * transition *iteration_dev under seed (iteration_dev is not incremented).
  */
-int mds_hmc_momentum(int64_t n, int32_t d, const double* inv_mass, uint64_t seed,
+MDS_API int mds_hmc_momentum(int64_t n, int32_t d, const double* inv_mass, uint64_t seed,
                      const uint64_t* iteration_dev, double* p, int64_t ldp, hipStream_t stream);
 
 /*
@@ -317,21 +321,21 @@ int mds_hmc_momentum(int64_t n, int32_t d, const double* inv_mass, uint64_t seed
  *    256-byte aligned, caller-owned) holds partial sums.  The sums run in a
  *    fixed order, so the result is deterministic.
  */
-int mds_heldout_workspace_bytes(int64_t n, size_t* bytes);
-int mds_heldout_count(const void* y_src, int32_t src_dtype, int64_t ld_src,
+MDS_API int mds_heldout_workspace_bytes(int64_t n, size_t* bytes);
+MDS_API int mds_heldout_count(const void* y_src, int32_t src_dtype, int64_t ld_src,
                       const uint8_t* missing, int64_t ld_mask, const uint8_t* heldout,
                       int64_t ld_heldout, int64_t n, int64_t* m_dev, void* workspace,
                       size_t workspace_bytes, hipStream_t stream);
-int mds_heldout_fill(const void* y_src, int32_t src_dtype, int64_t ld_src,
+MDS_API int mds_heldout_fill(const void* y_src, int32_t src_dtype, int64_t ld_src,
                      const uint8_t* missing, int64_t ld_mask, const uint8_t* heldout,
                      int64_t ld_heldout, int64_t n, const void* workspace,
                      size_t workspace_bytes, int64_t capacity, int32_t* pi, int32_t* pj,
                      double* py, hipStream_t stream);
-int mds_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj, const double* py,
+MDS_API int mds_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj, const double* py,
                        int32_t d, const double* x, int64_t ldx, const double* sigma_dev,
                        double* acc, int32_t first, hipStream_t stream);
-int mds_lpd_workspace_bytes(int64_t m, size_t* bytes);
-int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, void* workspace,
+MDS_API int mds_lpd_workspace_bytes(int64_t m, size_t* bytes);
+MDS_API int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, void* workspace,
                      size_t workspace_bytes, double* lpd_dev, hipStream_t stream);
 
 /*
@@ -341,7 +345,7 @@ int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, void* worksp
  * with the far lower tail t < -5 evaluated in FP64 by its log-erfc form).
  *   t, lnphi, mills   `count` FP64 values each (lnphi or mills may be NULL)
  */
-int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count,
+MDS_API int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count,
                 int32_t precision, hipStream_t stream);
 
 /* ------------------------------------------------------------ batches -- */
@@ -401,12 +405,12 @@ typedef struct mds_batch_plan {
  *     on `stream`; asynchronous, allocation-free, capturable.  Calls sharing
  *     a workspace must not overlap.
  */
-int mds_batch_workspace_bytes(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
+MDS_API int mds_batch_workspace_bytes(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
                               int32_t tile_waves, size_t* bytes);
-int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
+MDS_API int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype,
                    int32_t tile_waves, void* workspace, size_t workspace_bytes,
                    mds_batch_plan* plan, hipStream_t stream);
-int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t stream);
+MDS_API int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t stream);
 
 /*
  * Leapfrog trajectories (Section 2.3, Eqs. 6-8; unit mass, no prior) of
@@ -421,7 +425,7 @@ int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t st
  * the same tiling (unit mass, no prior), bit for bit.  Launches only: can be
  * captured in a graph.
  */
-int mds_batch_leapfrog(const mds_batch_plan* plan, int32_t n_steps, int32_t cache_valid,
+MDS_API int mds_batch_leapfrog(const mds_batch_plan* plan, int32_t n_steps, int32_t cache_valid,
                        hipStream_t stream);
 
 /*
@@ -433,7 +437,7 @@ int mds_batch_leapfrog(const mds_batch_plan* plan, int32_t n_steps, int32_t cach
  * later sweep launch; pass NULL, NULL to stop.  Thread-local; no effect on
  * results.
  */
-int mds_set_sweep_events(hipEvent_t before, hipEvent_t after);
+MDS_API int mds_set_sweep_events(hipEvent_t before, hipEvent_t after);
 
 #ifdef __cplusplus
 }

@@ -242,7 +242,7 @@ FinalizeArgs finalize_args(const Tiling& t, const SweepArgs& s)
 extern "C" {
 
 #if MDS_TILE_TRACE
-int mds_set_tile_trace(void* p)
+MDS_API int mds_set_tile_trace(void* p)
 {
     g_tile_trace = static_cast<unsigned long long*>(p);
     return 0;
