@@ -167,23 +167,15 @@ struct PairGeom {
 // each far under the rounding of the pair's other terms in that precision.
 template <typename T>
 __device__ __forceinline__ T skip_t();
-// (build variants: lower points skip more wavefronts but drop larger terms;
-// 8.5 / 6.0 measured 0.6% / 1.5% faster at N = 5392, not worth the margin)
-#ifndef MDS_SKIP_T64
-#define MDS_SKIP_T64 9.0
-#endif
-#ifndef MDS_SKIP_T32
-#define MDS_SKIP_T32 6.5f
-#endif
 template <>
 __device__ __forceinline__ double skip_t<double>()
 {
-    return MDS_SKIP_T64;
+    return 9.0;
 }
 template <>
 __device__ __forceinline__ float skip_t<float>()
 {
-    return MDS_SKIP_T32;
+    return 6.5f;
 }
 
 // One tile of one problem, processed by the whole work-group; `lds` is the
