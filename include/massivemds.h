@@ -354,7 +354,8 @@ MDS_API int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t c
 typedef struct mds_problem_desc {
     int64_t n;             /* locations */
     int32_t d;             /* latent dimension, 1..MDS_MAX_DIM */
-    int32_t tile_rows;     /* rows per tile (8/16/32/64/128/256), 0 = default for (dtype, d, n) */
+    int32_t tile_rows;     /* rows per tile (8/16/32/64/128/256); 0 = 128 rows, or the
+                              single-problem default where 128 rows exceed the LDS budget */
     const double* x;       /* N x D FP64, leading dimension ldx (moved by mds_batch_leapfrog) */
     int64_t ldx;
     const void* y;         /* prepared Y, the batch's y_dtype, leading dimension ldy */

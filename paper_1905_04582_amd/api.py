@@ -559,6 +559,7 @@ class MDSBatch:
         count = len(problems)
         self.count = count
         self.ys, self.m_obs, self.x, self.grad, self.perm = [], [], [], [], []
+        self.tiles = []  # (rows, 64-column groups) of each problem's tiles
         self._scal = torch.zeros((6, count), **f64)
         self.sigma, self.scale, self.loglik, self.dsigma, self.dlogsigma, self.step = self._scal
         self.sigma.fill_(1.0)
@@ -604,6 +605,16 @@ class MDSBatch:
             q.step = self.step.data_ptr() + 8 * k
         self._descs = descs
         code = _dtype_code(dtype) | (0 if truncated else MDS_UNTRUNCATED)
+        for k in range(count):
+            q = descs[k]
+            if q.tile_rows == 0:
+                try:
+                    t = mds_resolve_tiling(q.n, q.d, _dtype_code(dtype), 128, tile_waves or 4)
+                except MDSError:
+                    t = mds_resolve_tiling(q.n, q.d, _dtype_code(dtype), 0, tile_waves or 4)
+            else:
+                t = mds_resolve_tiling(q.n, q.d, _dtype_code(dtype), q.tile_rows, tile_waves or 4)
+            self.tiles.append(t)
         nb = ctypes.c_size_t(0)
         _check(lib().mds_batch_workspace_bytes(descs, count, code, tile_waves, ctypes.byref(nb)),
                "mds_batch_workspace_bytes")

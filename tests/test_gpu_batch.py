@@ -40,7 +40,7 @@ def test_batch_equals_single_calls_bitwise(dtype):
     torch.cuda.synchronize()
     for k, p in enumerate(probs):
         P = api.MDSProblem(p.y.astype(np.float32) if dtype == torch.float32 else p.y, p.d,
-                           p.mask, dtype, DEV, 0, 4)
+                           p.mask, dtype, DEV, *B.tiles[k])
         g, L, ds = P.gradient(B.x[k], p.sigma)
         torch.cuda.synchronize()
         assert torch.equal(g, B.grad[k]), k
@@ -63,7 +63,7 @@ def test_relabelled_batch_equals_single_calls_bitwise(dtype):
     B.eval()
     torch.cuda.synchronize()
     for k, p in enumerate(probs):
-        P = api.MDSProblem(yv[k], p.d, p.mask, dtype, DEV, 0, 4, order=p.x)
+        P = api.MDSProblem(yv[k], p.d, p.mask, dtype, DEV, *B.tiles[k], order=p.x)
         g, L, _ = P.gradient(P.relabel(p.x), p.sigma)
         torch.cuda.synchronize()
         assert torch.equal(B.perm[k], P.perm), k
@@ -134,7 +134,7 @@ def test_batched_workload_64_problems():
     torch.cuda.synchronize()
     for k in (0, 17, 41, 63):
         p = probs[k]
-        P = api.MDSProblem(p.y.astype(np.float32), p.d, p.mask, torch.float32, DEV, 0, 4)
+        P = api.MDSProblem(p.y.astype(np.float32), p.d, p.mask, torch.float32, DEV, *B.tiles[k])
         g, L, _ = P.gradient(B.x[k], p.sigma)
         torch.cuda.synchronize()
         assert torch.equal(g, B.grad[k]) and L.item() == B.loglik[k].item()
@@ -171,7 +171,7 @@ def test_batch_leapfrog_equals_single_calls_bitwise(dtype):
     torch.cuda.synchronize()
     for k, p in enumerate(probs):
         P = api.MDSProblem(p.y.astype(np.float32) if dtype == torch.float32 else p.y, p.d,
-                           p.mask, dtype, DEV, 0, 4)
+                           p.mask, dtype, DEV, *B.tiles[k])
         x = torch.as_tensor(p.x, dtype=torch.float64, device=DEV).clone()
         pm = torch.as_tensor(moms[k], dtype=torch.float64, device=DEV).clone()
         g = torch.empty_like(x)
