@@ -120,39 +120,56 @@ __global__ void __launch_bounds__(kRowThreads)
 
 // per pair: l = ln p(y | delta, sigma) of the truncated normal, folded into
 // the running log-sum-exp (acc[2k] = largest term, acc[2k+1] = sum of
-// exp(l - largest)); `first` starts the sums
+// exp(l - largest)); `first` starts the sums.  Each thread takes kLpdPairs
+// pairs (one block covers 256 * kLpdPairs consecutive pairs, lane-strided so
+// every load is coalesced), so ln sigma and 1/sigma are formed once per
+// thread.  A wavefront whose pairs all have delta/sigma >= 9 takes
+// ln Phi = 0 (|ln Phi(t)| < 2.3e-19 there, far below the rounding of l).
+constexpr int kLpdPairs = 4;
+constexpr int kLpdThreads = 256;
+
 template <int D>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kLpdThreads)
     lpd_accumulate_kernel(int64_t m, const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
                           const double* __restrict__ py, const double* __restrict__ x, int64_t ldx,
                           const double* __restrict__ sigma_p, double* __restrict__ acc, int first)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
     const double sigma = *sigma_p;
-    const int64_t i = pi[k], j = pj[k];
-    double s2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const double diff = x[i * ldx + d] - x[j * ldx + d];
-        s2 = fma(diff, diff, s2);
-    }
-    const double delta = sqrt(s2);
-    const double z = (py[k] - delta) / sigma;
-    double lnphi, mills;
-    log_phi_general_f64(delta / sigma, lnphi, mills);
+    const double inv_sigma = 1.0 / sigma;
     constexpr double kLnSqrt2Pi = 0.91893853320467274178;
-    const double l = -kLnSqrt2Pi - log(sigma) - 0.5 * z * z - lnphi;
-    if (first) {
-        acc[2 * k] = l;
-        acc[2 * k + 1] = 1.0;
-    } else {
-        const double mx = acc[2 * k];
-        if (l > mx) {
-            acc[2 * k + 1] = acc[2 * k + 1] * exp(mx - l) + 1.0;
+    const double c0 = -kLnSqrt2Pi - log(sigma);
+    const int64_t base = (int64_t)blockIdx.x * (kLpdThreads * kLpdPairs) + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kLpdPairs; ++u) {
+        const int64_t k = base + (int64_t)u * kLpdThreads;
+        const bool live = k < m;
+        // a lane past the end works on the last pair and stores nothing
+        const int64_t kk = live ? k : m - 1;
+        const int64_t i = pi[kk], j = pj[kk];
+        double s2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const double diff = x[i * ldx + d] - x[j * ldx + d];
+            s2 = fma(diff, diff, s2);
+        }
+        const double delta = sqrt(s2);
+        const double z = (py[kk] - delta) * inv_sigma;
+        const double t = delta * inv_sigma;
+        double lnphi = 0.0, mills;
+        if (__builtin_amdgcn_ballot_w64(t < 9.0)) log_phi_general_f64(t, lnphi, mills);
+        const double l = c0 - 0.5 * z * z - lnphi;
+        if (!live) continue;
+        if (first) {
             acc[2 * k] = l;
+            acc[2 * k + 1] = 1.0;
         } else {
-            acc[2 * k + 1] += exp(l - mx);
+            const double mx = acc[2 * k];
+            if (l > mx) {
+                acc[2 * k + 1] = acc[2 * k + 1] * exp(mx - l) + 1.0;
+                acc[2 * k] = l;
+            } else {
+                acc[2 * k + 1] += exp(l - mx);
+            }
         }
     }
 }
@@ -240,7 +257,8 @@ hipError_t launch_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj
                                  const double* sigma, double* acc, int first, hipStream_t s)
 {
     if (m == 0) return hipSuccess;
-    const dim3 grid((unsigned)((m + 255) / 256)), block(256);
+    const int64_t per_block = (int64_t)kLpdThreads * kLpdPairs;
+    const dim3 grid((unsigned)((m + per_block - 1) / per_block)), block(kLpdThreads);
 #define MDS_LPD_CASE(DD)                                                                     \
     case DD:                                                                                 \
         hipLaunchKernelGGL(lpd_accumulate_kernel<DD>, grid, block, 0, s, m, pi, pj, py, x, ldx, \
