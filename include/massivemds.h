@@ -315,7 +315,12 @@ MDS_API int mds_hmc_momentum(int64_t n, int32_t d, const double* inv_mass, uint6
  *    at most `capacity` are written.
  * 3. mds_lpd_accumulate, once per draw (x, sigma_dev): updates acc (2*m
  *    doubles, caller-owned: a running log-sum-exp per pair); first != 0
- *    starts it.
+ *    starts it.  mds_lpd_accumulate_draws folds n_draws draws in one pass
+ *    (draw s: x at xs + s * draw_stride doubles, leading dimension ldx,
+ *    sigma = sigmas_dev[s]), in draw order, reading and writing acc once;
+ *    the result is bit for bit that of n_draws single calls in the same
+ *    order (first != 0 starts the sums with draw 0; n_draws = 0 does
+ *    nothing).  The draws' arrays must not overlap acc.
  * 4. mds_lpd_finalize: lpd = sum over pairs of ln(average of the densities)
  *    over n_draws draws, into lpd_dev; its workspace (mds_lpd_workspace_bytes,
  *    256-byte aligned, caller-owned) holds partial sums.  The sums run in a
@@ -334,6 +339,11 @@ MDS_API int mds_heldout_fill(const void* y_src, int32_t src_dtype, int64_t ld_sr
 MDS_API int mds_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj, const double* py,
                        int32_t d, const double* x, int64_t ldx, const double* sigma_dev,
                        double* acc, int32_t first, hipStream_t stream);
+MDS_API int mds_lpd_accumulate_draws(int64_t m, const int32_t* pi, const int32_t* pj,
+                                     const double* py, int32_t d, const double* xs, int64_t ldx,
+                                     int64_t draw_stride, const double* sigmas_dev,
+                                     int32_t n_draws, double* acc, int32_t first,
+                                     hipStream_t stream);
 MDS_API int mds_lpd_workspace_bytes(int64_t m, size_t* bytes);
 MDS_API int mds_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, void* workspace,
                      size_t workspace_bytes, double* lpd_dev, hipStream_t stream);

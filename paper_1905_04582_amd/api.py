@@ -100,6 +100,9 @@ def lib():
     L.mds_lpd_accumulate.restype = ctypes.c_int
     L.mds_lpd_accumulate.argtypes = [_c_i64, _vp, _vp, _vp, _c_i32, _vp, _c_i64, _vp, _vp, _c_i32,
                                      _vp]
+    L.mds_lpd_accumulate_draws.restype = ctypes.c_int
+    L.mds_lpd_accumulate_draws.argtypes = [_c_i64, _vp, _vp, _vp, _c_i32, _vp, _c_i64, _c_i64,
+                                           _vp, _c_i32, _vp, _c_i32, _vp]
     L.mds_lpd_finalize.restype = ctypes.c_int
     L.mds_lpd_finalize.argtypes = [_c_i64, _vp, _c_i64, _vp, ctypes.c_size_t, _vp, _vp]
     L.mds_lpd_workspace_bytes.restype = ctypes.c_int
@@ -729,6 +732,28 @@ class HeldOutPairs:
                                         1 if self.draws == 0 else 0, _stream(stream)),
                "mds_lpd_accumulate")
         self.draws += 1
+
+    def add_draws(self, xs, sigmas, stream=None):
+        """Several posterior draws in one pass: xs is S x N x D (each draw
+        contiguous), sigmas S values.  The same result, bit for bit, as S
+        add_draw calls in order, with the per-pair state read and written
+        once."""
+        xs = torch.as_tensor(xs).to(device=self.device, dtype=torch.float64)
+        if xs.dim() != 3 or xs.shape[1] != self.n:
+            raise ValueError(f"xs must be S x {self.n} x D, got {tuple(xs.shape)}")
+        xs = xs.contiguous()
+        sig = torch.as_tensor(sigmas, dtype=torch.float64).to(self.device).reshape(-1).contiguous()
+        if sig.numel() != xs.shape[0]:
+            raise ValueError("one sigma per draw")
+        s_draws, _, d = xs.shape
+        if s_draws == 0:
+            return
+        _check(lib().mds_lpd_accumulate_draws(self.m, _ptr(self.pi), _ptr(self.pj),
+                                              _ptr(self.py), d, _ptr(xs), d, self.n * d,
+                                              _ptr(sig), s_draws, _ptr(self.acc),
+                                              1 if self.draws == 0 else 0, _stream(stream)),
+               "mds_lpd_accumulate_draws")
+        self.draws += s_draws
 
     def lpd(self, stream=None) -> torch.Tensor:
         if self.draws == 0:

@@ -44,8 +44,9 @@ hipError_t launch_heldout_fill(const void* y, int dt, int64_t ld_y, const uint8_
                                const int64_t* rows, int64_t capacity, int32_t* pi, int32_t* pj,
                                double* py, hipStream_t s);
 hipError_t launch_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj,
-                                 const double* py, int d, const double* x, int64_t ldx,
-                                 const double* sigma, double* acc, int first, hipStream_t s);
+                                 const double* py, int d, const double* xs, int64_t ldx,
+                                 int64_t xstride, const double* sigmas, int32_t n_draws,
+                                 double* acc, int first, hipStream_t s);
 hipError_t launch_lpd_finalize(int64_t m, const double* acc, int64_t n_draws, double* part,
                                double* out,
                                hipStream_t s);
@@ -737,8 +738,30 @@ int mds_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj, const do
     if (!aligned(pi, 4) || !aligned(pj, 4) || !aligned(py, 8) || !aligned(x, 8) ||
         !aligned(sigma_dev, 8) || !aligned(acc, 8))
         return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
-    hipError_t e = launch_lpd_accumulate(m, pi, pj, py, d, x, ldx, sigma_dev, acc, first ? 1 : 0,
-                                         stream);
+    hipError_t e = launch_lpd_accumulate(m, pi, pj, py, d, x, ldx, 0, sigma_dev, 1, acc,
+                                         first ? 1 : 0, stream);
+    if (e != hipSuccess) return hip_fail(e, "lpd accumulate launch");
+    return MDS_OK;
+}
+
+int mds_lpd_accumulate_draws(int64_t m, const int32_t* pi, const int32_t* pj, const double* py,
+                             int32_t d, const double* xs, int64_t ldx, int64_t draw_stride,
+                             const double* sigmas_dev, int32_t n_draws, double* acc,
+                             int32_t first, hipStream_t stream)
+{
+    if (m < 0) return fail(MDS_ERR_INVALID_ARGUMENT, "m < 0");
+    if (n_draws < 0) return fail(MDS_ERR_INVALID_ARGUMENT, "n_draws < 0");
+    if (d < 1 || d > MDS_MAX_DIM)
+        return fail(MDS_ERR_UNSUPPORTED, "d=%d: must be 1..%d", d, MDS_MAX_DIM);
+    if (ldx < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldx < d");
+    if (draw_stride < 0) return fail(MDS_ERR_INVALID_ARGUMENT, "draw_stride < 0");
+    if (m > 0 && n_draws > 0 && (!pi || !pj || !py || !xs || !sigmas_dev || !acc))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "NULL pointer");
+    if (!aligned(pi, 4) || !aligned(pj, 4) || !aligned(py, 8) || !aligned(xs, 8) ||
+        !aligned(sigmas_dev, 8) || !aligned(acc, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    hipError_t e = launch_lpd_accumulate(m, pi, pj, py, d, xs, ldx, draw_stride, sigmas_dev,
+                                         n_draws, acc, first ? 1 : 0, stream);
     if (e != hipSuccess) return hip_fail(e, "lpd accumulate launch");
     return MDS_OK;
 }

@@ -118,58 +118,83 @@ __global__ void __launch_bounds__(kRowThreads)
     }
 }
 
-// per pair: l = ln p(y | delta, sigma) of the truncated normal, folded into
-// the running log-sum-exp (acc[2k] = largest term, acc[2k+1] = sum of
-// exp(l - largest)); `first` starts the sums.  Each thread takes kLpdPairs
-// pairs (one block covers 256 * kLpdPairs consecutive pairs, lane-strided so
-// every load is coalesced), so ln sigma and 1/sigma are formed once per
-// thread.  A wavefront whose pairs all have delta/sigma >= 9 takes
-// ln Phi = 0 (|ln Phi(t)| < 2.3e-19 there, far below the rounding of l).
+// per pair: l = ln p(y | delta, sigma) of the truncated normal for each of
+// n_draws draws (draw s: x at xs + s * xstride, sigma = sigmas[s]), folded
+// in draw order into the running log-sum-exp (acc[2k] = largest term,
+// acc[2k+1] = sum of exp(l - largest)); `first` starts the sums with the
+// first draw.  The state stays in registers across the draws, so a call with
+// S draws reads and writes it once instead of S times.  Each thread takes
+// kLpdPairs pairs (one block covers 256 * kLpdPairs consecutive pairs,
+// lane-strided so every load is coalesced), so ln sigma and 1/sigma are
+// formed once per thread and draw.  A wavefront whose pairs all have
+// delta/sigma >= 9 takes ln Phi = 0 (|ln Phi(t)| < 2.3e-19 there, far below
+// the rounding of l).  The arithmetic of a draw does not depend on how the
+// draws are grouped into calls: S calls of one draw and one call of S draws
+// give the same bits.
 constexpr int kLpdPairs = 4;
 constexpr int kLpdThreads = 256;
 
-template <int D>
+template <int D, bool ONE>
 __global__ void __launch_bounds__(kLpdThreads)
     lpd_accumulate_kernel(int64_t m, const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
-                          const double* __restrict__ py, const double* __restrict__ x, int64_t ldx,
-                          const double* __restrict__ sigma_p, double* __restrict__ acc, int first)
+                          const double* __restrict__ py, const double* __restrict__ xs,
+                          int64_t ldx, int64_t xstride, const double* __restrict__ sigmas,
+                          int32_t n_draws, double* __restrict__ acc, int first)
 {
-    const double sigma = *sigma_p;
-    const double inv_sigma = 1.0 / sigma;
     constexpr double kLnSqrt2Pi = 0.91893853320467274178;
-    const double c0 = -kLnSqrt2Pi - log(sigma);
     const int64_t base = (int64_t)blockIdx.x * (kLpdThreads * kLpdPairs) + threadIdx.x;
+    int64_t ii[kLpdPairs], jj[kLpdPairs];
+    double yv[kLpdPairs], mx[kLpdPairs], sm[kLpdPairs];
 #pragma unroll
     for (int u = 0; u < kLpdPairs; ++u) {
         const int64_t k = base + (int64_t)u * kLpdThreads;
-        const bool live = k < m;
         // a lane past the end works on the last pair and stores nothing
-        const int64_t kk = live ? k : m - 1;
-        const int64_t i = pi[kk], j = pj[kk];
-        double s2 = 0.0;
+        const int64_t kk = k < m ? k : m - 1;
+        ii[u] = pi[kk];
+        jj[u] = pj[kk];
+        yv[u] = py[kk];
+        mx[u] = first ? 0.0 : acc[2 * kk];
+        sm[u] = first ? 0.0 : acc[2 * kk + 1];
+    }
+    // ONE: a single draw, with the loop known to run once (same arithmetic)
+    const int32_t draws = ONE ? 1 : n_draws;
+    for (int s = 0; s < draws; ++s) {
+        const double sigma = sigmas[s];
+        const double inv_sigma = 1.0 / sigma;
+        const double c0 = -kLnSqrt2Pi - log(sigma);
+        const double* x = xs + (int64_t)s * xstride;
+        const bool start = first && s == 0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const double diff = x[i * ldx + d] - x[j * ldx + d];
-            s2 = fma(diff, diff, s2);
-        }
-        const double delta = sqrt(s2);
-        const double z = (py[kk] - delta) * inv_sigma;
-        const double t = delta * inv_sigma;
-        double lnphi = 0.0, mills;
-        if (__builtin_amdgcn_ballot_w64(t < 9.0)) log_phi_general_f64(t, lnphi, mills);
-        const double l = c0 - 0.5 * z * z - lnphi;
-        if (!live) continue;
-        if (first) {
-            acc[2 * k] = l;
-            acc[2 * k + 1] = 1.0;
-        } else {
-            const double mx = acc[2 * k];
-            if (l > mx) {
-                acc[2 * k + 1] = acc[2 * k + 1] * exp(mx - l) + 1.0;
-                acc[2 * k] = l;
-            } else {
-                acc[2 * k + 1] += exp(l - mx);
+        for (int u = 0; u < kLpdPairs; ++u) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const double diff = x[ii[u] * ldx + d] - x[jj[u] * ldx + d];
+                s2 = fma(diff, diff, s2);
             }
+            const double delta = sqrt(s2);
+            const double z = (yv[u] - delta) * inv_sigma;
+            const double t = delta * inv_sigma;
+            double lnphi = 0.0, mills;
+            if (__builtin_amdgcn_ballot_w64(t < 9.0)) log_phi_general_f64(t, lnphi, mills);
+            const double l = c0 - 0.5 * z * z - lnphi;
+            if (start) {
+                mx[u] = l;
+                sm[u] = 1.0;
+            } else if (l > mx[u]) {
+                sm[u] = sm[u] * exp(mx[u] - l) + 1.0;
+                mx[u] = l;
+            } else {
+                sm[u] += exp(l - mx[u]);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kLpdPairs; ++u) {
+        const int64_t k = base + (int64_t)u * kLpdThreads;
+        if (k < m) {
+            acc[2 * k] = mx[u];
+            acc[2 * k + 1] = sm[u];
         }
     }
 }
@@ -253,16 +278,21 @@ hipError_t launch_heldout_fill(const void* y, int dt, int64_t ld_y, const uint8_
 }
 
 hipError_t launch_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj,
-                                 const double* py, int d, const double* x, int64_t ldx,
-                                 const double* sigma, double* acc, int first, hipStream_t s)
+                                 const double* py, int d, const double* xs, int64_t ldx,
+                                 int64_t xstride, const double* sigmas, int32_t n_draws,
+                                 double* acc, int first, hipStream_t s)
 {
-    if (m == 0) return hipSuccess;
+    if (m == 0 || n_draws == 0) return hipSuccess;
     const int64_t per_block = (int64_t)kLpdThreads * kLpdPairs;
     const dim3 grid((unsigned)((m + per_block - 1) / per_block)), block(kLpdThreads);
 #define MDS_LPD_CASE(DD)                                                                     \
     case DD:                                                                                 \
-        hipLaunchKernelGGL(lpd_accumulate_kernel<DD>, grid, block, 0, s, m, pi, pj, py, x, ldx, \
-                           sigma, acc, first);                                               \
+        if (n_draws == 1)                                                                    \
+            hipLaunchKernelGGL((lpd_accumulate_kernel<DD, true>), grid, block, 0, s, m, pi, pj,   \
+                               py, xs, ldx, xstride, sigmas, n_draws, acc, first);           \
+        else                                                                                 \
+            hipLaunchKernelGGL((lpd_accumulate_kernel<DD, false>), grid, block, 0, s, m, pi, pj,  \
+                               py, xs, ldx, xstride, sigmas, n_draws, acc, first);           \
         break;
     switch (d) {
         MDS_LPD_CASE(1)

@@ -235,6 +235,13 @@ def test_heldout_and_lpd_reject():
     bad = list(acc)
     bad[7] = None                                    # no sigma
     assert L.mds_lpd_accumulate(*bad) == ERR_ARG
+    many = [10, _p(), _p(), _p(), 2, _p(), 2, 20, _p(), 3, _p(), 1, None]
+    for k, v, err in ((0, -1, ERR_ARG), (4, 9, ERR_UNSUP), (6, 1, ERR_ARG),
+                      (7, -2, ERR_ARG), (8, None, ERR_ARG), (9, -1, ERR_ARG),
+                      (5, _p(FAKE + 4), ERR_ARG)):
+        bad = list(many)
+        bad[k] = v                                   # one bad argument at a time
+        assert L.mds_lpd_accumulate_draws(*bad) == err, k
     lb = ctypes.c_size_t()
     assert L.mds_lpd_workspace_bytes(10, None) == ERR_ARG
     assert L.mds_lpd_workspace_bytes(10, ctypes.byref(lb)) == 0 and lb.value % 256 == 0

@@ -144,3 +144,28 @@ def test_lpd_paper_scale():
     _log(f"  pairs {m}: lpd {got:.15e} oracle {ref:.15e}")
     assert H.m == m
     assert abs(got - ref) <= 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("n,d,draws", [(300, 2, 5), (1500, 3, 7), (257, 6, 3)])
+def test_many_draws_per_pass_equal_single_draws_bitwise(n, d, draws):
+    # one pass over S draws equals S single-draw passes bit for bit, also
+    # after a first single draw (continuing sums), and matches the oracle
+    _log(f"lpd draws per pass: n={n} d={d} S={draws}")
+    y, heldout, mask, xs, sig = _case(n, d, 0.4, seed=n + 1, draws=draws, nan_frac=0.01)
+    H1, got1 = _run(y, heldout, mask, xs, sig)
+    H2 = api.HeldOutPairs(torch.as_tensor(y), heldout, mask)
+    H2.add_draws(xs, sig)
+    H3 = api.HeldOutPairs(torch.as_tensor(y), heldout, mask)
+    H3.add_draw(xs[0], float(sig[0]))
+    H3.add_draws(xs[1:], sig[1:])
+    H3.add_draws(xs[:0], sig[:0])                      # no draws: nothing changes
+    assert H2.draws == H3.draws == draws
+    k = 2 * H1.m
+    a1 = H1.acc.cpu().numpy()[:k]
+    assert np.array_equal(a1, H2.acc.cpu().numpy()[:k])
+    assert np.array_equal(a1, H3.acc.cpu().numpy()[:k])
+    got2, got3 = H2.lpd().item(), H3.lpd().item()
+    assert got1 == got2 == got3
+    ref, _ = oracle.lpd(xs, sig, y, heldout, mask)
+    _log(f"  pairs {H1.m}: lpd {got2:.15e} oracle {ref:.15e}")
+    assert abs(got2 - ref) <= 1e-12 * abs(ref)
