@@ -279,6 +279,67 @@ def tile_trace(out_path, events):
     print(json.dumps(out), flush=True)
 
 
+
+# bytes one lpd accumulation pass moves per held-out pair: row and column
+# (int32 each), y (FP64), and the 2-double state read and written
+LPD_BYTES_PER_PAIR_PASS = 4 + 4 + 8 + 16 + 16
+
+
+def heldout_lpd(prob, xd, sigma, dev, draws=100, per_pass=10):
+    """The held-out predictive density of 10% of the pairs of `prob` at the
+    locations `xd` (original labelling): compaction time, then `draws` draws
+    one per pass and `draws` draws `per_pass` per pass.  Returns the bench
+    record (with the HBM figures of the single-draw pass), the lpd of the
+    single-draw accumulator and the held-out mask."""
+    import numpy as np
+    import torch
+    from paper_1905_04582_amd import api, synth
+    n = prob.n
+    held = synth.symmetric_mask(n, 0.10, np.random.Generator(np.random.PCG64(prob.seed + 9)))
+    y_d = torch.as_tensor(prob.y, device=dev)
+    held_d = torch.as_tensor(held, device=dev)
+    mask_d = torch.as_tensor(prob.mask, device=dev)
+    api.HeldOutPairs(y_d, held_d, mask_d, dev)          # warm: allocator and code paths
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = api.HeldOutPairs(y_d, held_d, mask_d, dev)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    sig_d = torch.tensor(sigma, dtype=torch.float64, device=dev)
+    for _ in range(5):
+        H.add_draw(xd, sig_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(draws):
+        H.add_draw(xd, sig_d)
+    torch.cuda.synchronize()
+    draw_ms = (time.perf_counter() - t0) * 1e3 / draws
+    lpd_val = H.lpd().item()
+    # the same draws folded per_pass to a pass (the per-pair state read and
+    # written once per pass), in a second accumulator
+    xs = xd.unsqueeze(0).expand(per_pass, -1, -1).contiguous()
+    sigs = sig_d.expand(per_pass).contiguous()
+    Hb = api.HeldOutPairs(y_d, held_d, mask_d, dev)
+    Hb.add_draws(xs, sigs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(draws // per_pass):
+        Hb.add_draws(xs, sigs)
+    torch.cuda.synchronize()
+    batched_ms = (time.perf_counter() - t0) * 1e3 / draws
+    pass_bytes = H.m * LPD_BYTES_PER_PAIR_PASS
+    achieved = pass_bytes / (draw_ms * 1e-3) / 1e9
+    rec = {"pairs": H.m, "draws": H.draws, "compaction_ms": round(setup_ms, 3),
+           "ms_per_draw": round(draw_ms, 5),
+           f"ms_per_draw_{per_pass}_per_pass": round(batched_ms, 5),
+           "pairs_per_s": round(H.m / (draw_ms * 1e-3), 1), "lpd": lpd_val,
+           "roofline": {"bound": "hbm", "kernel": "lpd_accumulate_kernel (one draw per pass)",
+                        "algorithmic_bytes_per_launch": pass_bytes,
+                        "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+    return rec, lpd_val, held
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,7 +347,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-evals", type=int, default=10)
-    ap.add_argument("--only", choices=("fp64", "fp32", "fp64-plain", "fp32-plain"), default=None,
+    ap.add_argument("--only", choices=("fp64", "fp32", "fp64-plain", "fp32-plain", "lpd"),
+                    default=None,
                     help="time one form only (for profiler runs); prints a short JSON line")
     ap.add_argument("--n-sweep", action="store_true",
                     help="time the evaluation against N instead (one JSON line with a point "
@@ -337,6 +399,11 @@ def main():
     n, d, sigma = prob.n, prob.d, prob.sigma
     x = torch.as_tensor(prob.x, device=dev).contiguous()
     npairs = n * (n - 1) // 2
+    if args.only == "lpd":
+        # the held-out density alone (for profiler runs), at the evaluation point
+        rec, _, _ = heldout_lpd(prob, x, sigma, dev, draws=max(10, args.steps))
+        print(json.dumps({"form": "lpd", **rec}), flush=True)
+        return
     events = HipEvents()
 
     # set-up (not timed as a step): relabel the locations in Hilbert order of
@@ -421,47 +488,9 @@ def main():
 
     # held-out predictive density: 10% of the pairs held out (symmetric
     # Bernoulli), compacted once, then one accumulation pass per posterior
-    # draw (the chain's states stand in for draws) and one finalize
-    held = synth.symmetric_mask(n, 0.10, np.random.Generator(np.random.PCG64(prob.seed + 9)))
-    y_d = torch.as_tensor(prob.y, device=dev)
-    held_d = torch.as_tensor(held, device=dev)
-    mask_d = torch.as_tensor(prob.mask, device=dev)
-    api.HeldOutPairs(y_d, held_d, mask_d, dev)          # warm: allocator and code paths
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    H = api.HeldOutPairs(y_d, held_d, mask_d, dev)
-    torch.cuda.synchronize()
-    lpd_setup_ms = (time.perf_counter() - t0) * 1e3
+    # draw (the chain's final state stands in for the draws) and one finalize
     xd = P64.unlabel(chain.x)
-    sig_d = torch.tensor(sigma, dtype=torch.float64, device=dev)
-    for _ in range(5):
-        H.add_draw(xd, sig_d)
-    torch.cuda.synchronize()
-    lpd_draws = 100
-    t0 = time.perf_counter()
-    for _ in range(lpd_draws):
-        H.add_draw(xd, sig_d)
-    torch.cuda.synchronize()
-    lpd_draw_ms = (time.perf_counter() - t0) * 1e3 / lpd_draws
-    lpd_val = H.lpd().item()
-    # the same draws folded ten per pass (the per-pair state read and
-    # written once per pass): a second accumulator over 100 draws
-    per_pass = 10
-    xs10 = xd.unsqueeze(0).expand(per_pass, -1, -1).contiguous()
-    sig10 = sig_d.expand(per_pass).contiguous()
-    H10 = api.HeldOutPairs(y_d, held_d, mask_d, dev)
-    H10.add_draws(xs10, sig10)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(lpd_draws // per_pass):
-        H10.add_draws(xs10, sig10)
-    torch.cuda.synchronize()
-    lpd_batched_ms = (time.perf_counter() - t0) * 1e3 / lpd_draws
-    del y_d, held_d, mask_d
-    heldout = {"pairs": H.m, "draws": H.draws, "compaction_ms": round(lpd_setup_ms, 3),
-               "ms_per_draw": round(lpd_draw_ms, 5),
-               "ms_per_draw_10_per_pass": round(lpd_batched_ms, 5),
-               "pairs_per_s": round(H.m / (lpd_draw_ms * 1e-3), 1), "lpd": lpd_val}
+    heldout, lpd_val, held = heldout_lpd(prob, xd, sigma, dev)
 
     # batched form: 64 independent problems, N ~ U[500, 8000], D in {2, 4, 6},
     # sigma ~ U(0.2, 1), 10% missing, FP32 Y drawn in device memory; one
