@@ -98,13 +98,83 @@ static int device_eval(const char* in_path, const char* out_path)
               hipMemcpy(&ds, dds, 8, hipMemcpyDeviceToHost) == hipSuccess &&
               hipMemcpy(&m, dm, 8, hipMemcpyDeviceToHost) == hipSuccess,
           "download");
+
+    /* held-out predictive density over two draws (x, and x + 0.01), one
+       pass: pairs with (i + j) % 7 == 0 held out */
+    uint8_t* held = (uint8_t*)malloc((size_t)(n * n));
+    double* xs = (double*)malloc(sizeof(double) * (size_t)(2 * n * d));
+    CHECK(held && xs, "host allocation (held-out)");
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) held[i * n + j] = (uint8_t)((i + j) % 7 == 0);
+    for (int64_t k = 0; k < n * d; ++k) {
+        xs[k] = x[k];
+        xs[n * d + k] = x[k] + 0.01;
+    }
+    const double sigmas[2] = {sigma, 1.1 * sigma};
+    size_t hwb = 0, fwb = 0;
+    CHECK(mds_heldout_workspace_bytes(n, &hwb) == MDS_OK, "held-out workspace size");
+    uint8_t* dheld;
+    double *dxs, *dsigs, *dlpd;
+    int64_t* dmh;
+    void* dhw;
+    CHECK(hipMalloc((void**)&dheld, (size_t)(n * n)) == hipSuccess &&
+              hipMalloc((void**)&dxs, sizeof(double) * (size_t)(2 * n * d)) == hipSuccess &&
+              hipMalloc((void**)&dsigs, 16) == hipSuccess &&
+              hipMalloc((void**)&dlpd, 8) == hipSuccess && hipMalloc((void**)&dmh, 8) == hipSuccess &&
+              hipMalloc(&dhw, hwb) == hipSuccess,
+          "device allocation (held-out)");
+    CHECK(hipMemcpy(dheld, held, (size_t)(n * n), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(dxs, xs, sizeof(double) * (size_t)(2 * n * d), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMemcpy(dsigs, sigmas, 16, hipMemcpyHostToDevice) == hipSuccess,
+          "upload (held-out)");
+    CHECK(mds_heldout_count(dy_src, MDS_F64, n, NULL, 0, dheld, n, n, dmh, dhw, hwb, NULL) ==
+              MDS_OK,
+          "held-out count");
+    int64_t mh = 0;
+    CHECK(hipMemcpy(&mh, dmh, 8, hipMemcpyDeviceToHost) == hipSuccess && mh > 0, "held-out m");
+    int32_t *dpi, *dpj;
+    double *dpy, *dacc;
+    void* dfw;
+    CHECK(mds_lpd_workspace_bytes(mh, &fwb) == MDS_OK, "lpd workspace size");
+    CHECK(hipMalloc((void**)&dpi, 4 * (size_t)mh) == hipSuccess &&
+              hipMalloc((void**)&dpj, 4 * (size_t)mh) == hipSuccess &&
+              hipMalloc((void**)&dpy, 8 * (size_t)mh) == hipSuccess &&
+              hipMalloc((void**)&dacc, 16 * (size_t)mh) == hipSuccess &&
+              hipMalloc(&dfw, fwb) == hipSuccess,
+          "device allocation (pairs)");
+    CHECK(mds_heldout_fill(dy_src, MDS_F64, n, NULL, 0, dheld, n, n, dhw, hwb, mh, dpi, dpj, dpy,
+                           NULL) == MDS_OK,
+          "held-out fill");
+    CHECK(mds_lpd_accumulate_draws(mh, dpi, dpj, dpy, d, dxs, d, n * d, dsigs, 2, dacc, 1,
+                                   NULL) == MDS_OK,
+          "lpd accumulate (two draws)");
+    CHECK(mds_lpd_finalize(mh, dacc, 2, dfw, fwb, dlpd, NULL) == MDS_OK, "lpd finalize");
+    double lpd;
+    CHECK(hipMemcpy(&lpd, dlpd, 8, hipMemcpyDeviceToHost) == hipSuccess, "download lpd");
+
     FILE* o = fopen(out_path, "wb");
     CHECK(o != NULL, "open output");
     fwrite(&L, 8, 1, o);
     fwrite(&ds, 8, 1, o);
     fwrite(&m, 8, 1, o);
     fwrite(g, 8, (size_t)(n * d), o);
+    fwrite(&lpd, 8, 1, o);
+    fwrite(&mh, 8, 1, o);
     fclose(o);
+    hipFree(dheld);
+    hipFree(dxs);
+    hipFree(dsigs);
+    hipFree(dlpd);
+    hipFree(dmh);
+    hipFree(dhw);
+    hipFree(dpi);
+    hipFree(dpj);
+    hipFree(dpy);
+    hipFree(dacc);
+    hipFree(dfw);
+    free(held);
+    free(xs);
     hipFree(dx);
     hipFree(dy_src);
     hipFree(dy);
@@ -117,7 +187,8 @@ static int device_eval(const char* in_path, const char* out_path)
     free(x);
     free(y);
     free(g);
-    printf("capi device evaluation ok: n=%lld L=%.17g\n", (long long)n, L);
+    printf("capi device evaluation ok: n=%lld L=%.17g lpd=%.17g over %lld held-out pairs\n",
+           (long long)n, L, lpd, (long long)mh);
     return 0;
 }
 
