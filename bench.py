@@ -214,57 +214,47 @@ def n_sweep(args, events):
         "points": rows_out}), flush=True)
 
 
-def tile_trace(out_path, events):
-    """Per-wave timeline of the FP64 sweep at N = 5392 (default tiles, relabelled):
-    needs a library built with -DMDS_TILE_TRACE=1 (named by MDS_LIB_PATH)."""
+def tile_trace(out_path, events, tile_rows=0, tile_waves=0):
+    """Per-wave timeline of the FP64 sweep at N = 5392 (relabelled; default
+    tiles unless given): start and end clock and hardware slot of every wave
+    (mds_set_tile_trace)."""
     import numpy as np
     import torch
 
     from paper_1905_04582_amd import api, synth
 
-    L = api.lib()
-    if not hasattr(L, "mds_set_tile_trace"):
-        sys.exit("--tile-trace needs the diagnostic build: python -m paper_1905_04582_amd.build "
-                 "-DMDS_TILE_TRACE=1 --out <lib>, then MDS_LIB_PATH=<lib>")
-    L.mds_set_tile_trace.argtypes = [ctypes.c_void_p]
     dev = torch.device("cuda:0")
     prob = synth.preset("paper_fp64")
     n = prob.n
-    P = api.MDSProblem(prob.y, 2, prob.mask, torch.float64, dev, order=prob.x)
-    br, w = api.mds_resolve_tiling(n, 2, api.MDS_F64)
-    cw, nrb = 64 * w, (n + br - 1) // br
-    if br >= cw:
-        sys.exit("--tile-trace assumes tiles narrower in rows than in columns")
-    k = cw // br
-    a, b = divmod(nrb, k)
-    ntiles = nrb + k * a * (a - 1) // 2 + a * b          # tiles of the lower triangle (br < cw)
+    P = api.MDSProblem(prob.y, 2, prob.mask, torch.float64, dev, order=prob.x,
+                       tile_rows=tile_rows, tile_waves=tile_waves)
+    br, tw = api.mds_resolve_tiling(n, 2, api.MDS_F64, tile_rows, tile_waves)
+    wc, wr = api.split_tile_waves(tw)
+    w = wc * wr
+    ntiles = api.tile_count(n, br, wc)
     buf = torch.zeros(ntiles * w * 3, dtype=torch.int64, device=dev)
     xr = P.relabel(torch.as_tensor(prob.x, device=dev))
     sig = torch.tensor(prob.sigma, dtype=torch.float64, device=dev)
     for _ in range(20):
         P.gradient(xr, sig)
     torch.cuda.synchronize()
-    L.mds_set_tile_trace(ctypes.c_void_p(buf.data_ptr()))
+    api.mds_set_tile_trace(buf)
     P.gradient(xr, sig)
     torch.cuda.synchronize()
-    L.mds_set_tile_trace(None)
+    api.mds_set_tile_trace(None)
     tr = buf.view(ntiles, w, 3).cpu().numpy()
     t0 = tr[:, :, 0].min()
     s, e = (tr[:, :, 0] - t0) * 0.01, (tr[:, :, 1] - t0) * 0.01      # 100 MHz clock -> us
     hw = tr[:, :, 2]
-    slot = (np.arange(ntiles) % 8)[:, None] * 4096 + ((hw >> 13) & 7) * 512 + \
-        ((hw >> 12) & 1) * 256 + ((hw >> 8) & 15) * 4 + ((hw >> 4) & 3)
+    xcd = (np.arange(ntiles) % 8)[:, None]
+    slot = xcd * 4096 + ((hw >> 13) & 7) * 512 + ((hw >> 12) & 1) * 256 + \
+        ((hw >> 8) & 15) * 4 + ((hw >> 4) & 3)
     _, per_simd = np.unique(slot, return_counts=True)
-    # tile -> (row block r, column block c), and its rows' distance from the diagonal
-    r_of = np.zeros(ntiles, np.int64)
-    first = np.array([r + k * (r // k) * (r // k - 1) // 2 + (r // k) * (r % k) for r in range(nrb + 1)])
-    r_of = np.searchsorted(first, np.arange(ntiles), side="right") - 1
-    c_of = np.arange(ntiles) - first[r_of]
-    dist = (r_of * br - c_of * cw)[:, None].repeat(w, 1)
     ts = np.linspace(0.0, float(e.max()), 15)
     dur = e - s
-    bands = [(0, 256), (256, 1024), (1024, 3000), (3000, 10 ** 9)]
-    out = {"n": n, "tiles": [br, cw], "waves": int(ntiles * w), "span_us": round(float(e.max()), 2),
+    busy = np.sort(np.concatenate([s.ravel(), e.ravel()]))
+    out = {"n": n, "tile_rows": br, "column_waves": wc, "row_waves": wr, "tiles": ntiles,
+           "waves": int(ntiles * w), "span_us": round(float(e.max()), 2),
            "last_start_us": round(float(s.max()), 2),
            "active_waves_at": {f"{t:.1f}": int(((s <= t) & (e > t)).sum()) for t in ts},
            "waves_per_simd": {"min": int(per_simd.min()), "max": int(per_simd.max()),
@@ -272,11 +262,12 @@ def tile_trace(out_path, events):
            "wave_us": {"mean": round(float(dur.mean()), 2), "p50": round(float(np.median(dur)), 2),
                        "p90": round(float(np.percentile(dur, 90)), 2),
                        "max": round(float(dur.max()), 2)},
-           "wave_us_by_rows_from_diagonal": {f"{lo}-{hi}": round(float(dur[(dist >= lo) & (dist < hi)].mean()), 2)
-                                             for lo, hi in bands if ((dist >= lo) & (dist < hi)).any()}}
-    with open(out_path, "w") as f:
-        json.dump(out, f, indent=1)
+           "wave_busy_us_total": round(float(dur.sum()), 1), "events": int(busy.size)}
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump(out, f, indent=1)
     print(json.dumps(out), flush=True)
+    return out
 
 
 
@@ -358,7 +349,10 @@ def main():
     ap.add_argument("--cpu-max-n", type=int, default=20000,
                     help="largest N at which the N sweep times the serial oracle")
     ap.add_argument("--tile-trace", default=None, metavar="JSON",
-                    help="diagnostic build only: write the per-wave timeline of one FP64 sweep")
+                    help="write the per-wave timeline of one FP64 sweep (diagnostics)")
+    ap.add_argument("--tile-rows", type=int, default=0, help="tile rows for --tile-trace")
+    ap.add_argument("--tile-waves", type=int, default=0,
+                    help="tile_waves (MDS_TILE_WAVES(wc, wr)) for --tile-trace")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of MB megabytes (calibrates the HBM "
                          "byte counters) and exit")
@@ -381,7 +375,7 @@ def main():
     if args.tile_trace:
         import torch
         torch.cuda.init()
-        tile_trace(args.tile_trace, None)
+        tile_trace(args.tile_trace, None, args.tile_rows, args.tile_waves)
         return
     if args.n_sweep:
         import torch

@@ -49,10 +49,14 @@
  *   - Results are deterministic: the same inputs on the same device give
  *     bitwise identical outputs (fixed-order reductions, no float atomics).
  *   - Pair tiling: `tile_rows` (rows per tile: 8, 16, 32, 64, 128 or 256) and
- *     `tile_waves` (64-wide column groups per tile: 1, 2, 4 or 8) pick the
- *     tile shape; 0 selects the built-in default for (dtype, D, N).  One of
- *     tile_rows and 64*tile_waves must divide the other.  The workspace
- *     must be sized with the same values.
+ *     `tile_waves` pick the tile shape and its waves; 0 selects the built-in
+ *     default for (dtype, D, N).  tile_waves = MDS_TILE_WAVES(wc, wr): wc
+ *     64-wide column groups per tile (1, 2, 4 or 8; the tile is 64*wc
+ *     columns wide) and wr waves down the tile's rows (1, 2, 4 or 8; each
+ *     walks tile_rows/wr >= 8 rows); wc * wr <= 8 waves per work-group.  A
+ *     plain count (wr = 0 in the second byte) means wr = 1.  One of
+ *     tile_rows and 64*wc must divide the other.  The workspace depends on
+ *     tile_rows and wc only, and must be sized with the same values.
  */
 #ifndef MASSIVEMDS_H
 #define MASSIVEMDS_H
@@ -77,8 +81,7 @@ enum mds_status {
     MDS_ERR_UNSUPPORTED = -2,      /* D outside 1..MDS_MAX_DIM, unknown dtype, bad tiling */
     MDS_ERR_WORKSPACE_TOO_SMALL = -3,
     MDS_ERR_HIP = -4, /* a HIP runtime call failed; mds_last_error() names it */
-    MDS_ERR_NOT_SYMMETRIC = -5 /* reported by the bindings when mds_check_symmetric
-                                  finds mismatched pairs */
+    MDS_ERR_NOT_SYMMETRIC = -5 /* mds_require_symmetric found mismatched pairs */
 };
 
 /* element types */
@@ -97,6 +100,8 @@ enum mds_dtype { MDS_F64 = 0, MDS_F32 = 1 };
 #define MDS_MAX_N ((int64_t)1 << 30)
 /* workspace pointers must be aligned to this many bytes */
 #define MDS_WORKSPACE_ALIGN 256
+/* the tile_waves argument: wc column waves, wr row waves */
+#define MDS_TILE_WAVES(wc, wr) ((int32_t)(wc) | ((int32_t)(wr) << 8))
 
 /* Human-readable name of a status code (static string). */
 MDS_API const char* mds_status_string(int status);
@@ -119,8 +124,10 @@ MDS_API int mds_workspace_bytes(int64_t n, int32_t d, int32_t y_dtype, int32_t t
  * The tiling the sweeps use for these arguments: tile_rows / tile_waves as
  * passed to mds_loglik and friends (0 = the library's default for n, d and
  * y_dtype), resolved and validated.  Writes *rows_out (rows per tile) and
- * *waves_out (64-column groups per tile); returns a status (an unsupported
- * tiling is MDS_ERR_UNSUPPORTED, as in the evaluation calls).
+ * *waves_out (the resolved MDS_TILE_WAVES(wc, wr); a plain count wc when
+ * wr = 1);
+ * returns a status (an unsupported tiling is MDS_ERR_UNSUPPORTED, as in the
+ * evaluation calls).
  */
 MDS_API int mds_resolve_tiling(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
                        int32_t tile_waves, int32_t* rows_out, int32_t* waves_out);
@@ -159,6 +166,16 @@ MDS_API int mds_prepare_y(const void* y_src, int32_t src_dtype, int64_t ld_src,
  */
 MDS_API int mds_check_symmetric(const void* y, int32_t y_dtype, int64_t ldy, int64_t n,
                         int64_t* mismatches_dev, hipStream_t stream);
+
+/*
+ * The checked mode of the symmetry test: mds_check_symmetric, then a wait for
+ * `stream` and a read-back of the count.  Returns MDS_OK for a symmetric Y
+ * and MDS_ERR_NOT_SYMMETRIC (mds_last_error() gives the count) otherwise.
+ * Synchronous, so not capturable: a set-up call, once per prepared Y.
+ * mismatches_dev is a caller-owned device int64 (it receives the count).
+ */
+MDS_API int mds_require_symmetric(const void* y, int32_t y_dtype, int64_t ldy, int64_t n,
+                                  int64_t* mismatches_dev, hipStream_t stream);
 
 /*
  * Spatial relabelling of the locations (a set-up step, not part of the
@@ -390,7 +407,7 @@ typedef struct mds_problem_desc {
 typedef struct mds_batch_plan {
     int32_t count;
     int32_t y_dtype;
-    int32_t tile_waves;
+    int32_t tile_waves;      /* waves per work-group of the persistent sweep (wc * wr) */
     int32_t grid;            /* persistent work-groups */
     int32_t max_d;           /* largest D of the batch */
     int32_t flags;           /* bit 0: every problem has momenta, step, grad and loglik */
@@ -406,7 +423,7 @@ typedef struct mds_batch_plan {
  * one finalize launch per evaluation.  Each problem's results equal, bit for
  * bit, those of mds_gradient with the same tile_rows and tile_waves.
  *   mds_batch_workspace_bytes: workspace for the batch (tile_waves common to
- *     the batch, 0 = 4; y_dtype common to the batch).
+ *     the batch, 0 = MDS_TILE_WAVES(4, 1); y_dtype common to the batch).
  *   mds_batch_init: validates every descriptor, writes the device-side
  *     problem table into the workspace with one host-to-device copy on
  *     `stream` and waits for it (not capturable; call once per batch layout),
@@ -449,6 +466,17 @@ MDS_API int mds_batch_leapfrog(const mds_batch_plan* plan, int32_t n_steps, int3
  * results.
  */
 MDS_API int mds_set_sweep_events(hipEvent_t before, hipEvent_t after);
+
+/*
+ * Diagnostics for benchmarks: while `trace` is non-NULL, every single-problem
+ * pair sweep launched by this thread writes, for wave w of the work-group of
+ * tile t (in launch order), three uint64 at trace[(t * waves + w) * 3]: its
+ * start and end reading of the 100 MHz real-time clock and its hardware slot
+ * (the HW_ID register).  The caller sizes the buffer (ntiles * waves * 3
+ * uint64, from mds_resolve_tiling); 8-byte aligned.  Thread-local; NULL
+ * stops it; no effect on results.
+ */
+MDS_API int mds_set_tile_trace(void* trace);
 
 #ifdef __cplusplus
 }

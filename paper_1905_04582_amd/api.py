@@ -109,6 +109,8 @@ def lib():
     L.mds_lpd_workspace_bytes.argtypes = [_c_i64, ctypes.POINTER(ctypes.c_size_t)]
     L.mds_check_symmetric.restype = ctypes.c_int
     L.mds_check_symmetric.argtypes = [_vp, _c_i32, _c_i64, _c_i64, _vp, _vp]
+    L.mds_require_symmetric.restype = ctypes.c_int
+    L.mds_require_symmetric.argtypes = [_vp, _c_i32, _c_i64, _c_i64, _vp, _vp]
     L.mds_resolve_tiling.restype = ctypes.c_int
     L.mds_resolve_tiling.argtypes = [_c_i64, _c_i32, _c_i32, _c_i32, _c_i32,
                                      ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]
@@ -133,6 +135,8 @@ def lib():
     L.mds_log_phi.argtypes = [_vp, _vp, _vp, _c_i64, _c_i32, _vp]
     L.mds_set_sweep_events.restype = ctypes.c_int
     L.mds_set_sweep_events.argtypes = [_vp, _vp]
+    L.mds_set_tile_trace.restype = ctypes.c_int
+    L.mds_set_tile_trace.argtypes = [_vp]
     L.mds_batch_workspace_bytes.restype = ctypes.c_int
     L.mds_batch_workspace_bytes.argtypes = [ctypes.POINTER(ProblemDesc), _c_i32, _c_i32, _c_i32,
                                             ctypes.POINTER(ctypes.c_size_t)]
@@ -211,9 +215,23 @@ def mds_workspace_bytes(n: int, d: int, y_dtype: int, tile_rows: int = 0,
     return int(out.value)
 
 
+def tile_waves(wc: int, wr: int = 1) -> int:
+    """The tile_waves argument: wc 64-column waves across a tile, wr waves
+    down its rows (MDS_TILE_WAVES)."""
+    return int(wc) | (int(wr) << 8) if wr != 1 else int(wc)
+
+
+def split_tile_waves(tw: int):
+    """(column waves, row waves) of a tile_waves value."""
+    wr = (int(tw) >> 8) & 0xFF
+    return int(tw) & 0xFF, (wr if wr else 1)
+
+
 def mds_resolve_tiling(n: int, d: int, y_dtype: int, tile_rows: int = 0,
                        tile_waves: int = 0):
-    """(rows per tile, 64-column groups per tile) the sweeps use."""
+    """(rows per tile, tile_waves) the sweeps use; tile_waves is the plain
+    column-wave count when the tile's waves do not split its rows (see
+    ``split_tile_waves``)."""
     r, w = _c_i32(), _c_i32()
     _check(lib().mds_resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, ctypes.byref(r),
                                     ctypes.byref(w)), "mds_resolve_tiling")
@@ -264,6 +282,17 @@ def mds_check_symmetric(y: torch.Tensor, stream=None) -> int:
     _check(lib().mds_check_symmetric(_ptr(y), _dtype_code(y.dtype), _ld(y), n, _ptr(cnt),
                                      _stream(stream)), "mds_check_symmetric")
     return int(cnt.item())
+
+
+def mds_require_symmetric(y: torch.Tensor, stream=None):
+    """The library's checked mode: raises MDSError(MDS_ERR_NOT_SYMMETRIC) when
+    some pair i > j has y[i, j] != y[j, i] (two NaNs count as equal);
+    synchronises."""
+    _check_mat(y, "y", y.dtype)
+    n = y.shape[0]
+    cnt = torch.zeros((), dtype=torch.int64, device=y.device)
+    _check(lib().mds_require_symmetric(_ptr(y), _dtype_code(y.dtype), _ld(y), n, _ptr(cnt),
+                                       _stream(stream)), "mds_require_symmetric")
 
 
 def _check_perm(perm, n, device):
@@ -442,6 +471,27 @@ def mds_set_sweep_events(before, after):
     _check(lib().mds_set_sweep_events(before, after), "mds_set_sweep_events")
 
 
+def mds_set_tile_trace(buf):
+    """Record every later single-problem sweep's per-wave (start clock, end
+    clock, hardware slot) in ``buf`` (a uint64/int64 device tensor of
+    tiles * waves * 3 entries), or stop with None.  Diagnostics only."""
+    _check(lib().mds_set_tile_trace(None if buf is None else ctypes.c_void_p(buf.data_ptr())),
+           "mds_set_tile_trace")
+
+
+def tile_count(n: int, tile_rows: int, wc: int) -> int:
+    """Work-groups of one sweep: tiles of tile_rows x 64*wc over the lower
+    triangle of an n x n matrix."""
+    br, cw = int(tile_rows), 64 * int(wc)
+    nrb = (int(n) + br - 1) // br
+    if br >= cw:
+        k = br // cw
+        return k * nrb * (nrb + 1) // 2
+    k = cw // br
+    a, b = divmod(nrb, k)
+    return nrb + k * a * (a - 1) // 2 + a * b
+
+
 class MDSProblem:
     """A prepared dissimilarity matrix on the device plus its workspace.
 
@@ -477,10 +527,7 @@ class MDSProblem:
             self.perm = mds_spatial_order(xo)
         self.y, self.m_obs = mds_prepare_y(src, dtype, m, perm=self.perm)
         if check_symmetric:
-            bad = mds_check_symmetric(self.y)
-            if bad:
-                raise MDSError(MDS_ERR_NOT_SYMMETRIC, "MDSProblem",
-                               f"{bad} pairs with y[i, j] != y[j, i] (Y or mask not symmetric)")
+            mds_require_symmetric(self.y)
         del src, m
         self.tile_rows, self.tile_waves = tile_rows, tile_waves
         self.ws_bytes = mds_workspace_bytes(n, self.d, _dtype_code(dtype), tile_rows, tile_waves)

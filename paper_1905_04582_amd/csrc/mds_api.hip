@@ -102,50 +102,76 @@ constexpr size_t kMaxSweepLds = 64 * 1024;
 // the dispatcher balance tiles of uneven cost (tiles whose wavefronts skip the
 // truncation terms are cheap); larger problems run long enough for 64 x 256
 // tiles, which write fewer partial sums.
-void default_tiling(int64_t n, int d, int dtype, int* br, int* waves)
+void default_tiling(int64_t n, int d, int dtype, int* br, int* wc, int* wr)
 {
     (void)d;
     (void)dtype;
+    *wr = 1;
     if (n <= 1536) {
         *br = 8;
-        *waves = 1;
+        *wc = 1;
     } else if (n <= 3072) {
         *br = 16;
-        *waves = 1;
+        *wc = 1;
     } else if (n <= 6144) {
         *br = 32;
-        *waves = 4;
+        *wc = 4;
     } else {
         *br = 64;
-        *waves = 4;
+        *wc = 4;
     }
 }
 
+bool pow2_upto8(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
+
 int resolve_tiling(int64_t n, int d, int dtype, int tile_rows, int tile_waves, Tiling* out)
 {
-    int br = tile_rows, waves = tile_waves;
-    if (br == 0 || waves == 0) {
-        int dbr, dw;
-        default_tiling(n, d, dtype, &dbr, &dw);
+    int br = tile_rows, wc = 0, wr = 1;
+    if (tile_waves != 0) {
+        if (tile_waves & ~0xFFFF)
+            return fail(MDS_ERR_UNSUPPORTED, "tile_waves=0x%x: only bits 0-15 are defined",
+                        (unsigned)tile_waves);
+        wc = tile_waves & 0xFF;
+        wr = (tile_waves >> 8) & 0xFF;
+        if (wr == 0) wr = 1;
+        if (!pow2_upto8(wc))
+            return fail(MDS_ERR_UNSUPPORTED, "tile_waves: %d column waves (must be 1, 2, 4 or 8)",
+                        wc);
+        if (!pow2_upto8(wr))
+            return fail(MDS_ERR_UNSUPPORTED, "tile_waves: %d row waves (must be 1, 2, 4 or 8)",
+                        wr);
+    }
+    if (br == 0 || wc == 0) {
+        int dbr, dwc, dwr;
+        default_tiling(n, d, dtype, &dbr, &dwc, &dwr);
         if (br == 0) br = dbr;
-        if (waves == 0) waves = dw;
+        if (wc == 0) {
+            wc = dwc;
+            wr = dwr;
+        }
     }
     if (br != 8 && br != 16 && br != 32 && br != 64 && br != 128 && br != 256)
         return fail(MDS_ERR_UNSUPPORTED, "tile_rows=%d: must be 8, 16, 32, 64, 128 or 256", br);
-    if (waves != 1 && waves != 2 && waves != 4 && waves != 8)
-        return fail(MDS_ERR_UNSUPPORTED, "tile_waves=%d: must be 1, 2, 4 or 8", waves);
-    const int cw = kWave * waves;
+    if (wc * wr > 8)
+        return fail(MDS_ERR_UNSUPPORTED, "%d x %d waves per tile: at most 8", wc, wr);
+    if (br / wr < 8)
+        return fail(MDS_ERR_UNSUPPORTED, "tile_rows=%d split over %d row waves: each needs >= 8 rows",
+                    br, wr);
+    const int cw = kWave * wc;
     if (!(br % cw == 0 || cw % br == 0))
         return fail(MDS_ERR_UNSUPPORTED, "tile_rows=%d and 64*tile_waves=%d: neither divides the other",
                     br, cw);
     // staged rows hold Y's element type; a model flag in dtype's high bits
     // does not change it
-    *out = make_tiling(n, br, waves, (dtype & 0xff) == MDS_F32 ? 4 : 8);
+    *out = make_tiling(n, br, wc, wr, (dtype & 0xff) == MDS_F32 ? 4 : 8);
     if (sweep_lds_bytes(*out, d) > kMaxSweepLds)
         return fail(MDS_ERR_UNSUPPORTED, "tile %dx%d with D=%d needs %zu B of LDS (max %zu)", br,
                     cw, d, sweep_lds_bytes(*out, d), kMaxSweepLds);
     return MDS_OK;
 }
+
+// the tile_waves value of a resolved tiling (a plain count when wr = 1)
+int32_t packed_waves(const Tiling& t) { return t.wr == 1 ? t.wc : (t.wc | (t.wr << 8)); }
 
 int check_problem(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
                   int32_t y_dtype, int64_t ldy, const double* sigma_dev)
@@ -191,10 +217,8 @@ hipError_t timed_sweep(int y_dtype, int d, bool grad, const Tiling& t, const Swe
     return launch_sweep(y_dtype, d, grad, t, a, s, g_ev_before, g_ev_after);
 }
 
-#if MDS_TILE_TRACE
-// diagnostic build only: where the sweep writes its per-wave clocks
-unsigned long long* g_tile_trace = nullptr;
-#endif
+// diagnostics: where single-problem sweeps write their per-wave clocks
+thread_local unsigned long long* g_tile_trace = nullptr;
 
 SweepArgs sweep_args(const Tiling& t, const WorkspaceLayout& lay, void* ws, int64_t n,
                      const double* x, int64_t ldx, const void* y, int64_t ldy,
@@ -212,13 +236,13 @@ SweepArgs sweep_args(const Tiling& t, const WorkspaceLayout& lay, void* ws, int6
     a.br = t.br;
     a.cw = t.cw;
     a.nrb = t.nrb;
+    a.wc = t.wc;
+    a.wr = t.wr;
     a.rowpart = reinterpret_cast<double*>(base + lay.rowpart);
     a.colpart = reinterpret_cast<double*>(base + lay.colpart);
     a.tscal = reinterpret_cast<double*>(base + lay.tscal);
     a.tcount = reinterpret_cast<uint32_t*>(base + lay.tcount);
-#if MDS_TILE_TRACE
     a.trace = g_tile_trace;
-#endif
     return a;
 }
 
@@ -241,14 +265,6 @@ FinalizeArgs finalize_args(const Tiling& t, const SweepArgs& s)
 }  // namespace
 
 extern "C" {
-
-#if MDS_TILE_TRACE
-MDS_API int mds_set_tile_trace(void* p)
-{
-    g_tile_trace = static_cast<unsigned long long*>(p);
-    return 0;
-}
-#endif
 
 const char* mds_status_string(int status)
 {
@@ -307,7 +323,7 @@ int mds_resolve_tiling(int64_t n, int32_t d, int32_t y_dtype, int32_t tile_rows,
     const int st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t);
     if (st) return st;
     *rows_out = t.br;
-    *waves_out = t.waves;
+    *waves_out = packed_waves(t);
     return MDS_OK;
 }
 
@@ -349,6 +365,21 @@ int mds_check_symmetric(const void* y, int32_t y_dtype, int64_t ldy, int64_t n,
         return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned pointer");
     hipError_t e = launch_check_symmetric(y, y_dtype, ldy, n, mismatches_dev, stream);
     if (e != hipSuccess) return hip_fail(e, "symmetry check launch");
+    return MDS_OK;
+}
+
+int mds_require_symmetric(const void* y, int32_t y_dtype, int64_t ldy, int64_t n,
+                          int64_t* mismatches_dev, hipStream_t stream)
+{
+    const int st = mds_check_symmetric(y, y_dtype, ldy, n, mismatches_dev, stream);
+    if (st) return st;
+    int64_t bad = 0;
+    hipError_t e = hipMemcpyAsync(&bad, mismatches_dev, sizeof(bad), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "symmetry count read-back");
+    if (bad)
+        return fail(MDS_ERR_NOT_SYMMETRIC, "%lld pairs i > j with y[i][j] != y[j][i] (Y or its "
+                    "missing-pair mask is not symmetric)", (long long)bad);
     return MDS_OK;
 }
 
@@ -833,7 +864,7 @@ static int batch_layout(const mds_problem_desc* descs, int32_t count, int32_t y_
     if (!descs) return fail(MDS_ERR_INVALID_ARGUMENT, "descs is NULL");
     if (y_dtype != MDS_F64 && y_dtype != MDS_F32)
         return fail(MDS_ERR_UNSUPPORTED, "y_dtype=%d unsupported", y_dtype);
-    const int waves = tile_waves ? tile_waves : 4;
+    const int waves = tile_waves ? tile_waves : 4;  // packed: column and row waves
     size_t off = 0;
     L->table = off;
     off = align_up(off + sizeof(BatchProblem) * (size_t)count, 256);
@@ -922,7 +953,8 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
     if (workspace_bytes < L.total)
         return fail(MDS_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu B < %zu B needed",
                     workspace_bytes, L.total);
-    const int waves = tile_waves ? tile_waves : 4;
+    // waves per work-group (column x row waves, common to the batch)
+    const int waves = L.tilings[0].waves;
 
     // host image of [table | cursor]; copied in one transfer
     std::vector<unsigned char> img(L.cursor + sizeof(unsigned long long), 0);
@@ -936,6 +968,7 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
         BatchProblem P = {};
         P.sweep = sweep_args(t, workspace_layout(t, q.d), base + L.ws[k], q.n, q.x, q.ldx, q.y,
                              q.ldy, q.sigma, trunc);
+        P.sweep.trace = nullptr;  // the per-wave timeline is for single-problem sweeps
         P.d = q.d;
         P.tile_base = tiles;
         P.ntiles = t.ntiles;
@@ -1040,6 +1073,13 @@ int mds_batch_leapfrog(const mds_batch_plan* plan, int32_t n_steps, int32_t cach
         const bool last = (s == n_steps);
         if ((st = evaluate(last ? 0.5 : 1.0, 1, last ? 0 : 1))) return st;
     }
+    return MDS_OK;
+}
+
+int mds_set_tile_trace(void* trace)
+{
+    if (!aligned(trace, 8)) return fail(MDS_ERR_INVALID_ARGUMENT, "trace misaligned");
+    g_tile_trace = static_cast<unsigned long long*>(trace);
     return MDS_OK;
 }
 

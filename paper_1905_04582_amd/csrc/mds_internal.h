@@ -13,16 +13,22 @@ constexpr int kWave = 64;     // CDNA wavefront width
 // Tile geometry of the lower-triangle pair sweep.
 //
 // Rows (index i) are cut into blocks of `br`, columns (index j) into blocks
-// of `cw` = 64 * waves; one work-group owns one (row block, column block)
-// tile and each of its waves owns 64 consecutive columns.  A tile exists
-// when it can hold a pair with j < i.  With one of br and cw dividing the
-// other, row block r holds a closed-form number of tiles, so a linear tile
-// index maps back to (r, c) by a short binary search on the prefix count.
+// of `cw` = 64 * wc; one work-group owns one (row block, column block) tile.
+// Its wc * wr waves form a grid: wave (u, v) owns the 64 consecutive columns
+// u*64 .. u*64+63 of the tile and the v-th of wr equal groups of its rows, so
+// wr > 1 shortens every wave's walk down the rows (and the time the last
+// work-groups of a launch keep the machine partly idle) without changing the
+// tile.  A tile exists when it can hold a pair with j < i.  With one of br
+// and cw dividing the other, row block r holds a closed-form number of tiles,
+// so a linear tile index maps back to (r, c) by a short binary search on the
+// prefix count.
 struct Tiling {
     int64_t n;
     int br;     // rows per tile
-    int cw;     // columns per tile
-    int waves;  // cw / 64
+    int cw;     // columns per tile (64 * wc)
+    int wc;     // waves across the tile's columns
+    int wr;     // waves down the tile's rows (each walks br / wr rows)
+    int waves;  // wc * wr: waves per work-group
     int nrb;    // number of row blocks
     int64_t ntiles;
     int elem;   // bytes of one Y element (8 in FP64, 4 in FP32): the staged rows' type
@@ -53,14 +59,69 @@ __host__ __device__ inline int first_row_block_of_column(int c, int br, int cw)
     return c * (cw / br);
 }
 
-inline Tiling make_tiling(int64_t n, int br, int waves, int elem)
+// (row block, column block) of linear tile index `tile` (row blocks in
+// order, then column blocks in order within a row block)
+__host__ __device__ inline void tile_coords(int64_t tile, int nrb, int br, int cw, int* r, int* c)
+{
+    int lo = 0, hi = nrb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tiles_before(mid, br, cw) <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    *r = lo;
+    *c = (int)(tile - tiles_before(lo, br, cw));
+}
+
+// rows staged per reduction step of the sweep (keeps the per-wave staging
+// buffer at <= 16 values per lane)
+__host__ __device__ constexpr int sweep_stage_rows(int d) { return d <= 2 ? 8 : (d <= 4 ? 4 : 2); }
+
+// The rows one wave of a tile walks.  The wave's row group is
+// [rw0, rw1) (empty when the group lies past N); rows i <= jw0 hold no pair
+// j < i for any of its lanes, so the walk starts at ib0, the last multiple
+// of `rb` rows from rw0 at or below max(rw0, jw0 + 1).  The wave visits rows
+// ib0 .. rw1-1 in order, and only when ib0 < rw1 (`active`); every row it
+// reads -- its Y prefetch included -- lies in [ib0, rw1), inside both the
+// tile and the matrix.
+struct WaveRows {
+    int64_t row0, row1;  // the tile's rows [row0, row1), row1 <= n
+    int64_t rw0, rw1;    // the wave's row group, rw1 <= row1
+    int64_t jw0;         // the wave's first column
+    int64_t ib0;         // first row visited
+    bool active;         // ib0 < rw1
+};
+
+__host__ __device__ inline WaveRows wave_rows(int64_t n, int br, int cw, int wc, int wr, int r,
+                                              int c, int wave, int rb)
+{
+    WaveRows w;
+    const int u = wave % wc, v = wave / wc;
+    const int rpw = br / wr;
+    w.row0 = (int64_t)r * br;
+    w.row1 = w.row0 + br < n ? w.row0 + br : n;
+    w.rw0 = w.row0 + (int64_t)v * rpw;
+    const int64_t e = w.rw0 + rpw;
+    w.rw1 = e < w.row1 ? e : w.row1;
+    w.jw0 = (int64_t)c * cw + (int64_t)u * 64;
+    const int64_t istart = w.rw0 > w.jw0 + 1 ? w.rw0 : w.jw0 + 1;
+    w.ib0 = w.rw0 + ((istart - w.rw0) / rb) * rb;
+    w.active = w.ib0 < w.rw1;
+    return w;
+}
+
+inline Tiling make_tiling(int64_t n, int br, int wc, int wr, int elem)
 {
     Tiling t;
     t.elem = elem;
     t.n = n;
     t.br = br;
-    t.waves = waves;
-    t.cw = kWave * waves;
+    t.wc = wc;
+    t.wr = wr;
+    t.waves = wc * wr;
+    t.cw = kWave * wc;
     t.nrb = (int)((n + br - 1) / br);
     t.ntiles = tiles_before(t.nrb, br, t.cw);
     return t;
@@ -97,31 +158,25 @@ inline WorkspaceLayout workspace_layout(const Tiling& t, int d)
     return w;
 }
 
-// rows staged per reduction step of the sweep (keeps the per-wave staging
-// buffer at <= 16 doubles per lane)
-#ifndef MDS_STAGE_ROWS_SMALL_D
-#define MDS_STAGE_ROWS_SMALL_D 8
-#endif
-#ifndef MDS_STAGE_ROWS_LARGE_D
-#define MDS_STAGE_ROWS_LARGE_D 2
-#endif
-__host__ __device__ constexpr int sweep_stage_rows(int d)
+// staged rows are padded by 32 bytes so that the rows a lane group reads in
+// the transposed reduction start in different LDS banks
+constexpr int kStagePadBytes = 32;
+
+// LDS bytes used by one sweep work-group: tile row sums (one copy per
+// column wave), per-wave scalars and the per-wave row staging buffer (rows of
+// Y's element type, padded by kStagePadBytes; it also carries a wave's
+// column sums when wr > 1, so it holds at least 64 * D doubles)
+__host__ __device__ inline size_t sweep_stage_bytes(int d, int elem)
 {
-    return d <= 2 ? MDS_STAGE_ROWS_SMALL_D : (d <= 4 ? 4 : MDS_STAGE_ROWS_LARGE_D);
+    const size_t rows = (size_t)sweep_stage_rows(d) * ((size_t)kWave * d * elem + kStagePadBytes);
+    const size_t cols = (size_t)kWave * d * sizeof(double);
+    return rows > cols ? rows : cols;
 }
 
-#ifndef MDS_STAGE_PAD_BYTES
-#define MDS_STAGE_PAD_BYTES 32
-#endif
-constexpr int kStagePadBytes = MDS_STAGE_PAD_BYTES;
-
-// LDS bytes used by one sweep work-group: tile row sums, per-wave scalars
-// and the per-wave row staging buffer (rows of Y's element type, padded by
-// kStagePadBytes)
 inline size_t sweep_lds_bytes(const Tiling& t, int d)
 {
-    return (size_t)t.waves * t.br * d * sizeof(double) + (size_t)t.waves * 4 * sizeof(double) +
-           (size_t)t.waves * sweep_stage_rows(d) * ((size_t)kWave * d * t.elem + kStagePadBytes);
+    return (size_t)t.wc * t.br * d * sizeof(double) + (size_t)t.waves * 4 * sizeof(double) +
+           (size_t)t.waves * sweep_stage_bytes(d, t.elem);
 }
 
 // partial sums of the lpd finalize (its workspace holds this many doubles)
@@ -135,14 +190,15 @@ struct SweepArgs {
     int64_t ldy;
     const double* sigma;
     int br, cw, nrb;
+    int wc, wr;     // waves across columns and down rows of a tile
     double* rowpart;
     double* colpart;
     double* tscal;
     uint32_t* tcount;
     int truncated;  // 0: the model without the truncation terms (ln Phi = m = 0)
-#if MDS_TILE_TRACE
-    unsigned long long* trace;  // diagnostic build only: per-wave start/end clocks
-#endif
+    // diagnostics (NULL in normal use): per wave of every tile, its start and
+    // end clock (100 MHz) and hardware slot id
+    unsigned long long* trace;
 };
 
 // What the finalize kernel does with the summed gradient of one element.

@@ -75,14 +75,8 @@ __device__ void block_sum3(double& a, double& b, double& c)
 // of kFinChunks adds list items w, w + kFinChunks, ... (64 consecutive
 // elements per wave: coalesced reads), and wave 0 adds the kFinChunks chunk
 // sums in chunk order.  Every order is fixed, so the result is reproducible.
-#ifndef MDS_FIN_CHUNKS
-#define MDS_FIN_CHUNKS 8
-#endif
-#ifndef MDS_FIN_UNROLL
-#define MDS_FIN_UNROLL 8
-#endif
-constexpr int kFinChunks = MDS_FIN_CHUNKS;
-constexpr int kFinUnroll = MDS_FIN_UNROLL;  // partial loads in flight per lane
+constexpr int kFinChunks = 8;
+constexpr int kFinUnroll = 8;  // partial loads in flight per lane
 
 // The scalar part: L, dL/dsigma and dL/d(ln sigma) from the per-tile sums,
 // by one work-group of kWave * kFinChunks threads in a fixed order: thread t

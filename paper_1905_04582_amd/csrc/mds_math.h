@@ -54,28 +54,15 @@ __device__ __forceinline__ double fma_sc(double acc, double x, double c)
 // immediates, which a 64-bit VALU operand cannot encode.
 typedef const __attribute__((address_space(4))) double* const_f64_ptr;
 
-#ifndef MDS_COEF_SMOV
-#define MDS_COEF_SMOV 0
-#endif
-
 template <int N>
 __device__ __forceinline__ double horner_tab(const double (&tab)[N], double x)
 {
-#if MDS_COEF_SMOV
-    // coefficients folded by the compiler and materialised in scalar
-    // registers (scalar moves issue beside the vector FMAs)
-    double acc = fma_sc(tab[N - 1], x, tab[N - 2]);
-#pragma unroll
-    for (int k = N - 3; k >= 0; --k) acc = fma_sc(acc, x, tab[k]);
-    return acc;
-#else
     const_f64_ptr c = (const_f64_ptr)tab;
     asm volatile("" : "+s"(c));
     double acc = fma_sc(c[N - 1], x, c[N - 2]);
 #pragma unroll
     for (int k = N - 3; k >= 0; --k) acc = fma_sc(acc, x, c[k]);
     return acc;
-#endif
 }
 
 // Horner's rule for two arguments at once: each coefficient is loaded once
@@ -110,18 +97,14 @@ __device__ __forceinline__ double rcp_f64(double d)
 }
 
 // 1/sqrt(x) for finite x >= DBL_MIN: hardware estimate (relative error
-// below 2^-24 on gfx950) + MDS_RSQ_NEWTON Newton steps (each roughly squares
-// the error: one step leaves it below 2^-47, two reach the rounding)
-#ifndef MDS_RSQ_NEWTON
-#define MDS_RSQ_NEWTON 2
-#endif
+// below 2^-24 on gfx950) + 2 Newton steps (each roughly squares the error:
+// one step leaves it below 2^-47, two reach the rounding)
 __device__ __forceinline__ double rsqrt_f64(double x)
 {
     double r = __builtin_amdgcn_rsq(x);
     const double hx = 0.5 * x;
-#pragma unroll
-    for (int k = 0; k < MDS_RSQ_NEWTON; ++k) r = fma(r, fma(-hx, r * r, 0.5), r);
-    return r;
+    r = fma(r, fma(-hx, r * r, 0.5), r);
+    return fma(r, fma(-hx, r * r, 0.5), r);
 }
 
 // exp(-t^2/2) for t >= 0; 0 once the value leaves the FP64 range

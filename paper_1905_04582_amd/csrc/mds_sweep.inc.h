@@ -3,23 +3,25 @@
 // (Eq. 2), of dL/dsigma, and of every gradient row (Eq. 9).
 //
 // Work decomposition (gfx950, 64-wide waves):
-//   * a work-group owns a tile of `br` rows x `cw` = 64*waves columns; wave w
-//     owns columns c*cw + 64w .. +63, one column j per lane;
-//   * the wave walks the tile's rows i (wave-uniform, so x_i comes through
+//   * a work-group owns a tile of `br` rows x `cw` = 64*wc columns and runs
+//     wc x wr waves: wave (u, v) owns columns c*cw + 64u .. +63, one column j
+//     per lane, and the v-th of wr equal groups of the tile's rows;
+//   * the wave walks its rows i in order (wave-uniform, so x_i comes through
 //     scalar loads) and reads Y[i][j0 .. j0+63]: 64 consecutive elements of
 //     one row, a fully coalesced load of the lower triangle;
 //   * each pair's gradient term goes to row j (+) and row i (-) -- each pair
 //     is evaluated once.  The column side stays in the lane's registers for
-//     the whole tile.  The row side is a sum across the 64 lanes: the lanes
+//     the wave's rows.  The row side is a sum across the 64 lanes: the lanes
 //     stage their terms of a few rows in LDS, then every (row, dimension)
 //     output is summed by a small group of lanes reading the staged values
 //     and finished by log2(group) exchanges;
 //   * a wavefront whose pairs in a row all have delta/sigma beyond a skip
 //     point branches over the special functions as a whole (no divergence);
-//   * the waves' row sums meet in LDS and are added in wave order; column,
-//     row and scalar partials of the tile go to the workspace, and the
-//     finalize kernel adds them in a fixed order.  No atomics: the result is
-//     bitwise reproducible.
+//   * the column sums of the wr waves of a column group, and the row sums of
+//     the wc waves of a row group, meet in LDS and are added in wave order;
+//     column, row and scalar partials of the tile go to the workspace, and
+//     the finalize kernel adds them in a fixed order.  No atomics: the result
+//     is bitwise reproducible.
 // The paper's GPU design (one thread per pair in 16x16 work-groups for the
 // likelihood, 128 threads per row for the gradient, every pair twice) is
 // replaced by this single fused triangle pass.
@@ -29,25 +31,6 @@
 
 #include "mds_internal.h"
 #include "mds_math.h"
-
-// Build-time variants of the sweep (the defaults are the measured best):
-// rows per step, reduction form, shared special-function coefficient loads, rows of Y prefetched ahead, and a
-// diagnostic build that records each wave's start and end clock.
-#ifndef MDS_ROW_UNROLL
-#define MDS_ROW_UNROLL 2
-#endif
-#ifndef MDS_REDUCE_PER_OUTPUT
-#define MDS_REDUCE_PER_OUTPUT 1
-#endif
-#ifndef MDS_SHARED_COEF
-#define MDS_SHARED_COEF 1
-#endif
-#ifndef MDS_PREFETCH_ROWS
-#define MDS_PREFETCH_ROWS 2
-#endif
-#ifndef MDS_TILE_TRACE
-#define MDS_TILE_TRACE 0
-#endif
 
 namespace mds {
 
@@ -129,12 +112,7 @@ template <>
 __device__ __forceinline__ void trunc_terms2<double>(double t1, double t2, double& l1,
                                                      double& m1, double& l2, double& m2)
 {
-#if MDS_SHARED_COEF
     trunc_terms2_f64(t1, t2, l1, m1, l2, m2);
-#else
-    trunc_terms_f64(t1, l1, m1);
-    trunc_terms_f64(t2, l2, m2);
-#endif
 }
 
 template <typename T>
@@ -178,9 +156,6 @@ __device__ __forceinline__ float skip_t<float>()
     return 6.5f;
 }
 
-// One tile of one problem, processed by the whole work-group; `lds` is the
-// work-group's dynamic LDS (sweep_lds_bytes).  Ends with a barrier, so the
-// caller may reuse the LDS for the next tile straight away.
 // lanes per output in the row reduction: the largest power of two g with
 // outputs * g <= 64
 __host__ __device__ constexpr int reduce_group(int outputs)
@@ -190,6 +165,9 @@ __host__ __device__ constexpr int reduce_group(int outputs)
     return g;
 }
 
+// One tile of one problem, processed by the whole work-group; `lds` is the
+// work-group's dynamic LDS (sweep_lds_bytes).  Ends with a barrier, so the
+// caller may reuse the LDS for the next tile straight away.
 template <typename T, int D, bool GRAD>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t tile, double* lds)
 {
@@ -197,41 +175,29 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int waves = blockDim.x / kWave;
-    const int br = a.br, cw = a.cw;
+    const int br = a.br, cw = a.cw, wc = a.wc;
+    const int wu = w % wc;  // this wave's column group
 
-    // tile -> (row block r, column block c)
-    int lo = 0, hi = a.nrb - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tiles_before(mid, br, cw) <= tile)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const int r = lo;
-    const int c = (int)(tile - tiles_before(r, br, cw));
-    const int64_t row0 = (int64_t)r * br;
-    const int64_t row1 = min(a.n, row0 + br);
-    const int64_t jw0 = (int64_t)c * cw + (int64_t)w * kWave;
-    const int64_t j = jw0 + lane;
+    int r, c;
+    tile_coords(tile, a.nrb, br, cw, &r, &c);
+    const WaveRows wv = wave_rows(a.n, br, cw, wc, a.wr, r, c, w, RB);
+    const int64_t row0 = wv.row0, row1 = wv.row1;
+    const int64_t j = wv.jw0 + lane;
     const bool colok = j < a.n;
 
-    // LDS: [waves][br][D] tile row sums | [waves][4] scalars | [waves][RB][64][D] staging
-    double* lrows = lds + (size_t)w * br * D;
-    double* lscal = lds + (size_t)waves * br * D;
-    // staged rows are padded by 32 bytes so that the RB rows a lane group
-    // reads in the transposed reduction start in different LDS banks
+    // LDS: [wc][br][D] tile row sums | [waves][4] scalars | [waves] staging
+    // (rows of RB x (64 D + pad) elements, or a wave's 64 x D column sums)
+    double* lrows = lds + (size_t)wu * br * D;
+    double* lscal = lds + (size_t)wc * br * D;
     constexpr int SROW = kWave * D + kStagePadBytes / (int)sizeof(T);
-    T* stage = reinterpret_cast<T*>(lscal + (size_t)waves * 4) + (size_t)w * RB * SROW;
+    const size_t stage_bytes = sweep_stage_bytes(D, (int)sizeof(T));
+    char* stage_base = reinterpret_cast<char*>(lscal + (size_t)waves * 4) + (size_t)w * stage_bytes;
+    T* stage = reinterpret_cast<T*>(stage_base);
+    // this wave's rows of the tile's row sums start at zero (rows it skips
+    // hold no pair of its columns)
     if (GRAD)
-        for (int k = lane; k < br * D; k += kWave) lrows[k] = 0.0;
-
-    double xj[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) xj[d] = colok ? a.x[j * a.ldx + d] : 0.0;
-
-    const PairConsts<T> pc = pair_consts<T>(*a.sigma);
-    const T* __restrict__ Y = static_cast<const T*>(a.y);
+        for (int k = lane; k < (int)(wv.rw1 - wv.rw0) * D; k += kWave)
+            lrows[(wv.rw0 - row0) * D + k] = 0.0;
 
     double gj[D];
 #pragma unroll
@@ -239,166 +205,108 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     double acc_r = 0.0, acc_s = 0.0;
     int cnt = 0;
 
-    // rows i <= jw0 hold no pair (j < i) for any lane of this wave
-    const int64_t istart = max(row0, jw0 + 1);
-    const int64_t ib0 = row0 + ((istart - row0) / RB) * RB;
-    // Y is prefetched one iteration (PF rows) ahead, so each row's load has
-    // an iteration of arithmetic to arrive.  The load itself is unconditional (row clamped
-    // into the tile, column into the matrix; lanes outside the triangle
-    // discard the value through `ok`), so no branch splits the wave and the
-    // wait before a row's first use leaves the two newer loads in flight.
-    // Rows are loaded strictly in order, so the row's address is a uniform
-    // pointer that advances by ldy per load and stops at the tile's last row;
-    // each lane adds its 32-bit column offset.  Row and column indices fit
-    // 32 bits (N <= 2^30).
-    const uint32_t jc = colok ? (uint32_t)j : 0u;
-    const int j32 = (int)j;
-    const int last_row = (int)(row1 - 1);
-    const T* yrow = Y + ib0 * a.ldy;
-    int ynext = (int)ib0;
-    struct RowIn {
-        T y;
-    };
-    auto load_y = [&]() -> RowIn {
-        RowIn r;
-        r.y = yrow[jc];
-        if (ynext < last_row) yrow += a.ldy;
-        ++ynext;
-        return r;
-    };
-    // x_i is uniform across the wave and comes through scalar loads (X is
-    // read-only during the sweep, so the constant address space is valid);
-    // rows are visited in order, so its address advances by ldx per row
-    const double* xrow = a.x + ib0 * a.ldx;
-    // rows per iteration (UR) and rows prefetched ahead (PF); a batch of RB
-    // staged rows holds whole iterations
-    constexpr int UR = (MDS_ROW_UNROLL >= 4 && RB % 4 == 0) ? 4 : (MDS_ROW_UNROLL >= 2 ? 2 : 1);
-    constexpr int PF = (UR < 2 ? 2 : UR) > MDS_PREFETCH_ROWS ? (UR < 2 ? 2 : UR) : MDS_PREFETCH_ROWS;
-    RowIn pf[PF];
+    if (wv.active) {
+        double xj[D];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) pf[k] = load_y();
-    for (int64_t ib = ib0; ib < row1; ib += RB) {
-        T gjb[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) gjb[d] = T(0);
-        T br_r = T(0), br_s = T(0);
-        const int nq = (int)min((int64_t)RB, row1 - ib);
+        for (int d = 0; d < D; ++d) xj[d] = colok ? a.x[j * a.ldx + d] : 0.0;
+        const PairConsts<T> pc = pair_consts<T>(*a.sigma);
+        const T* __restrict__ Y = static_cast<const T*>(a.y);
 
-        // geometry of one pair row (row ib + q, this lane's column)
-        auto geom = [&](const int q, const RowIn& rin, PairGeom<T, D>& g) {
-            const int i = (int)(ib + q);
-            const T yv = rin.y;
-            const const_f64_ptr xi = (const_f64_ptr)xrow;
-            xrow += a.ldx;
-            g.ok = colok && (j32 < i) && !isnan(yv);
-            T s2 = T(0);
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                g.dl[d] = (T)(xi[d] - xj[d]);
-                s2 = fma(g.dl[d], g.dl[d], s2);
-            }
-            // delta and 1/delta from one reciprocal square root.  A coincident
-            // pair (s2 below the normal range) has no direction: 1/delta is
-            // taken as 0, and delta = s2 * rsqrt(DBL_MIN) is 0 for s2 = 0
-            // (below 1.5e-154 otherwise)
-            const T rs = rsqrt_t(fmax(s2, min_normal<T>()));
-            g.delta = s2 * rs;
-            g.rinv = (s2 >= min_normal<T>()) ? rs : T(0);
-            g.t = g.delta * pc.inv_sigma;
-            // a pair outside the sums gets y = delta: its residual is 0, and
-            // with ln Phi = m = 0 (set by the caller) all its terms vanish
-            g.res = g.ok ? yv - g.delta : T(0);
+        // Y is prefetched two rows ahead, so each row's load has an iteration
+        // of arithmetic to arrive.  The load is unconditional (lanes outside
+        // the triangle discard the value through `ok`), so no branch splits
+        // the wave and the wait before a row's first use leaves the two newer
+        // loads in flight.  Rows are loaded strictly in order from ib0, and
+        // the row pointer stops at the wave's last row rw1-1: every address
+        // lies in rows [ib0, rw1) of the tile and in columns [0, n).  Row and
+        // column indices fit 32 bits (N <= 2^30).
+        const uint32_t jc = colok ? (uint32_t)j : 0u;
+        const int j32 = (int)j;
+        const int last_row = (int)(wv.rw1 - 1);
+        const T* yrow = Y + wv.ib0 * a.ldy;
+        int ynext = (int)wv.ib0;
+        auto load_y = [&]() -> T {
+            const T v = yrow[jc];
+            if (ynext < last_row) yrow += a.ldy;
+            ++ynext;
+            return v;
         };
-        // the pair's terms given ln Phi(t) and phi(t)/Phi(t) (both 0 for a
-        // pair outside the sums)
-        auto accum = [&](const int q, const PairGeom<T, D>& g, const T lnphi, const T mills) {
-            const T res2 = g.res * g.res;
-            br_r += fma(res2, pc.half_inv_s2, lnphi);
-            if (GRAD) {
-                // w = (delta - y)/sigma^2 + m/sigma; the pair's term is w (x_i - x_j)/delta
-                const T wv = fma(mills, pc.inv_sigma, -g.res * pc.inv_s2);
-                const T coef = wv * g.rinv;
-                T* st = stage + (size_t)q * SROW + (size_t)lane * D;
+        // x_i is uniform across the wave and comes through scalar loads (X is
+        // read-only during the sweep, so the constant address space is
+        // valid); rows are visited in order, so its address advances by ldx
+        const double* xrow = a.x + wv.ib0 * a.ldx;
+        T pf0 = load_y(), pf1 = load_y();
+        for (int64_t ib = wv.ib0; ib < wv.rw1; ib += RB) {
+            T gjb[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) gjb[d] = T(0);
+            T br_r = T(0), br_s = T(0);
+            const int nq = (int)min((int64_t)RB, wv.rw1 - ib);
+
+            // geometry of one pair row (row ib + q, this lane's column)
+            auto geom = [&](const int q, const T yv, PairGeom<T, D>& g) {
+                const int i = (int)(ib + q);
+                const const_f64_ptr xi = (const_f64_ptr)xrow;
+                xrow += a.ldx;
+                g.ok = colok && (j32 < i) && !isnan(yv);
+                T s2 = T(0);
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    const T cd = coef * g.dl[d];
-                    st[d] = -cd;
-                    gjb[d] += cd;
+                    g.dl[d] = (T)(xi[d] - xj[d]);
+                    s2 = fma(g.dl[d], g.dl[d], s2);
                 }
-                br_s += fma(res2, pc.inv_s3, g.delta * pc.inv_s2 * mills);
-            }
-        };
-        // observed pairs of a row in this wave (a wave-uniform count)
-        auto count_ok = [&](const PairGeom<T, D>& g) {
-            cnt += (int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(g.ok));
-        };
-        // when no observed pair of the row(s) in this wave has t below the
-        // skip point, the wave takes ln Phi = m = 0 and skips the special
-        // functions (a wave-uniform branch; lanes never diverge)
-        auto needs_tail = [&](const PairGeom<T, D>& g) { return g.ok && g.t < skip_t<T>(); };
-        // one row at a time (loop tails)
-        auto one_row = [&](const int q) {
-            const RowIn ya = pf[0];
+                // delta and 1/delta from one reciprocal square root.  A
+                // coincident pair (s2 below the normal range) has no
+                // direction: 1/delta is taken as 0, and delta = s2 *
+                // rsqrt(min normal) is 0 for s2 = 0 (tiny otherwise)
+                const T rs = rsqrt_t(fmax(s2, min_normal<T>()));
+                g.delta = s2 * rs;
+                g.rinv = (s2 >= min_normal<T>()) ? rs : T(0);
+                g.t = g.delta * pc.inv_sigma;
+                // a pair outside the sums gets y = delta: its residual is 0,
+                // and with ln Phi = m = 0 (set by the caller) all its terms
+                // vanish
+                g.res = g.ok ? yv - g.delta : T(0);
+            };
+            // the pair's terms given ln Phi(t) and phi(t)/Phi(t) (both 0 for
+            // a pair outside the sums)
+            auto accum = [&](const int q, const PairGeom<T, D>& g, const T lnphi, const T mills) {
+                const T res2 = g.res * g.res;
+                br_r += fma(res2, pc.half_inv_s2, lnphi);
+                if (GRAD) {
+                    // w = (delta - y)/sigma^2 + m/sigma; the pair's term is
+                    // w (x_i - x_j)/delta
+                    const T wv_ = fma(mills, pc.inv_sigma, -g.res * pc.inv_s2);
+                    const T coef = wv_ * g.rinv;
+                    T* st = stage + (size_t)q * SROW + (size_t)lane * D;
 #pragma unroll
-            for (int k = 0; k + 1 < PF; ++k) pf[k] = pf[k + 1];
-            pf[PF - 1] = load_y();
-            PairGeom<T, D> ga;
-            geom(q, ya, ga);
-            count_ok(ga);
-            T la = T(0), ma = T(0);
-            if (a.truncated && __builtin_amdgcn_ballot_w64(needs_tail(ga))) {
-                trunc_terms<T>(ga.t, la, ma);
-                la = ga.ok ? la : T(0);
-                ma = ga.ok ? ma : T(0);
-            }
-            accum(q, ga, la, ma);
-        };
-        int q = 0;
-        if constexpr (UR == 4) {
-            // four rows per iteration: two pairs of rows share the special
-            // functions' coefficient loads, four dependency chains interleave
+                    for (int d = 0; d < D; ++d) {
+                        const T cd = coef * g.dl[d];
+                        st[d] = -cd;
+                        gjb[d] += cd;
+                    }
+                    br_s += fma(res2, pc.inv_s3, g.delta * pc.inv_s2 * mills);
+                }
+            };
+            // observed pairs of a row in this wave (a wave-uniform count)
+            auto count_ok = [&](const PairGeom<T, D>& g) {
+                cnt += (int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(g.ok));
+            };
+            // when no observed pair of the rows in this wave has t below the
+            // skip point, the wave takes ln Phi = m = 0 and skips the special
+            // functions (a wave-uniform branch; lanes never diverge)
+            auto needs_tail = [&](const PairGeom<T, D>& g) { return g.ok && g.t < skip_t<T>(); };
+            // two rows per step: their dependency chains interleave and they
+            // share the special functions' coefficient loads
+            int q = 0;
 #pragma unroll 1
-            for (; q + 3 < nq; q += 4) {
-                const RowIn ya = pf[0], yb = pf[1], yc = pf[2], yd = pf[3];
-#pragma unroll
-                for (int k = 0; k + 4 < PF; ++k) pf[k] = pf[k + 4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) pf[PF - 4 + k] = load_y();
-                PairGeom<T, D> ga, gb, gc, gd;
+            for (; q + 1 < nq; q += 2) {
+                const T ya = pf0, yb = pf1;
+                pf0 = load_y();
+                pf1 = load_y();
+                PairGeom<T, D> ga, gb;
                 geom(q, ya, ga);
                 geom(q + 1, yb, gb);
-                geom(q + 2, yc, gc);
-                geom(q + 3, yd, gd);
-                count_ok(ga);
-                count_ok(gb);
-                count_ok(gc);
-                count_ok(gd);
-                T la = T(0), ma = T(0), lb = T(0), mb = T(0);
-                T lc = T(0), mc = T(0), ld = T(0), md = T(0);
-                if (a.truncated && __builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb) ||
-                                                needs_tail(gc) || needs_tail(gd))) {
-                    trunc_terms2<T>(ga.t, gb.t, la, ma, lb, mb);
-                    trunc_terms2<T>(gc.t, gd.t, lc, mc, ld, md);
-                    la = ga.ok ? la : T(0);
-                    ma = ga.ok ? ma : T(0);
-                    lb = gb.ok ? lb : T(0);
-                    mb = gb.ok ? mb : T(0);
-                    lc = gc.ok ? lc : T(0);
-                    mc = gc.ok ? mc : T(0);
-                    ld = gd.ok ? ld : T(0);
-                    md = gd.ok ? md : T(0);
-                }
-                accum(q, ga, la, ma);
-                accum(q + 1, gb, lb, mb);
-                accum(q + 2, gc, lc, mc);
-                accum(q + 3, gd, ld, md);
-            }
-        } else if constexpr (UR == 2) {
-            // two rows per step: independent dependency chains interleave
-            auto two_rows = [&](const int qq, const RowIn& ya, const RowIn& yb) {
-                PairGeom<T, D> ga, gb;
-                geom(qq, ya, ga);
-                geom(qq + 1, yb, gb);
                 count_ok(ga);
                 count_ok(gb);
                 T la = T(0), ma = T(0), lb = T(0), mb = T(0);
@@ -409,95 +317,64 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                     lb = gb.ok ? lb : T(0);
                     mb = gb.ok ? mb : T(0);
                 }
-                accum(qq, ga, la, ma);
-                accum(qq + 1, gb, lb, mb);
-            };
-            if constexpr (PF > 2 && RB % PF == 0) {
-                // PF/2 steps per trip, unrolled, so that each step reloads
-                // the two ring slots it consumed: the ring needs no register
-                // moves (a move of a register with a load in flight would wait
-                // for that load)
-#pragma unroll 1
-                for (; q + PF - 1 < nq; q += PF) {
-#pragma unroll
-                    for (int k = 0; k < PF; k += 2) {
-                        const RowIn ya = pf[k], yb = pf[k + 1];
-                        pf[k] = load_y();
-                        pf[k + 1] = load_y();
-                        two_rows(q + k, ya, yb);
-                    }
+                accum(q, ga, la, ma);
+                accum(q + 1, gb, lb, mb);
+            }
+            if (q < nq) {
+                // the odd last row of the wave's rows
+                const T ya = pf0;
+                pf0 = pf1;
+                pf1 = load_y();
+                PairGeom<T, D> ga;
+                geom(q, ya, ga);
+                count_ok(ga);
+                T la = T(0), ma = T(0);
+                if (a.truncated && __builtin_amdgcn_ballot_w64(needs_tail(ga))) {
+                    trunc_terms<T>(ga.t, la, ma);
+                    la = ga.ok ? la : T(0);
+                    ma = ga.ok ? ma : T(0);
                 }
+                accum(q, ga, la, ma);
             }
-#pragma unroll 1
-            for (; q + 1 < nq; q += 2) {
-                const RowIn ya = pf[0], yb = pf[1];
+            acc_r += (double)br_r;
+            if (GRAD) {
+                acc_s += (double)br_s;
 #pragma unroll
-                for (int k = 0; k + 2 < PF; ++k) pf[k] = pf[k + 2];
-                pf[PF - 2] = load_y();
-                pf[PF - 1] = load_y();
-                two_rows(q, ya, yb);
-            }
-        }
-#pragma unroll 1
-        for (; q < nq; ++q) one_row(q);
-        acc_r += (double)br_r;
-        if (GRAD) {
-            acc_s += (double)br_s;
+                for (int d = 0; d < D; ++d) gj[d] += (double)gjb[d];
+                // transposed reduction of the staged rows: each (row,
+                // dimension) output of the batch gets RG lanes; lane h of its
+                // group adds the staged values of lanes h, h+RG, ..., then the
+                // group combines by log2(RG) exchanges
+                constexpr int NO = RB * D;
+                constexpr int RG = reduce_group(NO);
+                const int o = lane / RG, h = lane % RG;
+                const int orow = o / D, odim = o % D;
+                const bool live = o < NO && orow < nq;
+                T sum = T(0);
+                if (live) {
+                    const T* src = stage + (size_t)orow * SROW + (size_t)h * D + odim;
 #pragma unroll
-            for (int d = 0; d < D; ++d) gj[d] += (double)gjb[d];
-#if MDS_REDUCE_PER_OUTPUT
-            // transposed reduction of the staged rows: each (row, dimension)
-            // output of the batch gets RG lanes; lane h of its group adds the
-            // staged values of lanes h, h+RG, ..., then the group combines by
-            // log2(RG) exchanges
-            constexpr int NO = RB * D;
-            constexpr int RG = reduce_group(NO);
-            const int o = lane / RG, h = lane % RG;
-            const int orow = o / D, odim = o % D;
-            const bool live = o < NO && orow < nq;
-            T sum = T(0);
-            if (live) {
-                const T* src = stage + (size_t)orow * SROW + (size_t)h * D + odim;
-#pragma unroll
-                for (int k = 0; k < kWave / RG; ++k) sum += src[(size_t)k * RG * D];
-            }
-#pragma unroll
-            for (int m = RG / 2; m >= 1; m >>= 1) sum += shfl_xor_t(sum, m);
-            if (live && h == 0) lrows[(ib - row0 + orow) * D + odim] = (double)sum;
-#else
-            // transposed reduction of the staged rows: lane (g, p) adds the
-            // values of lanes p, p+GL, ... of row g, then GL lanes combine
-            constexpr int GL = kWave / RB;
-            const int g = lane / GL, p = lane % GL;
-            T sum[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) sum[d] = T(0);
-            if (g < nq) {
-#pragma unroll
-                for (int k = 0; k < RB; ++k) {
-                    const T* src = stage + (size_t)g * SROW + (size_t)(p + k * GL) * D;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) sum[d] += src[d];
+                    for (int k = 0; k < kWave / RG; ++k) sum += src[(size_t)k * RG * D];
                 }
+#pragma unroll
+                for (int m = RG / 2; m >= 1; m >>= 1) sum += shfl_xor_t(sum, m);
+                if (live && h == 0) lrows[(ib - row0 + orow) * D + odim] = (double)sum;
             }
-#pragma unroll
-            for (int m = GL / 2; m >= 1; m >>= 1)
-#pragma unroll
-                for (int d = 0; d < D; ++d) sum[d] += shfl_xor_t(sum[d], m);
-            if (p == 0 && g < nq) {
-                const int64_t row = ib - row0 + g;
-#pragma unroll
-                for (int d = 0; d < D; ++d) lrows[row * D + d] = (double)sum[d];
-            }
-#endif
         }
     }
 
+    const int wr = a.wr;
+    double* cp = a.colpart + (((size_t)c * a.nrb + r) * cw + (size_t)wu * kWave + lane) * D;
     if (GRAD) {
-        double* cp =
-            a.colpart + (((size_t)c * a.nrb + r) * cw + (size_t)w * kWave + lane) * D;
+        if (wr == 1) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) cp[d] = gj[d];
+            for (int d = 0; d < D; ++d) cp[d] = gj[d];
+        } else {
+            // the wr waves of one column group add their column sums in LDS
+            double* gs = reinterpret_cast<double*>(stage_base) + (size_t)lane * D;
+#pragma unroll
+            for (int d = 0; d < D; ++d) gs[d] = gj[d];
+        }
     }
     acc_r = wave_sum(acc_r);
     acc_s = wave_sum(acc_s);
@@ -509,10 +386,28 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     }
     __syncthreads();
     if (GRAD) {
+        if (wr > 1 && w < wc) {
+            // wave (wu, 0) adds the column sums of waves (wu, 0..wr-1) in order
+            double s[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) s[d] = 0.0;
+            for (int v = 0; v < wr; ++v) {
+                const double* gs = reinterpret_cast<const double*>(
+                                       reinterpret_cast<const char*>(lscal + (size_t)waves * 4) +
+                                       (size_t)(v * wc + wu) * stage_bytes) +
+                                   (size_t)lane * D;
+#pragma unroll
+                for (int d = 0; d < D; ++d) s[d] += gs[d];
+            }
+#pragma unroll
+            for (int d = 0; d < D; ++d) cp[d] = s[d];
+        }
+        // tile row sums: the column groups' copies added in order
         double* rp = a.rowpart + (size_t)tile * br * D;
-        for (int k = threadIdx.x; k < br * D; k += blockDim.x) {
+        const int nrow = (int)(row1 - row0) * D;
+        for (int k = threadIdx.x; k < nrow; k += blockDim.x) {
             double s = 0.0;
-            for (int ww = 0; ww < waves; ++ww) s += lds[(size_t)ww * br * D + k];
+            for (int u = 0; u < wc; ++u) s += lds[(size_t)u * br * D + k];
             rp[k] = s;
         }
     }
@@ -534,20 +429,20 @@ template <typename T, int D, bool GRAD>
 __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
-#if MDS_TILE_TRACE
-    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-#endif
+    const bool traced = a.trace != nullptr;
+    unsigned long long t0 = 0;
+    if (traced) t0 = __builtin_amdgcn_s_memrealtime();
     sweep_tile<T, D, GRAD>(a, blockIdx.x, lds);
-#if MDS_TILE_TRACE
-    // diagnostic build only: start and end clock (100 MHz) and HW_ID of each wave
-    const unsigned long long t1 = __builtin_amdgcn_s_memrealtime();
-    const unsigned long long hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);
-    const int ln = threadIdx.x & (kWave - 1);
-    if (a.trace && ln < 3) {
-        const unsigned long long v = ln == 0 ? t0 : (ln == 1 ? t1 : hw);
-        a.trace[((size_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * 3 + ln] = v;
+    if (traced) {
+        // diagnostics: start and end clock (100 MHz) and HW_ID of each wave
+        const unsigned long long t1 = __builtin_amdgcn_s_memrealtime();
+        const unsigned long long hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);
+        const int ln = threadIdx.x & (kWave - 1);
+        if (ln < 3) {
+            const unsigned long long v = ln == 0 ? t0 : (ln == 1 ? t1 : hw);
+            a.trace[((size_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * 3 + ln] = v;
+        }
     }
-#endif
 }
 
 // Persistent sweep over the tiles of a batch of independent problems: each

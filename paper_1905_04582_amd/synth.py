@@ -207,7 +207,17 @@ PRESETS = {
     "paper_fp32_d6_tight": dict(n=5392, d=6, sigma=0.05, dup_frac=0.01, seed=5394),
     "large_fp32_d2": dict(n=20000, d=2, sigma=0.5, dup_frac=0.01, seed=20000),
     "large_fp32_d6_tight": dict(n=20000, d=6, sigma=0.05, dup_frac=0.01, seed=20001),
+    "paper_fp32_d2_tight": dict(n=5392, d=2, sigma=0.05, dup_frac=0.01, seed=5395),
+    "paper_fp32_d6": dict(n=5392, d=6, sigma=0.5, dup_frac=0.01, seed=5396),
+    "large_fp32_d2_tight": dict(n=20000, d=2, sigma=0.05, dup_frac=0.01, seed=20002),
+    "large_fp32_d6": dict(n=20000, d=6, sigma=0.5, dup_frac=0.01, seed=20003),
 }
+
+# The precision form's grid: N in {5392, 20000} x D in {2, 6} x sigma in
+# {0.5, 0.05}, FP32 Y, 1% of the points near-duplicates (jitter 1e-4).
+PRECISION_PRESETS = ("paper_fp32_d2", "paper_fp32_d2_tight", "paper_fp32_d6",
+                     "paper_fp32_d6_tight", "large_fp32_d2", "large_fp32_d2_tight",
+                     "large_fp32_d6", "large_fp32_d6_tight")
 
 
 def preset(name: str, **override) -> Problem:

@@ -22,7 +22,17 @@ def _observed(y, mask, i, j):
     return not math.isnan(float(y[i][j]))
 
 
-def brute_force(x, y, sigma, mask=None, dps=40):
+def brute_force(x, y, sigma, mask=None, dps=40, truncated=True):
+    """L, dL/dX, dL/dsigma and the observed-pair count, plus the magnitude
+    sums that scale the rounding error of each output (the same pair terms
+    with every summand taken in absolute value):
+      absrow[i]  = sum_j |w_ij|                                   (A_i)
+      condrow[i] = sum_j [(delta_ij + |y_ij|)/sigma^2 + m_ij/sigma] (B_i, the
+                   bracket w_ij with both of its terms' sizes added)
+      abs_loglik = sum |r_ij| + M |ln sigma|
+      abs_dsigma = sum |(y - delta)^2/sigma^3 + delta m/sigma^2| + M/sigma
+    with m_ij = phi(t)/Phi(t).  truncated=False: the same sums with the ln Phi
+    and phi/Phi terms left out (normal errors without the truncation)."""
     with mp.workdps(dps):
         n = len(x)
         d = len(x[0])
@@ -30,7 +40,11 @@ def brute_force(x, y, sigma, mask=None, dps=40):
         X = [[mp.mpf(float(v)) for v in row] for row in x]
         L = mp.mpf(0)
         dS = mp.mpf(0)
+        absL = mp.mpf(0)
+        absS = mp.mpf(0)
         G = [[mp.mpf(0)] * d for _ in range(n)]
+        A = [mp.mpf(0)] * n
+        B = [mp.mpf(0)] * n
         m = 0
         for i in range(n):
             for j in range(i):
@@ -44,17 +58,31 @@ def brute_force(x, y, sigma, mask=None, dps=40):
                 Phi = mp.ncdf(t)
                 phi = mp.npdf(t)
                 # ln Phi(t) = log1p(-Phi(-t)) keeps every digit as Phi(t) -> 1
-                L -= (yij - delta) ** 2 / (2 * s * s) + mp.log1p(-mp.ncdf(-t))
-                w = (delta - yij) / (s * s) + phi / (s * Phi)
+                lnPhi = mp.log1p(-mp.ncdf(-t)) if truncated else mp.mpf(0)
+                mills = phi / Phi if truncated else mp.mpf(0)
+                r = (yij - delta) ** 2 / (2 * s * s) + lnPhi
+                L -= r
+                absL += abs(r)
+                w = (delta - yij) / (s * s) + mills / s
+                A[i] += abs(w)
+                A[j] += abs(w)
+                b = (delta + abs(yij)) / (s * s) + mills / s
+                B[i] += b
+                B[j] += b
                 if delta != 0:
                     for k in range(d):
                         G[i][k] -= w * diff[k] / delta
                         G[j][k] += w * diff[k] / delta
-                dS += (yij - delta) ** 2 / s ** 3 + delta / (s * s) * phi / Phi
+                ds = (yij - delta) ** 2 / s ** 3 + delta / (s * s) * mills
+                dS += ds
+                absS += abs(ds)
         if m:
             L -= m * mp.log(s)
             dS -= m / s
-        return dict(loglik=L, grad=G, dsigma=dS, m_obs=m)
+            absL += m * abs(mp.log(s))
+            absS += m / s
+        return dict(loglik=L, grad=G, dsigma=dS, m_obs=m, absrow=A, condrow=B,
+                    abs_loglik=absL, abs_dsigma=absS)
 
 
 def log_phi(t, dps=50):

@@ -39,6 +39,10 @@ static int host_checks(void)
               MDS_ERR_INVALID_ARGUMENT,
           "null pointers");
     CHECK(strcmp(mds_status_string(MDS_ERR_HIP), "MDS_ERR_HIP") == 0, "status string");
+    CHECK(mds_require_symmetric(NULL, MDS_F64, 10, 10, NULL, NULL) == MDS_ERR_INVALID_ARGUMENT,
+          "checked mode rejects NULL");
+    CHECK(strcmp(mds_status_string(MDS_ERR_NOT_SYMMETRIC), "MDS_ERR_NOT_SYMMETRIC") == 0,
+          "status string (symmetry)");
     printf("capi host checks ok (default tiles %dx%d, workspace %zu B at N=5392)\n", br, 64 * w,
            ws);
     return 0;
@@ -54,7 +58,7 @@ static int device_eval(const char* in_path, const char* out_path)
     CHECK(fread(&n, 8, 1, f) == 1 && fread(&d, 4, 1, f) == 1 && fread(&pad, 4, 1, f) == 1 &&
               fread(&sigma, 8, 1, f) == 1,
           "read header");
-    CHECK(n > 1 && n <= 4096 && d >= 1 && d <= MDS_MAX_DIM, "header values");
+    CHECK(n > 1 && n <= 8192 && d >= 1 && d <= MDS_MAX_DIM, "header values");
     double* x = (double*)malloc(sizeof(double) * (size_t)(n * d));
     double* y = (double*)malloc(sizeof(double) * (size_t)(n * n));
     double* g = (double*)malloc(sizeof(double) * (size_t)(n * d));
@@ -87,6 +91,12 @@ static int device_eval(const char* in_path, const char* out_path)
     CHECK(mds_prepare_y(dy_src, MDS_F64, n, NULL, 0, dy, MDS_F64, ldy, n, NULL, (int64_t*)dm,
                         NULL) == MDS_OK,
           "prepare");
+    /* the checked mode: the prepared Y is symmetric */
+    int64_t* dbad;
+    CHECK(hipMalloc((void**)&dbad, 8) == hipSuccess, "device allocation (count)");
+    CHECK(mds_require_symmetric(dy, MDS_F64, ldy, n, dbad, NULL) == MDS_OK, "symmetric Y accepted");
+    /* Y and the prepared copy are exact-size allocations (n x n and n x ldy
+       doubles): the sweep reads no row past the last one */
     CHECK(mds_gradient(n, d, dx, d, dy, MDS_F64, ldy, dsig, NULL, dg, d, dl, dds, NULL, dws, wsb,
                        0, 0, NULL) == MDS_OK,
           "gradient");
@@ -152,6 +162,18 @@ static int device_eval(const char* in_path, const char* out_path)
     CHECK(mds_lpd_finalize(mh, dacc, 2, dfw, fwb, dlpd, NULL) == MDS_OK, "lpd finalize");
     double lpd;
     CHECK(hipMemcpy(&lpd, dlpd, 8, hipMemcpyDeviceToHost) == hipSuccess, "download lpd");
+
+    /* one pair changed on one side only: the checked mode reports it */
+    int64_t ip = 1;
+    while (ip < n - 1 && y[ip * n] != y[ip * n]) ++ip; /* an observed pair (ip, 0) */
+    const double bump = y[ip * n] + 1.0;
+    CHECK(hipMemcpy(dy + ip * ldy, &bump, 8, hipMemcpyHostToDevice) == hipSuccess, "perturb");
+    CHECK(mds_require_symmetric(dy, MDS_F64, ldy, n, dbad, NULL) == MDS_ERR_NOT_SYMMETRIC,
+          "asymmetric Y rejected");
+    int64_t nbad = 0;
+    CHECK(hipMemcpy(&nbad, dbad, 8, hipMemcpyDeviceToHost) == hipSuccess && nbad == 1,
+          "one mismatched pair");
+    hipFree(dbad);
 
     FILE* o = fopen(out_path, "wb");
     CHECK(o != NULL, "open output");

@@ -153,6 +153,11 @@ def test_check_symmetric_rejects():
     assert L.mds_check_symmetric(_p(), 0, 10, 10, None, None) == ERR_ARG
     assert L.mds_check_symmetric(_p(FAKE + 4), 0, 10, 10, _p(), None) == ERR_ARG
     assert L.mds_status_string(-5) == b"MDS_ERR_NOT_SYMMETRIC"
+    # the checked mode validates the same way before any HIP call
+    assert L.mds_require_symmetric(_p(), 2, 10, 10, _p(), None) == ERR_UNSUP
+    assert L.mds_require_symmetric(_p(), 0, 9, 10, _p(), None) == ERR_ARG
+    assert L.mds_require_symmetric(None, 0, 10, 10, _p(), None) == ERR_ARG
+    assert L.mds_require_symmetric(_p(), 0, 10, 10, None, None) == ERR_ARG
 
 
 def test_hmc_rejects():
@@ -293,6 +298,21 @@ def test_resolve_tiling():
     assert L.mds_resolve_tiling(100, 2, 2, 0, 0, ctypes.byref(r), ctypes.byref(w)) == ERR_UNSUP
     assert L.mds_resolve_tiling(-1, 2, 0, 0, 0, ctypes.byref(r), ctypes.byref(w)) == ERR_ARG
     assert L.mds_resolve_tiling(100, 2, 0, 0, 0, None, ctypes.byref(w)) == ERR_ARG
+    # waves down the rows: the value round-trips; a plain count means one row wave
+    tw = api.tile_waves(1, 4)
+    assert tw == 1 | (4 << 8) and api.split_tile_waves(tw) == (1, 4)
+    assert api.split_tile_waves(4) == (4, 1)
+    assert api.mds_resolve_tiling(5392, 2, f64, 64, tw) == (64, tw)
+    assert api.mds_resolve_tiling(5392, 2, f64, 64, api.tile_waves(2, 1)) == (64, 2)
+    # the workspace depends on the tile, not on how its waves split it
+    assert api.mds_workspace_bytes(5392, 2, f64, 64, tw) == api.mds_workspace_bytes(5392, 2, f64, 64, 1)
+    for br, wv in ((64, api.tile_waves(1, 3)),      # 3 row waves
+                   (64, api.tile_waves(4, 4)),      # 16 waves per work-group
+                   (16, api.tile_waves(1, 4)),      # 4 rows per wave
+                   (64, api.tile_waves(0, 2)),      # no column wave
+                   (64, 1 << 16)):                  # undefined bits
+        assert L.mds_resolve_tiling(5392, 2, 0, br, wv, ctypes.byref(r), ctypes.byref(w)) == \
+            ERR_UNSUP, (br, hex(wv))
     # every tiling the tuner proposes resolves to itself
     import torch
     from paper_1905_04582_amd import autotune

@@ -15,10 +15,14 @@ from paper_1905_04582_amd import build, synth
 pytestmark = pytest.mark.gpu
 
 
-def test_c_program_matches_oracle(tmp_path):
+@pytest.mark.parametrize("case", ["n400_d3", "paper_n5392"])
+def test_c_program_matches_oracle(tmp_path, case):
     exe = build.NATIVE_BIN
     assert os.path.exists(exe), "build() compiles tests/native/capi_roundtrip"
-    p = synth.make_problem(400, 3, 0.6, seed=77, missing=0.1)
+    # n400_d3: a small problem; paper_n5392: the paper-scale workload with the
+    # default tiling, Y in exact-size device allocations
+    p = (synth.make_problem(400, 3, 0.6, seed=77, missing=0.1) if case == "n400_d3"
+         else synth.preset("paper_fp64"))
     y = p.y.copy()
     y[p.mask != 0] = np.nan                      # missing pairs travel as NaN
     inp, out = tmp_path / "in.bin", tmp_path / "out.bin"
@@ -28,7 +32,7 @@ def test_c_program_matches_oracle(tmp_path):
         np.array([p.sigma], np.float64).tofile(f)
         np.ascontiguousarray(p.x, np.float64).tofile(f)
         np.ascontiguousarray(y, np.float64).tofile(f)
-    print(f"native C-ABI run: n={p.n} d={p.d}", flush=True)
+    print(f"native C-ABI run: {case} n={p.n} d={p.d}", flush=True)
     r = subprocess.run([exe, "gpu", str(inp), str(out)], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr

@@ -65,40 +65,7 @@ def test_large_n_sampled_rows(n):
     err32 = np.max(np.abs(g32[rows] - g32ref), axis=1) / b32
     rel = abs(L32 - L64) / abs(L64)
     _log(f"  fp32 sampled rows: max err/B_i {err32.max():.2e}; L rel diff vs FP64 {rel:.2e}")
-    assert err32.max() < 1e-3
+    assert err32.max() <= 2.0 ** -17      # the FP32 form's stated row bound
     # FP64 L of FP64 Y against FP32 of FP32-rounded Y: the rounding of Y
     # itself moves L by well under the FP32 bound
-    assert rel <= 1e-5
-
-
-@pytest.mark.parametrize("sigma", [0.5, 0.05])
-def test_precision_form_n20000_d6(sigma):
-    # the precision-form sizes at D = 6: FP64 and FP32 sampled rows against
-    # the row oracle (each on its own Y), and L of the two forms
-    n, d = 20000, 6
-    _log(f"precision form: N={n} D={d} sigma={sigma}, Y drawn on the device")
-    _, x, y = synth.device_problem(n, d, sigma, seed=n + d, device=DEV)
-    rows = np.concatenate([np.random.default_rng(7).choice(n, 24, replace=False), [0, n - 1]])
-    yrows = y[torch.as_tensor(rows, device=DEV)].cpu().numpy()
-    gref, _, b = oracle.grad_rows_given(x, yrows, sigma, rows)
-
-    P = api.MDSProblem(y, d, None, torch.float64, DEV, order=x)
-    g64, L64, ds64 = _eval(P, x, sigma)
-    del P
-    err = np.max(np.abs(g64[rows] - gref), axis=1)
-    _log(f"  fp64 sampled rows: max err/B_i {np.max(err / b):.2e}")
-    assert np.all(err <= TOL64 * b)
-    assert np.isfinite(L64) and np.isfinite(ds64)
-
-    P32 = api.MDSProblem(y, d, None, torch.float32, DEV, order=x)
-    del y
-    torch.cuda.empty_cache()
-    g32, L32, _ = _eval(P32, x, sigma)
-    del P32
-    yr32 = yrows.astype(np.float32).astype(np.float64)
-    g32ref, _, b32 = oracle.grad_rows_given(x, yr32, sigma, rows)
-    err32 = np.max(np.abs(g32[rows] - g32ref), axis=1) / b32
-    rel = abs(L32 - L64) / abs(L64)
-    _log(f"  fp32 sampled rows: max err/B_i {err32.max():.2e}; L rel diff vs FP64 {rel:.2e}")
-    assert err32.max() < 1e-3
     assert rel <= 1e-5

@@ -99,6 +99,18 @@ def test_tiny_cases_vs_brute_force(name):
     gref = np.array([[float(v) for v in row] for row in ref["grad"]])
     scale = np.max(np.abs(gref))
     assert np.max(np.abs(ev.grad - gref)) <= 1e-14 * scale
+    _check_scales(ev, ref)
+
+
+def _check_scales(ev, ref, tol=1e-14):
+    """The oracle's rounding scales -- A_i, B_i and the absolute sums of L and
+    dL/dsigma, which set the tolerance of every GPU parity check -- against
+    the same sums in mpmath."""
+    for got, want in ((ev.absrow, ref["absrow"]), (ev.condrow, ref["condrow"])):
+        want = np.array([float(v) for v in want])
+        assert np.all(np.abs(got - want) <= tol * np.maximum(want, 1e-300)), (got, want)
+    assert _rel(ev.abs_loglik, float(ref["abs_loglik"])) < tol
+    assert _rel(ev.abs_dsigma, float(ref["abs_dsigma"])) < tol
 
 
 def test_case_c_closed_form():
@@ -153,6 +165,31 @@ def test_random_vs_brute_force(n, d, sigma, seed, missing, nan_frac):
     gref = np.array([[float(v) for v in row] for row in ref["grad"]])
     for i in range(n):
         assert np.max(np.abs(ev.grad[i] - gref[i])) <= 1e-14 * max(ev.absrow[i], 1e-300)
+    _check_scales(ev, ref)
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_scales_of_untruncated_model_vs_brute_force(seed):
+    # the untruncated evaluation's scales (the tolerances of its GPU checks)
+    x, y, mask = _rand_problem(7, 3, 0.7, seed, missing=0.2, nan_frac=0.1)
+    ref = mpr.brute_force(x, y, 0.7, mask, truncated=False)
+    ev = oracle.evaluate(x, y, 0.7, mask, truncated=False)
+    _check_scales(ev, ref)
+
+
+def test_scale_of_a_pair_by_hand():
+    # two points, delta = 1, y = 2, sigma = 0.5: w = (1 - 2)/0.25 + 2 m(2),
+    # r = 1/(2 0.25) + ln Phi(2), ds = 1/0.125 + 4 m(2), with m(2) = phi(2)/Phi(2)
+    x = np.array([[0.0], [1.0]])
+    y = np.array([[0.0, 2.0], [2.0, 0.0]])
+    ev = oracle.evaluate(x, y, 0.5)
+    m2 = math.exp(-2.0) / math.sqrt(2 * math.pi) / special.ndtr(2.0)
+    b = (1.0 + 2.0) / 0.25 + m2 / 0.5
+    assert ev.condrow == pytest.approx([b, b], rel=1e-15)
+    assert ev.absrow == pytest.approx([abs(-4.0 + 2 * m2)] * 2, rel=1e-15)
+    assert ev.abs_loglik == pytest.approx(abs(2.0 + special.log_ndtr(2.0)) + math.log(2.0),
+                                          rel=1e-15)
+    assert ev.abs_dsigma == pytest.approx(8.0 + 4.0 * m2 + 2.0, rel=1e-15)
 
 
 def test_coincident_points():
@@ -364,8 +401,8 @@ def test_grad_rows_vs_brute_force():
     for r, i in enumerate(rows):
         gref = np.array([float(v) for v in ref["grad"][i]])
         assert np.max(np.abs(g[r] - gref)) <= 1e-14 * ev.absrow[i]
-        assert a[r] == pytest.approx(ev.absrow[i], rel=1e-15)
-        assert b[r] == pytest.approx(ev.condrow[i], rel=1e-15)
+        assert a[r] == pytest.approx(float(ref["absrow"][i]), rel=1e-14)
+        assert b[r] == pytest.approx(float(ref["condrow"][i]), rel=1e-14)
 
 
 def test_grad_rows_given_vs_brute_force():
@@ -379,8 +416,8 @@ def test_grad_rows_given_vs_brute_force():
     for r, i in enumerate(rows):
         gref = np.array([float(v) for v in ref["grad"][i]])
         assert np.max(np.abs(g[r] - gref)) <= 1e-14 * ev.absrow[i]
-        assert a[r] == pytest.approx(ev.absrow[i], rel=1e-15)
-        assert b[r] == pytest.approx(ev.condrow[i], rel=1e-15)
+        assert a[r] == pytest.approx(float(ref["absrow"][i]), rel=1e-14)
+        assert b[r] == pytest.approx(float(ref["condrow"][i]), rel=1e-14)
     with pytest.raises(ValueError):
         oracle.grad_rows_given(x, yf[rows], 0.6, [0, 9, 1])
 
