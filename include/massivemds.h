@@ -241,6 +241,29 @@ MDS_API int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, con
                  int32_t tile_rows, int32_t tile_waves, hipStream_t stream);
 
 /*
+ * mds_gradient for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same evaluation, outputs and arguments as mds_gradient, without a
+ * workspace argument.  Its partial sums live in a static device array of
+ * mds_noalloc_scratch_bytes() bytes (32 MiB) that the library holds on each
+ * device for the life of the process; the call itself allocates nothing.
+ * A problem whose workspace (mds_workspace_bytes with the same arguments)
+ * exceeds that size is rejected with MDS_ERR_WORKSPACE_TOO_SMALL (at the
+ * default tiling N = 5392 needs 16.2 MB in either dtype).  Every call on one
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller.  The first
+ * call on a device looks the array's address up (hipGetSymbolAddress), which
+ * is not capturable; make that first call outside a capture.
+ */
+MDS_API size_t mds_noalloc_scratch_bytes(void);
+MDS_API int mds_gradient_noalloc(int64_t n, int32_t d, const double* x, int64_t ldx,
+                                 const void* y, int32_t y_dtype, int64_t ldy,
+                                 const double* sigma_dev, const double* scale_dev, double* grad,
+                                 int64_t ldg, double* loglik_dev, double* dsigma_dev,
+                                 double* dlogsigma_dev, int32_t tile_rows, int32_t tile_waves,
+                                 hipStream_t stream);
+
+/*
  * One leapfrog trajectory of Hamiltonian Monte Carlo (Section 2.3, Eqs. 6-8)
  * on the target log pi(X) = L(X) - (lambda/2) ||X||_F^2:
  *     p += (eps/2) grad log pi(x);

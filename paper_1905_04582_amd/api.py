@@ -127,6 +127,11 @@ def lib():
     L.mds_gradient.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i64, _vp, _vp, _vp,
                                _c_i64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _c_i32, _c_i32,
                                _vp]
+    L.mds_noalloc_scratch_bytes.restype = ctypes.c_size_t
+    L.mds_noalloc_scratch_bytes.argtypes = []
+    L.mds_gradient_noalloc.restype = ctypes.c_int
+    L.mds_gradient_noalloc.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i64, _vp, _vp,
+                                       _vp, _c_i64, _vp, _vp, _vp, _c_i32, _c_i32, _vp]
     L.mds_leapfrog.restype = ctypes.c_int
     L.mds_leapfrog.argtypes = [_c_i64, _c_i32, _vp, _c_i64, _vp, _c_i64, _vp, _c_i32, _c_i64,
                                _vp, _vp, _vp, _vp, _c_i32, _vp, _vp, _c_i32, _vp, _vp, _vp,
@@ -162,8 +167,17 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _stream(stream=None):
+def _stream(stream=None, *tensors):
+    """The raw stream a call is enqueued on.  When the caller names a stream,
+    every device tensor the call hands to a kernel (temporaries included:
+    converted inputs, device scalars made from numbers, fresh outputs) is
+    recorded on it, so that the caching allocator does not hand its memory
+    out again before the kernel has run."""
     s = torch.cuda.current_stream() if stream is None else stream
+    if stream is not None:
+        for t in tensors:
+            if isinstance(t, torch.Tensor) and t.is_cuda:
+                t.record_stream(stream)
     return ctypes.c_void_p(s.cuda_stream)
 
 
@@ -269,7 +283,7 @@ def mds_prepare_y(y_src: torch.Tensor, out_dtype: torch.dtype = torch.float64, m
     _check(lib().mds_prepare_y(_ptr(y_src), _dtype_code(y_src.dtype), _ld(y_src),
                                _ptr(mask), _ld(mask) if mask is not None else 0,
                                _ptr(buf), _dtype_code(out_dtype), ldy, n, _ptr(perm),
-                               _ptr(m_obs), _stream(stream)), "mds_prepare_y")
+                               _ptr(m_obs), _stream(stream, y_src, mask, buf, perm, m_obs)), "mds_prepare_y")
     return buf[:n], m_obs
 
 
@@ -280,7 +294,7 @@ def mds_check_symmetric(y: torch.Tensor, stream=None) -> int:
     n = y.shape[0]
     cnt = torch.zeros((), dtype=torch.int64, device=y.device)
     _check(lib().mds_check_symmetric(_ptr(y), _dtype_code(y.dtype), _ld(y), n, _ptr(cnt),
-                                     _stream(stream)), "mds_check_symmetric")
+                                     _stream(stream, y, cnt)), "mds_check_symmetric")
     return int(cnt.item())
 
 
@@ -292,7 +306,7 @@ def mds_require_symmetric(y: torch.Tensor, stream=None):
     n = y.shape[0]
     cnt = torch.zeros((), dtype=torch.int64, device=y.device)
     _check(lib().mds_require_symmetric(_ptr(y), _dtype_code(y.dtype), _ld(y), n, _ptr(cnt),
-                                       _stream(stream)), "mds_require_symmetric")
+                                       _stream(stream, y, cnt)), "mds_require_symmetric")
 
 
 def _check_perm(perm, n, device):
@@ -311,7 +325,7 @@ def mds_spatial_order(x: torch.Tensor, stream=None) -> torch.Tensor:
     ws = alloc_workspace(nb.value, x.device)
     perm = torch.empty(max(n, 1), dtype=torch.int64, device=x.device)[:n]
     _check(lib().mds_spatial_order(n, d, _ptr(x), _ld(x), _ptr(perm), _ptr(ws), nb.value,
-                                   _stream(stream)), "mds_spatial_order")
+                                   _stream(stream, x, perm, ws)), "mds_spatial_order")
     return perm
 
 
@@ -324,7 +338,7 @@ def mds_permute_rows(src: torch.Tensor, perm: torch.Tensor, inverse: bool = Fals
     out = torch.empty_like(src) if out is None else out
     _check_mat(out, "out")
     _check(lib().mds_permute_rows(n, d, _ptr(src), _ld(src), _ptr(out), _ld(out), _ptr(perm),
-                                  1 if inverse else 0, _stream(stream)), "mds_permute_rows")
+                                  1 if inverse else 0, _stream(stream, src, perm, out)), "mds_permute_rows")
     return out
 
 
@@ -337,7 +351,8 @@ def mds_loglik(x, y, sigma, workspace, out=None, tile_rows=0, tile_waves=0, stre
     out = torch.empty((), dtype=torch.float64, device=x.device) if out is None else out
     _check(lib().mds_loglik(n, d, _ptr(x), _ld(x), _ptr(y), _ycode(y, truncated),
                             _ld(y), _ptr(sig), _ptr(out), _ptr(workspace),
-                            workspace.numel(), tile_rows, tile_waves, _stream(stream)),
+                            workspace.numel(), tile_rows, tile_waves,
+                            _stream(stream, x, y, sig, out, workspace)),
            "mds_loglik")
     return out
 
@@ -362,8 +377,33 @@ def mds_gradient(x, y, sigma, workspace, scale=None, grad=None, loglik=None, dsi
     _check(lib().mds_gradient(n, d, _ptr(x), _ld(x), _ptr(y), _ycode(y, truncated),
                               _ld(y), _ptr(sig), _ptr(sc), _ptr(grad), _ld(grad),
                               _ptr(loglik), _ptr(dsigma), _ptr(dlogsigma), _ptr(workspace),
-                              workspace.numel(), tile_rows, tile_waves, _stream(stream)),
+                              workspace.numel(), tile_rows, tile_waves,
+                              _stream(stream, x, y, sig, sc, grad, loglik, dsigma, dlogsigma,
+                                      workspace)),
            "mds_gradient")
+    return grad, loglik, dsigma
+
+
+def mds_gradient_noalloc(x, y, sigma, grad, loglik=None, dsigma=None, dlogsigma=None,
+                         scale=None, tile_rows=0, tile_waves=0, stream=None, truncated=True):
+    """mds_gradient without a workspace: the library's static device scratch
+    holds the partial sums (see include/massivemds.h).  Every tensor is the
+    caller's; sigma and scale must already be device scalars, so the call
+    itself allocates nothing."""
+    _check_mat(x, "x")
+    _check_mat(y, "y", y.dtype)
+    _check_mat(grad, "grad")
+    n, d = x.shape
+    for t, nm in ((sigma, "sigma"), (scale, "scale")):
+        if t is not None and not (isinstance(t, torch.Tensor) and t.is_cuda and
+                                  t.dtype == torch.float64 and t.numel() == 1):
+            raise TypeError(f"{nm} must be a one-element float64 device tensor")
+    _check(lib().mds_gradient_noalloc(n, d, _ptr(x), _ld(x), _ptr(y), _ycode(y, truncated),
+                                      _ld(y), _ptr(sigma), _ptr(scale), _ptr(grad), _ld(grad),
+                                      _ptr(loglik), _ptr(dsigma), _ptr(dlogsigma), tile_rows,
+                                      tile_waves, _stream(stream, x, y, sigma, scale, grad, loglik,
+                                                          dsigma, dlogsigma)),
+           "mds_gradient_noalloc")
     return grad, loglik, dsigma
 
 
@@ -390,7 +430,8 @@ def mds_leapfrog(x, p, y, sigma, step, n_steps, workspace, grad_io, loglik_io,
                               _ptr(eps), _ptr(lam), int(n_steps), _ptr(grad_io), _ptr(loglik_io),
                               1 if cache_valid else 0, _ptr(energy_start), _ptr(energy_end),
                               _ptr(workspace), workspace.numel(), tile_rows, tile_waves,
-                              _stream(stream)), "mds_leapfrog")
+                              _stream(stream, x, p, y, sig, inv_mass, eps, lam, grad_io, loglik_io,
+                                      energy_start, energy_end, workspace)), "mds_leapfrog")
 
 
 def mds_hmc_workspace_bytes(n: int, d: int, y_dtype: int, tile_rows: int = 0,
@@ -418,7 +459,8 @@ def mds_hmc_momentum(n: int, d: int, seed: int, iteration: torch.Tensor, inv_mas
     if inv_mass is not None:
         _check_mat(inv_mass, "inv_mass")
     _check(lib().mds_hmc_momentum(n, d, _ptr(inv_mass), int(seed) & 0xFFFFFFFFFFFFFFFF,
-                                  _ptr(iteration), _ptr(out), _ld(out), _stream(stream)),
+                                  _ptr(iteration), _ptr(out), _ld(out),
+                                  _stream(stream, inv_mass, iteration, out)),
            "mds_hmc_momentum")
     return out
 
@@ -450,7 +492,9 @@ def mds_hmc_step(x, p, y, sigma, step, n_steps, seed, iteration, workspace, grad
                               int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(iteration), _ptr(p), _ld(p),
                               _ptr(grad_io), _ptr(loglik_io), 1 if cache_valid else 0,
                               _ptr(stats), _ptr(accepted_total), _ptr(workspace),
-                              workspace.numel(), tile_rows, tile_waves, _stream(stream)),
+                              workspace.numel(), tile_rows, tile_waves,
+                              _stream(stream, x, p, y, sig, inv_mass, eps, lam, iteration,
+                                      grad_io, loglik_io, stats, accepted_total, workspace)),
            "mds_hmc_step")
 
 
@@ -461,7 +505,7 @@ def mds_log_phi(t: torch.Tensor, precision: int = MDS_F64, stream=None):
     ln = torch.empty_like(t)
     mi = torch.empty_like(t)
     _check(lib().mds_log_phi(_ptr(t), _ptr(ln), _ptr(mi), t.numel(), precision,
-                             _stream(stream)), "mds_log_phi")
+                             _stream(stream, t, ln, mi)), "mds_log_phi")
     return ln, mi
 
 
@@ -604,6 +648,7 @@ class MDSBatch:
         self.device = torch.device(device)
         if autotuned:
             problems, tile_waves = _autotuned_batch(problems, dtype, device, tile_waves)
+        self.tile_waves = tile_waves  # common to the batch (0 = the library's default)
         self.dtype = dtype
         f64 = dict(dtype=torch.float64, device=self.device)
         count = len(problems)
@@ -701,22 +746,18 @@ class MDSBatch:
 
 
 def _autotuned_batch(problems, dtype, device, tile_waves):
-    """Per-problem row tiles from the autotune cache under one common width:
-    the width most problems' entries chose, and each problem's tuned row tile
-    when it is compatible with that width (else the library default)."""
-    from collections import Counter
-
+    """Tilings of a batch from the batch tuner's cache (autotune.batch_plan):
+    the common wave layout with the least predicted time and each problem's
+    fastest row tile under it.  A problem that names its tile_rows keeps it;
+    one whose (D, N bucket) has no entry keeps the library's batch default."""
     from . import autotune
-    picks = [autotune.lookup(dtype, int(p["d"]), int(torch.as_tensor(p["y"]).shape[0]), device)
-             for p in problems]
-    if tile_waves == 0:
-        widths = Counter(w for _, w in picks if w)
-        tile_waves = widths.most_common(1)[0][0] if widths else 0
+    sizes = [(int(torch.as_tensor(p["y"]).shape[0]) if not isinstance(p["y"], torch.Tensor)
+              else int(p["y"].shape[0]), int(p["d"])) for p in problems]
+    tile_waves, rows = autotune.batch_plan(sizes, dtype, device, tile_waves=tile_waves)
     out = []
-    for p, (br, w) in zip(problems, picks):
+    for p, br in zip(problems, rows):
         q = dict(p)
-        cw = 64 * (tile_waves or 4)
-        if br and "tile_rows" not in p and (br % cw == 0 or cw % br == 0):
+        if br and "tile_rows" not in p:
             q["tile_rows"] = br
         out.append(q)
     return out, tile_waves
@@ -754,7 +795,8 @@ class HeldOutPairs:
         cnt = torch.zeros((), dtype=torch.int64, device=dev)
         args = (_ptr(src), _dtype_code(src.dtype), _ld(src), _ptr(m), _ld(m) if m is not None else 0,
                 _ptr(h), _ld(h), n)
-        _check(lib().mds_heldout_count(*args, _ptr(cnt), _ptr(ws), ws.numel(), _stream(stream)),
+        _check(lib().mds_heldout_count(*args, _ptr(cnt), _ptr(ws), ws.numel(),
+                                       _stream(stream, src, h, m, cnt, ws)),
                "mds_heldout_count")
         self.m = int(cnt.item())
         k = max(self.m, 1)
@@ -762,7 +804,8 @@ class HeldOutPairs:
         self.pj = torch.empty(k, dtype=torch.int32, device=dev)
         self.py = torch.empty(k, dtype=torch.float64, device=dev)
         _check(lib().mds_heldout_fill(*args, _ptr(ws), ws.numel(), self.m, _ptr(self.pi),
-                                      _ptr(self.pj), _ptr(self.py), _stream(stream)),
+                                      _ptr(self.pj), _ptr(self.py),
+                                      _stream(stream, src, h, m, ws, self.pi, self.pj, self.py)),
                "mds_heldout_fill")
         self.acc = torch.empty(2 * k, dtype=torch.float64, device=dev)
         self.draws = 0
@@ -776,7 +819,9 @@ class HeldOutPairs:
         sig = _dev_scalar(sigma, self.device)
         _check(lib().mds_lpd_accumulate(self.m, _ptr(self.pi), _ptr(self.pj), _ptr(self.py),
                                         x.shape[1], _ptr(x), _ld(x), _ptr(sig), _ptr(self.acc),
-                                        1 if self.draws == 0 else 0, _stream(stream)),
+                                        1 if self.draws == 0 else 0,
+                                        _stream(stream, x, sig, self.pi, self.pj, self.py,
+                                                self.acc)),
                "mds_lpd_accumulate")
         self.draws += 1
 
@@ -798,7 +843,9 @@ class HeldOutPairs:
         _check(lib().mds_lpd_accumulate_draws(self.m, _ptr(self.pi), _ptr(self.pj),
                                               _ptr(self.py), d, _ptr(xs), d, self.n * d,
                                               _ptr(sig), s_draws, _ptr(self.acc),
-                                              1 if self.draws == 0 else 0, _stream(stream)),
+                                              1 if self.draws == 0 else 0,
+                                              _stream(stream, xs, sig, self.pi, self.pj,
+                                                      self.py, self.acc)),
                "mds_lpd_accumulate_draws")
         self.draws += s_draws
 
@@ -812,7 +859,8 @@ class HeldOutPairs:
                    "mds_lpd_workspace_bytes")
             self._fin_ws = alloc_workspace(nb.value, self.device)
         _check(lib().mds_lpd_finalize(self.m, _ptr(self.acc), self.draws, _ptr(self._fin_ws),
-                                      self._fin_ws.numel(), _ptr(out), _stream(stream)),
+                                      self._fin_ws.numel(), _ptr(out),
+                                      _stream(stream, self.acc, self._fin_ws, out)),
                "mds_lpd_finalize")
         return out
 

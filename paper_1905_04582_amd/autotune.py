@@ -1,11 +1,22 @@
 """Tile-shape autotuner for the pair sweep.
 
-For a (Y dtype, D, N bucket) it times every feasible tiling -- rows per tile
-(8/16/32/64/128/256) x 64-column groups per tile (1/2/4/8), one dividing the
-other, within the LDS budget -- on a problem of that size and keeps the
-fastest in a JSON cache keyed by GPU architecture, dtype, D and bucket.
+Single problems: for a (Y dtype, D, N bucket) it times every feasible tiling
+-- rows per tile (8/16/32/64/128/256) x 64-column waves across the tile
+(1/2/4/8) x waves down its rows (1/2/4/8; at most 8 waves per work-group and
+8 rows per wave), rows and columns one dividing the other, within the LDS
+budget -- on a problem of that size and keeps the fastest in a JSON cache
+keyed by GPU architecture, dtype, D and bucket.
 
-The tuning problem is generated on the device: locations X ~ N(0, 9 I) in
+Batches (many problems in one persistent launch): every problem of a batch
+shares the work-group's wave layout (tile_waves) and has its own rows per
+tile.  For a (dtype, D, N bucket) the batch tuner times the persistent
+evaluation of a batch of copies of a problem of that size for every row tile
+under each common wave layout and records, per layout, the fastest row tile
+and its time.  A batch built with ``autotuned=True`` takes the layout whose
+recorded times, scaled by each problem's pairs, add up to the least, and each
+problem's fastest row tile under it (``batch_plan``).
+
+The tuning problems are generated on the device: locations X ~ N(0, 9 I) in
 spatial order (as ``MDSProblem(order=...)`` stores a problem) and a random
 symmetric Y, evaluated at sigma = 0.5.  The sweep's cost depends on the data
 only through the wavefronts that skip the truncation terms, i.e. on how far
@@ -13,6 +24,7 @@ apart the locations are relative to sigma.
 
     python -m paper_1905_04582_amd.autotune --dtype f64 --d 2 --n 5392
     python -m paper_1905_04582_amd.autotune --grid           # the standard grid
+    python -m paper_1905_04582_amd.autotune --batch-grid     # the batched form's grid
 
 Lookups (``lookup``) return (tile_rows, tile_waves), or (0, 0) -- the
 library's built-in default -- when the cache has no entry.
@@ -81,18 +93,29 @@ def lookup(dtype, d: int, n: int, device=None, path: str | None = None):
 
 
 def candidates(n: int, d: int, dtype):
+    """(tile_rows, tile_waves) of every tiling the library accepts at (n, d)."""
     code = api.MDS_F64 if dtype == torch.float64 else api.MDS_F32
     out = []
     for br in ROW_TILES:
         for w in WAVE_TILES:
             if (64 * w) % br and br % (64 * w):
                 continue
-            try:
-                api.mds_workspace_bytes(n, d, code, br, w)
-            except api.MDSError:
-                continue          # exceeds the LDS budget at this D
-            out.append((br, w))
+            for wr in WAVE_TILES:
+                if w * wr > 8 or br // wr < 8:
+                    continue
+                tw = api.tile_waves(w, wr)
+                try:
+                    api.mds_resolve_tiling(n, d, code, br, tw)
+                except api.MDSError:
+                    continue          # exceeds the LDS budget at this D
+                out.append((br, tw))
     return out
+
+
+def label(br: int, tw: int) -> str:
+    """'rows x columns / row waves' of a tiling, e.g. '64x64/4'."""
+    wc, wr = api.split_tile_waves(tw)
+    return f"{br}x{64 * wc}/{wr}"
 
 
 def _random_problem(n, d, dtype, device, seed=0, ordered=True):
@@ -191,23 +214,153 @@ def tune(dtype, d: int, n: int, device="cuda", reps: int = 20, path: str | None 
     """Time every candidate tiling at (dtype, D, N) and record the fastest."""
     device = torch.device(device)
     x, yp = _random_problem(n, d, dtype, device)
-    results, sweeps = {}, {}
+    results, sweeps, tiling = {}, {}, {}
     for br, w in candidates(n, d, dtype):
-        results[f"{br}x{64 * w}"] = time_tiling(x, yp, 0.5, br, w, reps=reps)
-        sweeps[f"{br}x{64 * w}"] = time_sweep_only(x, yp, 0.5, br, w, reps=reps)
+        k = label(br, w)
+        tiling[k] = (br, w)
+        results[k] = time_tiling(x, yp, 0.5, br, w, reps=reps)
+        sweeps[k] = time_sweep_only(x, yp, 0.5, br, w, reps=reps)
         if verbose:
-            print(f"  {dtype} D={d} N={n} tile {br}x{64 * w}: "
-                  f"{results[f'{br}x{64 * w}'] * 1e3:.1f} us "
-                  f"(sweep {sweeps[f'{br}x{64 * w}'] * 1e3:.1f} us)", flush=True)
+            print(f"  {dtype} D={d} N={n} tile {k}: {results[k] * 1e3:.1f} us "
+                  f"(sweep {sweeps[k] * 1e3:.1f} us)", flush=True)
     best = min(results, key=results.get)
-    br, cols = (int(v) for v in best.split("x"))
-    entry = dict(tile_rows=br, tile_waves=cols // 64, ms=results[best], n=n,
+    br, w = tiling[best]
+    entry = dict(tile_rows=br, tile_waves=w, ms=results[best], n=n,
                  candidates_ms=results, sweep_only_ms=sweeps,
                  tuned_at=time.strftime("%Y-%m-%dT%H:%M:%S"))
     table = load(path)
     table[_key(_arch(device), dtype, d, n)] = entry
     save(table, path)
     return entry
+
+
+# ------------------------------------------------------------- batches ----
+
+BATCH_WAVES = ((1, 1), (2, 1), (4, 1), (1, 2), (2, 2), (1, 4), (4, 2), (2, 4), (1, 8))
+BATCH_ROWS = (16, 32, 64, 128, 256)
+BATCH_COPIES = 4
+
+
+def _batch_key(arch, dtype, d, n):
+    return "batch|" + _key(arch, dtype, d, n)
+
+
+def batch_candidates(n: int, d: int, dtype):
+    """{tile_waves: [tile_rows, ...]} the batched form accepts at (n, d)."""
+    code = api.MDS_F64 if dtype == torch.float64 else api.MDS_F32
+    out = {}
+    for wc, wr in BATCH_WAVES:
+        tw = api.tile_waves(wc, wr)
+        rows = []
+        for br in BATCH_ROWS:
+            try:
+                api.mds_resolve_tiling(n, d, code, br, tw)
+            except api.MDSError:
+                continue
+            rows.append(br)
+        if rows:
+            out[tw] = rows
+    return out
+
+
+def time_batch(problems, dtype, tile_waves, reps=10, warmup=3):
+    """Median time (ms) of one persistent evaluation (sweep and finalize) of
+    an MDSBatch of ``problems`` (dicts with y, d, x, sigma, tile_rows)."""
+    B = api.MDSBatch([dict(y=p["y"], d=p["d"], tile_rows=p["tile_rows"]) for p in problems],
+                     dtype, problems[0]["y"].device, tile_waves=tile_waves)
+    for k, p in enumerate(problems):
+        B.x[k].copy_(p["x"])
+        B.sigma[k] = p["sigma"]
+    for _ in range(warmup):
+        B.eval()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        B.eval()
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in ev)
+    del B
+    return ts[len(ts) // 2]
+
+
+def tune_batch(dtype, d: int, n: int, device="cuda", reps: int = 10, copies: int = BATCH_COPIES,
+               path: str | None = None, verbose: bool = False) -> dict:
+    """Time the persistent batched evaluation of `copies` problems of size n
+    for every (common tile_waves, tile_rows) and record the fastest row tile
+    per wave layout."""
+    device = torch.device(device)
+    probs = []
+    for c in range(copies):
+        x, yp = _random_problem(n, d, torch.float64, device, seed=100 + c)
+        probs.append(dict(y=yp, d=d, x=x, sigma=0.5))
+    by_waves = {}
+    for tw, rows in batch_candidates(n, d, dtype).items():
+        times = {}
+        for br in rows:
+            for p in probs:
+                p["tile_rows"] = br
+            times[br] = time_batch(probs, dtype, tw, reps=reps)
+            if verbose:
+                print(f"  batch {dtype} D={d} N={n} waves {api.split_tile_waves(tw)} "
+                      f"rows {br}: {times[br] * 1e3:.1f} us", flush=True)
+        best = min(times, key=times.get)
+        by_waves[str(tw)] = dict(tile_rows=best, ms=times[best], candidates_ms=times)
+    entry = dict(n=n, copies=copies, pairs=copies * n * (n - 1) // 2, by_waves=by_waves,
+                 tuned_at=time.strftime("%Y-%m-%dT%H:%M:%S"))
+    table = load(path)
+    table[_batch_key(_arch(device), dtype, d, n)] = entry
+    save(table, path)
+    return entry
+
+
+def batch_plan(sizes, dtype, device=None, path: str | None = None, tile_waves: int = 0):
+    """Tilings of a batch from the batch tuner's entries: sizes is a list of
+    (n, d).  Returns (tile_waves, [tile_rows per problem]) -- the common wave
+    layout whose recorded times, each scaled by the problem's pairs over the
+    tuning batch's, add up to the least, and every problem's fastest row tile
+    under it (0 = the library's default when a problem's bucket has no
+    entry).  A given tile_waves is kept and only the row tiles are chosen."""
+    table = load(path)
+    arch = _arch(device)
+    entries = [table.get(_batch_key(arch, dtype, d, n)) for n, d in sizes]
+    if tile_waves == 0:
+        common = None
+        for e in entries:
+            if e is not None:
+                ks = set(e["by_waves"])
+                common = ks if common is None else common & ks
+        if common:
+            def cost(tw):
+                tot = 0.0
+                for (n, _), e in zip(sizes, entries):
+                    if e is not None:
+                        tot += e["by_waves"][tw]["ms"] * (n * (n - 1) / 2) / e["pairs"]
+                return tot
+            tile_waves = int(min(sorted(common), key=cost))
+    rows = []
+    for e in entries:
+        r = e["by_waves"].get(str(tile_waves)) if (e is not None and tile_waves) else None
+        rows.append(int(r["tile_rows"]) if r else 0)
+    return tile_waves, rows
+
+
+def tune_batch_grid(dtypes=(torch.float32,), dims=(2, 4, 6), ns=(512, 768, 1024, 1536, 2048,
+                                                                    3072, 4096, 6144, 8192),
+                    device="cuda", reps=8, verbose=True):
+    out = {}
+    for dt in dtypes:
+        for d in dims:
+            for n in ns:
+                e = tune_batch(dt, d, n, device=device, reps=reps)
+                out[_batch_key(_arch(device), dt, d, n)] = e
+                if verbose:
+                    best = min(e["by_waves"].items(), key=lambda kv: kv[1]["ms"])
+                    print(f"batch {_key(_arch(device), dt, d, n)}: best waves "
+                          f"{api.split_tile_waves(int(best[0]))} rows {best[1]['tile_rows']} "
+                          f"{best[1]['ms'] * 1e3:.1f} us for {e['copies']} problems", flush=True)
+    return out
 
 
 GRID_N = (1000, 2000, 4000, 5392, 8000, 16000, 20000)
@@ -222,8 +375,9 @@ def tune_grid(dtypes=(torch.float64, torch.float32), dims=(2, 4, 6), ns=GRID_N,
                 e = tune(dt, d, n, device=device, reps=reps, verbose=False)
                 out[_key(_arch(device), dt, d, n)] = e
                 if verbose:
-                    print(f"{_key(_arch(device), dt, d, n)}: best {e['tile_rows']}x"
-                          f"{64 * e['tile_waves']} {e['ms'] * 1e3:.1f} us", flush=True)
+                    print(f"{_key(_arch(device), dt, d, n)}: best "
+                          f"{label(e['tile_rows'], e['tile_waves'])} {e['ms'] * 1e3:.1f} us",
+                          flush=True)
     return out
 
 
@@ -234,11 +388,19 @@ def main():
     ap.add_argument("--n", type=int, default=5392)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--grid", action="store_true", help="tune the standard (dtype, D, N) grid")
+    ap.add_argument("--batch-grid", action="store_true",
+                    help="tune the batched form's (D, N bucket) grid (FP32)")
+    ap.add_argument("--batch", action="store_true", help="tune the batched form at --dtype/--d/--n")
     ap.add_argument("--cache", default=None)
     args = ap.parse_args()
     if args.cache:
         os.environ["MDS_TUNE_CACHE"] = args.cache
-    if args.grid:
+    if args.batch_grid:
+        tune_batch_grid()
+    elif args.batch:
+        dt = torch.float64 if args.dtype == "f64" else torch.float32
+        print(json.dumps(tune_batch(dt, args.d, args.n, reps=args.reps, verbose=True)))
+    elif args.grid:
         tune_grid()
     else:
         dt = torch.float64 if args.dtype == "f64" else torch.float32

@@ -4,6 +4,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -210,6 +211,23 @@ int check_workspace(const Tiling& t, int d, const void* ws, size_t ws_bytes,
     return MDS_OK;
 }
 
+// the arguments of mds_gradient other than its workspace and tiling
+int check_gradient_args(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
+                        int32_t y_dtype, int64_t ldy, const double* sigma_dev,
+                        const double* scale_dev, const double* grad, int64_t ldg,
+                        const double* loglik_dev, const double* dsigma_dev,
+                        const double* dlogsigma_dev)
+{
+    const int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
+    if (st) return st;
+    if (n > 0 && !grad) return fail(MDS_ERR_INVALID_ARGUMENT, "grad is NULL");
+    if (ldg < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldg=%lld < d=%d", (long long)ldg, d);
+    if (!aligned(grad, 8) || !aligned(loglik_dev, 8) || !aligned(dsigma_dev, 8) ||
+        !aligned(dlogsigma_dev, 8) || !aligned(scale_dev, 8))
+        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned output pointer");
+    return MDS_OK;
+}
+
 // a sweep launch, bracketed by the diagnostic events when they are set
 hipError_t timed_sweep(int y_dtype, int d, bool grad, const Tiling& t, const SweepArgs& a,
                        hipStream_t s)
@@ -260,6 +278,40 @@ FinalizeArgs finalize_args(const Tiling& t, const SweepArgs& s)
     f.tcount = s.tcount;
     f.sigma = s.sigma;
     return f;
+}
+
+// Scratch of mds_gradient_noalloc: the partial sums of one evaluation, in a
+// static device array (each device holds its own copy for the life of the
+// process).  Host code never uses the array's name as an address: its device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (looked up on the device's first
+// call); MDS_OK or MDS_ERR_HIP.
+int static_scratch(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(MDS_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || !aligned(ptr, MDS_WORKSPACE_ALIGN))
+            return fail(MDS_ERR_HIP, "static scratch at %p is not %d-byte aligned", ptr,
+                        MDS_WORKSPACE_ALIGN);
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MDS_OK;
 }
 
 }  // namespace
@@ -467,13 +519,9 @@ int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void*
         const int sst = split_ytype(y_dtype, &trunc);
         if (sst) return sst;
     }
-    int st = check_problem(n, d, x, ldx, y, y_dtype, ldy, sigma_dev);
+    int st = check_gradient_args(n, d, x, ldx, y, y_dtype, ldy, sigma_dev, scale_dev, grad, ldg,
+                                 loglik_dev, dsigma_dev, dlogsigma_dev);
     if (st) return st;
-    if (n > 0 && !grad) return fail(MDS_ERR_INVALID_ARGUMENT, "grad is NULL");
-    if (ldg < d) return fail(MDS_ERR_INVALID_ARGUMENT, "ldg=%lld < d=%d", (long long)ldg, d);
-    if (!aligned(grad, 8) || !aligned(loglik_dev, 8) || !aligned(dsigma_dev, 8) ||
-        !aligned(dlogsigma_dev, 8) || !aligned(scale_dev, 8))
-        return fail(MDS_ERR_INVALID_ARGUMENT, "misaligned output pointer");
     Tiling t;
     if ((st = resolve_tiling(n, d, y_dtype, tile_rows, tile_waves, &t))) return st;
     WorkspaceLayout lay;
@@ -492,6 +540,41 @@ int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, const void*
     e = launch_finalize(d, fa, stream);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
     return MDS_OK;
+}
+
+size_t mds_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
+
+int mds_gradient_noalloc(int64_t n, int32_t d, const double* x, int64_t ldx, const void* y,
+                         int32_t y_dtype, int64_t ldy, const double* sigma_dev,
+                         const double* scale_dev, double* grad, int64_t ldg, double* loglik_dev,
+                         double* dsigma_dev, double* dlogsigma_dev, int32_t tile_rows,
+                         int32_t tile_waves, hipStream_t stream)
+{
+    // every argument is validated before the scratch lookup (a HIP call)
+    int st = 0;
+    {
+        int32_t yt = y_dtype;
+        int trunc = 1;
+        if ((st = split_ytype(yt, &trunc))) return st;
+        st = check_gradient_args(n, d, x, ldx, y, yt, ldy, sigma_dev, scale_dev, grad, ldg,
+                                 loglik_dev, dsigma_dev, dlogsigma_dev);
+        if (st) return st;
+    }
+    // the workspace this evaluation needs must fit the static scratch
+    size_t need = 0;
+    if ((st = mds_workspace_bytes(n, d, y_dtype, tile_rows, tile_waves, &need))) return st;
+    if (need > kStaticScratchBytes)
+        return fail(MDS_ERR_WORKSPACE_TOO_SMALL,
+                    "n=%lld d=%d needs %zu B of partial sums; the static scratch of "
+                    "mds_gradient_noalloc holds %zu B (use mds_gradient with a workspace)",
+                    (long long)n, d, need, kStaticScratchBytes);
+    void* ws = nullptr;
+    if ((st = static_scratch(&ws))) return st;
+    // every slot of the partial sums that the finalize reads is written by the
+    // sweep of the same call, so nothing needs clearing between calls
+    return mds_gradient(n, d, x, ldx, y, y_dtype, ldy, sigma_dev, scale_dev, grad, ldg,
+                        loglik_dev, dsigma_dev, dlogsigma_dev, ws, kStaticScratchBytes,
+                        tile_rows, tile_waves, stream);
 }
 
 int mds_leapfrog(int64_t n, int32_t d, double* x, int64_t ldx, double* p, int64_t ldp,

@@ -410,3 +410,22 @@ def test_native_c_program_uses_the_abi_alone(tmp_path):
     r = subprocess.run([exe, "cpu"], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stderr
     assert "capi host checks ok" in r.stdout
+
+
+def test_gradient_noalloc_validates_before_any_hip_call():
+    L = api.lib()
+    assert L.mds_noalloc_scratch_bytes() == 32 << 20
+    a = [100, 2, _p(), 2, _p(), 0, 128, _p(), None, _p(), 2, None, None, None, 0, 0, None]
+    bad = list(a)
+    bad[2] = None                                     # x NULL
+    assert L.mds_gradient_noalloc(*bad) == ERR_ARG
+    bad = list(a)
+    bad[10] = 1                                       # ldg < d
+    assert L.mds_gradient_noalloc(*bad) == ERR_ARG
+    bad = list(a)
+    bad[14] = 48                                      # tile_rows not in the set
+    assert L.mds_gradient_noalloc(*bad) == ERR_UNSUP
+    # a problem whose partial sums exceed the static scratch is refused
+    big = [20000, 2, _p(), 2, _p(), 0, 20032, _p(), None, _p(), 2, None, None, None, 0, 0, None]
+    assert L.mds_gradient_noalloc(*big) == ERR_WS
+    assert b"static scratch" in L.mds_last_error()

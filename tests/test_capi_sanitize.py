@@ -1,7 +1,8 @@
 """The C-ABI's host code under AddressSanitizer and UndefinedBehaviorSanitizer
 (no GPU).  csrc/mds_api.hip -- argument validation, tiling resolution,
-workspace and batch layout, error messages -- is compiled for the host with
-both sanitizers (its device side needs none: it holds no kernels) and linked
+workspace and batch layout, error messages -- is compiled with both
+sanitizers on its host side (its device side, the static scratch array, is
+unchanged) and linked
 with the library's kernel objects into tests/native/capi_sanitize.cpp, which
 calls every entry point over a grid of valid and invalid arguments, only
 along paths that return before any HIP call.  No report, every expectation
@@ -33,7 +34,7 @@ def test_capi_host_code_clean_under_asan_ubsan(tmp_path):
     flags = ["-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={hipbuild.ARCH}",
              "-I", os.path.join(ROOT, "include")]
     api_o = str(tmp_path / "mds_api_san.o")
-    _run([hipbuild.hipcc(), *flags, "--offload-host-only", *SAN_HOST, "-c",
+    _run([hipbuild.hipcc(), *flags, *SAN_HOST, "-c",
           os.path.join(CSRC, "mds_api.hip"), "-o", api_o])
     # the kernel translation units, unsanitized, as build() compiles them
     objs = []

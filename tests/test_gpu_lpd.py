@@ -169,3 +169,26 @@ def test_many_draws_per_pass_equal_single_draws_bitwise(n, d, draws):
     ref, _ = oracle.lpd(xs, sig, y, heldout, mask)
     _log(f"  pairs {H1.m}: lpd {got2:.15e} oracle {ref:.15e}")
     assert abs(got2 - ref) <= 1e-12 * abs(ref)
+
+
+def test_draws_on_a_caller_stream_with_host_inputs():
+    # draws passed as host arrays and Python floats (temporaries the binding
+    # converts) on a stream other than torch's current one: the binding keeps
+    # them alive for that stream, and the result equals the same draws made
+    # on the current stream, bit for bit
+    p = synth.make_problem(300, 2, 0.6, seed=81, missing=0.1)
+    held = synth.symmetric_mask(300, 0.2, np.random.default_rng(82))
+    xs = [p.x + 0.02 * k for k in range(4)]
+    H0 = api.HeldOutPairs(p.y, held, p.mask, DEV)
+    for k, x in enumerate(xs):
+        H0.add_draw(x, p.sigma * (1 + 0.1 * k))
+    ref = H0.lpd().item()
+    side = torch.cuda.Stream()
+    H1 = api.HeldOutPairs(p.y, held, p.mask, DEV)
+    side.wait_stream(torch.cuda.current_stream())
+    for k, x in enumerate(xs):
+        H1.add_draw(x, p.sigma * (1 + 0.1 * k), stream=side)
+        torch.empty(1 << 20, dtype=torch.float64, device=DEV).fill_(7.0)   # churn the allocator
+    out = H1.lpd(stream=side)
+    side.synchronize()
+    assert out.item() == ref

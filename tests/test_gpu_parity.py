@@ -138,8 +138,9 @@ def test_fp64_every_tiling(tile):
 @pytest.mark.parametrize("d", [1, 2, 5, 8])
 def test_row_waves(br, wc, wr, d):
     # the waves of a tile split its rows as well as its columns: every D, a
-    # ragged last row block, both precisions; the same partial sums as the
-    # single-row-wave tile, so the results are bitwise those of (br, wc)
+    # ragged last row block, both precisions (the row waves add their column
+    # sums in another order than one wave would, so the results match the
+    # single-row-wave tile to rounding, not bit for bit)
     x, y, mask, sigma = _rand(333, d, seed=60 + d, sigma=0.8)
     ref = oracle.evaluate(x, y, sigma, mask)
     tile = (br, api.tile_waves(wc, wr))
@@ -149,8 +150,6 @@ def test_row_waves(br, wc, wr, d):
         assert e.status == api.MDS_ERR_UNSUPPORTED, e   # the LDS budget of large tiles
         return
     check64(got, ref, f"tile={br}x{64 * wc} rows/wave={br // wr} d={d}")
-    one, _ = gpu_eval(y, x, sigma, mask, tile=(br, wc))
-    assert np.array_equal(one["grad"], got["grad"]) and one["loglik"] == got["loglik"]
     yf = y.astype(np.float32)
     g32, _ = gpu_eval(yf, x, sigma, mask, dtype=torch.float32, tile=tile)
     ref32 = oracle.evaluate(x, yf.astype(np.float64), sigma, mask)
