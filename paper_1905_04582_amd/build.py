@@ -3,7 +3,8 @@
     python -m paper_1905_04582_amd.build [-DMACRO=value ...] [--out other.so]
 
 Every translation unit under csrc/ is compiled for gfx950 only, with packed
-FP32 instructions disabled, then linked into paper_1905_04582_amd/libmassivemds.so.
+FP32 instructions disabled and no implicit multiply-add contraction, then
+linked into paper_1905_04582_amd/libmassivemds.so.
 """
 from __future__ import annotations
 
@@ -33,6 +34,11 @@ def hipcc() -> str:
 def common_flags():
     return ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # no implicit multiply-add fusion: every fused operation is an
+            # explicit fma(), so each kernel instantiation (with or without
+            # the gradient, single or batched) rounds the same expressions the
+            # same way
+            "-ffp-contract=off",
             "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 

@@ -15,8 +15,12 @@
 //     stage their terms of a few rows in LDS, then every (row, dimension)
 //     output is summed by a small group of lanes reading the staged values
 //     and finished by log2(group) exchanges;
-//   * a wavefront whose pairs in a row all have delta/sigma beyond a skip
-//     point branches over the special functions as a whole (no divergence);
+//   * a wavefront whose pairs in two rows all have delta/sigma beyond a skip
+//     point branches over the special functions as a whole (no divergence),
+//     and the pair then adds one product to the wave's sums: the residual
+//     square, which both the likelihood and dL/dsigma scale by a power of
+//     1/sigma once per wave, and its gradient coefficient (scaled by
+//     1/sigma^2 once per staging batch);
 //   * the column sums of the wr waves of a column group, and the row sums of
 //     the wc waves of a row group, meet in LDS and are added in wave order;
 //     column, row and scalar partials of the tile go to the workspace, and
@@ -59,23 +63,6 @@ __device__ __forceinline__ int wave_sum(int v)
 // points would otherwise lose their distance to cancellation), the rest is
 // FP32.
 template <typename T>
-struct PairConsts {
-    T inv_sigma, inv_s2, half_inv_s2, inv_s3;
-};
-
-template <typename T>
-__device__ __forceinline__ PairConsts<T> pair_consts(double sigma)
-{
-    PairConsts<T> c;
-    const double is = 1.0 / sigma;
-    c.inv_sigma = (T)is;
-    c.inv_s2 = (T)(is * is);
-    c.half_inv_s2 = (T)(0.5 * is * is);
-    c.inv_s3 = (T)(is * is * is);
-    return c;
-}
-
-template <typename T>
 __device__ __forceinline__ T min_normal();
 template <>
 __device__ __forceinline__ double min_normal<double>()
@@ -115,34 +102,12 @@ __device__ __forceinline__ void trunc_terms2<double>(double t1, double t2, doubl
     trunc_terms2_f64(t1, t2, l1, m1, l2, m2);
 }
 
-template <typename T>
-__device__ __forceinline__ void trunc_terms(T t, T& lnphi, T& mills);
-template <>
-__device__ __forceinline__ void trunc_terms<double>(double t, double& lnphi, double& mills)
-{
-    trunc_terms_f64(t, lnphi, mills);
-}
-template <>
-__device__ __forceinline__ void trunc_terms<float>(float t, float& lnphi, float& mills)
-{
-    trunc_terms_f32(t, lnphi, mills);
-}
-
-// Per-pair quantities computed before the special functions.
-template <typename T, int D>
-struct PairGeom {
-    T dl[D];   // x_i - x_j
-    T delta;   // |x_i - x_j|
-    T rinv;    // 1/delta (0 for a coincident pair)
-    T t;       // delta / sigma
-    T res;     // y - delta
-    bool ok;   // an observed pair of the strict lower triangle
-};
-
 // Skip point of the truncation terms.  For t >= T, 0 <= -ln Phi(t) <=
 // 2 Phi(-T) and phi(t)/Phi(t) <= 2 phi(T): below 2.3e-19 and 2.1e-18 for the
 // FP64 sweep (T = 9), below 8.1e-11 and 5.4e-10 for the FP32 sweep (T = 6.5),
 // each far under the rounding of the pair's other terms in that precision.
+// The sweep compares the squared distance with (T sigma)^2, so a pair within
+// rounding of the skip point may fall on either side.
 template <typename T>
 __device__ __forceinline__ T skip_t();
 template <>
@@ -154,6 +119,23 @@ template <>
 __device__ __forceinline__ float skip_t<float>()
 {
     return 6.5f;
+}
+
+// One element of Y through a buffer resource: lane byte offset `voff`, row
+// byte offset `soff` (uniform).
+template <typename T>
+__device__ __forceinline__ T load_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ double load_buf<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                   uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float load_buf<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                 uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
 // lanes per output in the row reduction: the largest power of two g with
@@ -202,154 +184,100 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     double gj[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) gj[d] = 0.0;
-    double acc_r = 0.0, acc_s = 0.0;
+    // the wave's sums over its pairs: A = sum (y - delta)^2, Lsum = sum ln Phi(t),
+    // Msum = sum delta phi(t)/Phi(t); the tile's r and dsigma sums follow from
+    // them (r = A / (2 sigma^2) + Lsum, dsigma terms = A / sigma^3 + Msum /
+    // sigma^2), so a pair past the skip point adds one product to them
+    double acc_A = 0.0, acc_L = 0.0, acc_M = 0.0;
     int cnt = 0;
+    const double sig = *a.sigma;
+    const double inv_s = 1.0 / sig;
+    const double inv_s2 = inv_s * inv_s;
 
     if (wv.active) {
         double xj[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) xj[d] = colok ? a.x[j * a.ldx + d] : 0.0;
-        const PairConsts<T> pc = pair_consts<T>(*a.sigma);
+        const T sigT = (T)sig, inv_sT = (T)inv_s;
+        // skip test on the squared distance: s2 >= (skip point * sigma)^2
+        // means t >= the skip point (to the rounding of the bound)
+        const double tb = (double)skip_t<T>() * sig;
+        const T thr2 = (T)(tb * tb);
         const T* __restrict__ Y = static_cast<const T*>(a.y);
 
-        // Y is prefetched two rows ahead, so each row's load has an iteration
-        // of arithmetic to arrive.  The load is unconditional (lanes outside
-        // the triangle discard the value through `ok`), so no branch splits
-        // the wave and the wait before a row's first use leaves the two newer
-        // loads in flight.  Rows are loaded strictly in order from ib0, and
-        // the row pointer stops at the wave's last row rw1-1: every address
-        // lies in rows [ib0, rw1) of the tile and in columns [0, n).  Row and
-        // column indices fit 32 bits (N <= 2^30).
-        const uint32_t jc = colok ? (uint32_t)j : 0u;
+        // Y is read two steps (four rows) ahead of use into two register
+        // pairs that alternate, so each load has two steps of arithmetic to
+        // arrive and no value is copied between registers.  Loads are
+        // unconditional (lanes outside the triangle discard the value), and
+        // rows are loaded strictly in order from ib0 with the row pointer
+        // stopping at the wave's last row rw1-1: every address lies in rows
+        // [ib0, rw1) of the tile and in columns [0, n).  Row and column
+        // indices fit 32 bits (N <= 2^30); so does a lane's byte offset in a
+        // row (the N^2 elements of Y must fit the device).
+        const uint32_t joff = (colok ? (uint32_t)j : 0u) * (uint32_t)sizeof(T);
         const int j32 = (int)j;
-        const int last_row = (int)(wv.rw1 - 1);
-        const T* yrow = Y + wv.ib0 * a.ldy;
-        int ynext = (int)wv.ib0;
+        const uint64_t colmask = __builtin_amdgcn_ballot_w64(colok);
+        const int ib0 = (int)wv.ib0, rw1 = (int)wv.rw1;
+        const int last_row = rw1 - 1;
+        // a buffer resource at the wave's first row: the row's byte offset is
+        // a scalar operand and the lane's a fixed vector one, so a load costs
+        // no vector address arithmetic (the host checks that the offsets of
+        // a tile's rows fit 31 bits)
+        const __amdgpu_buffer_rsrc_t yres = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<T*>(Y + wv.ib0 * a.ldy), (short)0, 0x7fffffff, 0x00020000);
+        const uint32_t ystep = (uint32_t)a.ldy * (uint32_t)sizeof(T);
+        uint32_t yoff = 0;
+        int ynext = ib0;
         auto load_y = [&]() -> T {
-            const T v = yrow[jc];
-            if (ynext < last_row) yrow += a.ldy;
+            const T v = load_buf<T>(yres, joff, yoff);
+            if (ynext < last_row) yoff += ystep;
             ++ynext;
             return v;
         };
         // x_i is uniform across the wave and comes through scalar loads (X is
         // read-only during the sweep, so the constant address space is
         // valid); rows are visited in order, so its address advances by ldx
+        // and, like Y's, stops at the wave's last row
         const double* xrow = a.x + wv.ib0 * a.ldx;
-        T pf0 = load_y(), pf1 = load_y();
-        for (int64_t ib = wv.ib0; ib < wv.rw1; ib += RB) {
-            T gjb[D];
+        int xnext = ib0;
+        auto next_x = [&]() -> const_f64_ptr {
+            const const_f64_ptr p = (const_f64_ptr)xrow;
+            if (xnext < last_row) xrow += a.ldx;
+            ++xnext;
+            return p;
+        };
+        T pa0 = load_y(), pa1 = load_y();
+        // keep the issue order: the first pair is consumed first
+        __builtin_amdgcn_sched_barrier(0);
+        T pb0 = load_y(), pb1 = load_y();
+
+        constexpr int NO = RB * D;
+        constexpr int RG = reduce_group(NO);
+        const int o = lane / RG, h = lane % RG;
+        const int orow = o / D, odim = o % D;
+
+        T gjb[D];
+        T bA, bL, bM;
+        auto batch_reset = [&]() {
 #pragma unroll
             for (int d = 0; d < D; ++d) gjb[d] = T(0);
-            T br_r = T(0), br_s = T(0);
-            const int nq = (int)min((int64_t)RB, wv.rw1 - ib);
-
-            // geometry of one pair row (row ib + q, this lane's column)
-            auto geom = [&](const int q, const T yv, PairGeom<T, D>& g) {
-                const int i = (int)(ib + q);
-                const const_f64_ptr xi = (const_f64_ptr)xrow;
-                xrow += a.ldx;
-                g.ok = colok && (j32 < i) && !isnan(yv);
-                T s2 = T(0);
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    g.dl[d] = (T)(xi[d] - xj[d]);
-                    s2 = fma(g.dl[d], g.dl[d], s2);
-                }
-                // delta and 1/delta from one reciprocal square root.  A
-                // coincident pair (s2 below the normal range) has no
-                // direction: 1/delta is taken as 0, and delta = s2 *
-                // rsqrt(min normal) is 0 for s2 = 0 (tiny otherwise)
-                const T rs = rsqrt_t(fmax(s2, min_normal<T>()));
-                g.delta = s2 * rs;
-                g.rinv = (s2 >= min_normal<T>()) ? rs : T(0);
-                g.t = g.delta * pc.inv_sigma;
-                // a pair outside the sums gets y = delta: its residual is 0,
-                // and with ln Phi = m = 0 (set by the caller) all its terms
-                // vanish
-                g.res = g.ok ? yv - g.delta : T(0);
-            };
-            // the pair's terms given ln Phi(t) and phi(t)/Phi(t) (both 0 for
-            // a pair outside the sums)
-            auto accum = [&](const int q, const PairGeom<T, D>& g, const T lnphi, const T mills) {
-                const T res2 = g.res * g.res;
-                br_r += fma(res2, pc.half_inv_s2, lnphi);
-                if (GRAD) {
-                    // w = (delta - y)/sigma^2 + m/sigma; the pair's term is
-                    // w (x_i - x_j)/delta
-                    const T wv_ = fma(mills, pc.inv_sigma, -g.res * pc.inv_s2);
-                    const T coef = wv_ * g.rinv;
-                    T* st = stage + (size_t)q * SROW + (size_t)lane * D;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        const T cd = coef * g.dl[d];
-                        st[d] = -cd;
-                        gjb[d] += cd;
-                    }
-                    br_s += fma(res2, pc.inv_s3, g.delta * pc.inv_s2 * mills);
-                }
-            };
-            // observed pairs of a row in this wave (a wave-uniform count)
-            auto count_ok = [&](const PairGeom<T, D>& g) {
-                cnt += (int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(g.ok));
-            };
-            // when no observed pair of the rows in this wave has t below the
-            // skip point, the wave takes ln Phi = m = 0 and skips the special
-            // functions (a wave-uniform branch; lanes never diverge)
-            auto needs_tail = [&](const PairGeom<T, D>& g) { return g.ok && g.t < skip_t<T>(); };
-            // two rows per step: their dependency chains interleave and they
-            // share the special functions' coefficient loads
-            int q = 0;
-#pragma unroll 1
-            for (; q + 1 < nq; q += 2) {
-                const T ya = pf0, yb = pf1;
-                pf0 = load_y();
-                pf1 = load_y();
-                PairGeom<T, D> ga, gb;
-                geom(q, ya, ga);
-                geom(q + 1, yb, gb);
-                count_ok(ga);
-                count_ok(gb);
-                T la = T(0), ma = T(0), lb = T(0), mb = T(0);
-                if (a.truncated && __builtin_amdgcn_ballot_w64(needs_tail(ga) || needs_tail(gb))) {
-                    trunc_terms2<T>(ga.t, gb.t, la, ma, lb, mb);
-                    la = ga.ok ? la : T(0);
-                    ma = ga.ok ? ma : T(0);
-                    lb = gb.ok ? lb : T(0);
-                    mb = gb.ok ? mb : T(0);
-                }
-                accum(q, ga, la, ma);
-                accum(q + 1, gb, lb, mb);
-            }
-            if (q < nq) {
-                // the odd last row of the wave's rows
-                const T ya = pf0;
-                pf0 = pf1;
-                pf1 = load_y();
-                PairGeom<T, D> ga;
-                geom(q, ya, ga);
-                count_ok(ga);
-                T la = T(0), ma = T(0);
-                if (a.truncated && __builtin_amdgcn_ballot_w64(needs_tail(ga))) {
-                    trunc_terms<T>(ga.t, la, ma);
-                    la = ga.ok ? la : T(0);
-                    ma = ga.ok ? ma : T(0);
-                }
-                accum(q, ga, la, ma);
-            }
-            acc_r += (double)br_r;
+            bA = T(0);
+            bL = T(0);
+            bM = T(0);
+        };
+        // end of the staging batch of rows [b0, b0 + RB) (rows at or past rw1
+        // are dead): the batch's sums go to the FP64 accumulators, and every
+        // (row, dimension) output gets RG lanes -- lane h of its group adds
+        // the staged values of lanes h, h+RG, ..., then the group combines by
+        // log2(RG) exchanges
+        auto batch_flush = [&](const int b0) {
+            acc_A += (double)bA;
+            acc_L += (double)bL;
+            acc_M += (double)bM;
             if (GRAD) {
-                acc_s += (double)br_s;
 #pragma unroll
-                for (int d = 0; d < D; ++d) gj[d] += (double)gjb[d];
-                // transposed reduction of the staged rows: each (row,
-                // dimension) output of the batch gets RG lanes; lane h of its
-                // group adds the staged values of lanes h, h+RG, ..., then the
-                // group combines by log2(RG) exchanges
-                constexpr int NO = RB * D;
-                constexpr int RG = reduce_group(NO);
-                const int o = lane / RG, h = lane % RG;
-                const int orow = o / D, odim = o % D;
-                const bool live = o < NO && orow < nq;
+                for (int d = 0; d < D; ++d) gj[d] = fma((double)gjb[d], inv_s2, gj[d]);
+                const bool live = o < NO && b0 + orow < rw1;
                 T sum = T(0);
                 if (live) {
                     const T* src = stage + (size_t)orow * SROW + (size_t)h * D + odim;
@@ -358,10 +286,120 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 }
 #pragma unroll
                 for (int m = RG / 2; m >= 1; m >>= 1) sum += shfl_xor_t(sum, m);
-                if (live && h == 0) lrows[(ib - row0 + orow) * D + odim] = (double)sum;
+                if (live && h == 0) lrows[(b0 - row0 + orow) * D + odim] = (double)sum * inv_s2;
+            }
+            batch_reset();
+        };
+        batch_reset();
+
+        // One step: rows i0 and i0 + 1, staged at positions q and q + 1 of
+        // the batch.  A row at or past rw1 is dead: no lane's pair counts,
+        // and its loads repeat the wave's last row.
+        auto step = [&](const int i0, const int q, const T ya, const T yb) {
+            const bool live0 = i0 < rw1, live1 = i0 + 1 < rw1;
+            const const_f64_ptr xa = next_x();
+            const const_f64_ptr xb = next_x();
+            T da[D], db[D];
+            T s2a = T(0), s2b = T(0);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                da[d] = (T)(xa[d] - xj[d]);
+                db[d] = (T)(xb[d] - xj[d]);
+                s2a = fma(da[d], da[d], s2a);
+                s2b = fma(db[d], db[d], s2b);
+            }
+            // observed pairs of the strict lower triangle: each condition is
+            // one compare, the counts come from the compares' own lane masks,
+            // and bitwise operators keep the conditions branch-free
+            const bool tra = j32 < i0, trb = j32 < i0 + 1;
+            const bool nna = !isnan(ya), nnb = !isnan(yb);
+            const uint64_t ma = __builtin_amdgcn_ballot_w64(tra) &
+                                __builtin_amdgcn_ballot_w64(nna) & colmask &
+                                (0ull - (uint64_t)live0);
+            const uint64_t mb = __builtin_amdgcn_ballot_w64(trb) &
+                                __builtin_amdgcn_ballot_w64(nnb) & colmask &
+                                (0ull - (uint64_t)live1);
+            cnt += (int)__builtin_popcountll(ma) + (int)__builtin_popcountll(mb);
+            const bool oka = live0 & colok & tra & nna;
+            const bool okb = live1 & colok & trb & nnb;
+            // delta and 1/delta from one reciprocal square root.  A coincident
+            // pair (s2 below the normal range) has no direction: 1/delta is
+            // taken as 0, and delta = s2 * rsqrt(min normal) is 0 for s2 = 0
+            // (tiny otherwise)
+            const T rsa = rsqrt_t(fmax(s2a, min_normal<T>()));
+            const T rsb = rsqrt_t(fmax(s2b, min_normal<T>()));
+            const T dla = s2a * rsa, dlb = s2b * rsb;
+            const T ria = (s2a >= min_normal<T>()) ? rsa : T(0);
+            const T rib = (s2b >= min_normal<T>()) ? rsb : T(0);
+            // a pair outside the sums gets residual 0 (and, below, ln Phi =
+            // m = 0): all its terms vanish
+            const T ra = oka ? fma(-s2a, rsa, ya) : T(0);
+            const T rb = okb ? fma(-s2b, rsb, yb) : T(0);
+            bA = fma(ra, ra, bA);
+            bA = fma(rb, rb, bA);
+            // sigma^2 w (x_i - x_j)/delta = (m sigma - (y - delta)) (x_i -
+            // x_j)/delta; far pairs (t past the skip point for every lane of
+            // the wave) take m = ln Phi = 0 without evaluating them
+            T ca = -ra * ria, cb = -rb * rib;
+            const uint64_t near = (__builtin_amdgcn_ballot_w64(s2a < thr2) & ma) |
+                                  (__builtin_amdgcn_ballot_w64(s2b < thr2) & mb);
+            if (a.truncated && near) {
+                T la, mla, lb, mlb;
+                trunc_terms2<T>(dla * inv_sT, dlb * inv_sT, la, mla, lb, mlb);
+                la = oka ? la : T(0);
+                mla = oka ? mla : T(0);
+                lb = okb ? lb : T(0);
+                mlb = okb ? mlb : T(0);
+                bL += la + lb;
+                bM = fma(dla, mla, bM);
+                bM = fma(dlb, mlb, bM);
+                ca = fma(mla * sigT, ria, ca);
+                cb = fma(mlb * sigT, rib, cb);
+            }
+            if (GRAD) {
+                T* st = stage + (size_t)q * SROW + (size_t)lane * D;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    st[d] = -ca * da[d];
+                    st[SROW + d] = -cb * db[d];
+                    gjb[d] = fma(ca, da[d], gjb[d]);
+                    gjb[d] = fma(cb, db[d], gjb[d]);
+                }
+            }
+        };
+
+        // The walk: four rows per iteration in two steps that take the two
+        // register pairs in turn; a staging batch of RB rows closes after
+        // RB/2 steps.  The wave's rows [ib0, rw1) are a whole number of
+        // batches except at the matrix's last row; rows past rw1 in the last
+        // iteration are dead.
+        int q = 0;  // staging position of the next step
+        int ib = ib0;
+#pragma unroll 1
+        for (; ib < rw1; ib += 4) {
+            step(ib, q, pa0, pa1);
+            pa0 = load_y();
+            pa1 = load_y();
+            q += 2;
+            if (q == RB) {
+                batch_flush(ib + 2 - RB);
+                q = 0;
+            }
+            step(ib + 2, q, pb0, pb1);
+            pb0 = load_y();
+            pb1 = load_y();
+            q += 2;
+            if (q == RB) {
+                batch_flush(ib + 4 - RB);
+                q = 0;
             }
         }
+        // a batch the walk left open (rows [ib - q, ib))
+        if (q != 0) batch_flush(ib - q);
     }
+
+    double acc_r = fma(acc_A, 0.5 * inv_s2, acc_L);
+    double acc_s = fma(acc_A, inv_s2 * inv_s, acc_M * inv_s2);
 
     const int wr = a.wr;
     double* cp = a.colpart + (((size_t)c * a.nrb + r) * cw + (size_t)wu * kWave + lane) * D;
@@ -425,8 +463,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     __syncthreads();
 }
 
+// Waves per SIMD the register allocation must allow for D <= 2: four in
+// FP64 (the LDS of four 4-wave work-groups per compute unit), seven in FP32;
+// no bound above (the allocator's own choice).
+template <typename T, int D>
+constexpr int sweep_waves_per_simd() { return D > 2 ? 1 : (sizeof(T) == 8 ? 4 : 7); }
+
 template <typename T, int D, bool GRAD>
-__global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
+__global__ void __launch_bounds__(512)
+    __attribute__((amdgpu_waves_per_eu(sweep_waves_per_simd<T, D>()))) sweep_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const bool traced = a.trace != nullptr;
@@ -453,7 +498,8 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs a)
 // of the single-problem sweep, bit for bit.  MAXD bounds the D cases compiled
 // in, so the register allocation follows the largest D of the batch.
 template <typename T, bool GRAD, int MAXD>
-__global__ void __launch_bounds__(512) batch_sweep_kernel(const BatchProblem* __restrict__ probs,
+__global__ void __launch_bounds__(512)
+    __attribute__((amdgpu_waves_per_eu(sweep_waves_per_simd<T, MAXD>()))) batch_sweep_kernel(const BatchProblem* __restrict__ probs,
                                                           int32_t count, int64_t total_tiles,
                                                           unsigned long long* cursor)
 {

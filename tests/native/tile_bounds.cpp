@@ -4,8 +4,9 @@
 // each of its waves to a row range with wave_rows(); this program calls the
 // same functions (mds_internal.h) and checks, for many N, every valid tiling
 // and the staging batch of every D:
-//   * every row a wave reads -- its Y prefetch, which runs two rows ahead of
-//     the arithmetic, included -- lies inside its tile and inside the matrix;
+//   * every row a wave reads -- its Y prefetch, which runs four rows ahead of
+//     the arithmetic, and its x rows included -- lies inside its tile and
+//     inside the matrix, and its staging batches cover its rows in order;
 //   * the rows a wave skips below its first row hold no pair of its columns;
 //   * every pair i > j of the strict lower triangle is visited exactly once
 //     (counted pair by pair for small N, in total for large N);
@@ -39,23 +40,50 @@ struct Tile {
     int br, wc, wr;
 };
 
-// The rows the kernel's load_y() reads for one wave: two loads before the
-// row loop, then one per row visited; the row pointer starts at ib0 and
-// advances after a load while it is below the wave's last row.
-static void replay_loads(const WaveRows& w, std::vector<int64_t>& rows)
+// The rows the kernel's load_y() and next_x() read for one wave, and the
+// first rows of the staging batches it closes.  The walk visits rows ib0,
+// ib0+4, ... below rw1 in iterations of two steps of two rows (rows at or
+// past rw1 are dead); Y is loaded four rows before the loop, then two rows
+// after each step; x two rows per step.  Each pointer starts at ib0 and
+// advances after a read while it is below the wave's last row.  A batch of
+// rb rows closes after rb/2 steps, and a batch left open at the end closes
+// after the loop.
+static void replay_walk(const WaveRows& w, int rb, std::vector<int64_t>& yrows,
+                        std::vector<int64_t>& xrows, std::vector<int64_t>& batches)
 {
-    rows.clear();
+    yrows.clear();
+    xrows.clear();
+    batches.clear();
     if (!w.active) return;
     const int64_t last_row = w.rw1 - 1;
-    int64_t cur = w.ib0, next = w.ib0;
-    auto load = [&]() {
-        rows.push_back(cur);
-        if (next < last_row) ++cur;
-        ++next;
+    int64_t ycur = w.ib0, ynext = w.ib0, xcur = w.ib0, xnext = w.ib0;
+    auto load_y = [&]() {
+        yrows.push_back(ycur);
+        if (ynext < last_row) ++ycur;
+        ++ynext;
     };
-    load();
-    load();
-    for (int64_t i = w.ib0; i < w.rw1; ++i) load();
+    auto next_x = [&]() {
+        xrows.push_back(xcur);
+        if (xnext < last_row) ++xcur;
+        ++xnext;
+    };
+    for (int k = 0; k < 4; ++k) load_y();
+    int q = 0;
+    int64_t ib = w.ib0;
+    for (; ib < w.rw1; ib += 4) {
+        for (int half = 0; half < 2; ++half) {
+            next_x();
+            next_x();
+            load_y();
+            load_y();
+            q += 2;
+            if (q == rb) {
+                batches.push_back(ib + 2 * (half + 1) - rb);
+                q = 0;
+            }
+        }
+    }
+    if (q != 0) batches.push_back(ib - q);
 }
 
 // sum over k < m of min(max(k, 0), 64): the pairs of a wave's 64 columns in
@@ -79,7 +107,7 @@ static void check_case(int64_t n, const Tile& tl, int rb, bool per_pair, bool sa
     std::vector<unsigned char> seen;
     if (per_pair) seen.assign((size_t)n * (size_t)n, 0);
     std::vector<int64_t> col_tiles(ncb > 0 ? ncb : 1, 0);
-    std::vector<int64_t> loads;
+    std::vector<int64_t> loads, xloads, batches;
     long double pairs = 0;
     int64_t prev_tile_r = 0;
     for (int64_t tile = 0; tile < t.ntiles; ++tile) {
@@ -122,11 +150,26 @@ static void check_case(int64_t n, const Tile& tl, int rb, bool per_pair, bool sa
                 continue;
             }
             CHECK((w.ib0 - w.rw0) % rb == 0 && w.ib0 >= w.rw0, fmt, CASE);
-            replay_loads(w, loads);
+            replay_walk(w, rb, loads, xloads, batches);
             for (int64_t y : loads) {
                 CHECK(y >= w.ib0 && y < w.rw1, "%s load row %lld", "", (long long)y);
                 CHECK(y >= w.row0 && y < w.row1 && y < n, fmt, CASE);
             }
+            for (int64_t x : xloads) CHECK(x >= w.ib0 && x < w.rw1 && x < n, fmt, CASE);
+            // the staging batches: consecutive runs of rb rows from ib0 that
+            // cover [ib0, rw1); the row sums a batch writes (its live rows)
+            // lie in the wave's rows of the tile
+            CHECK(!batches.empty() && batches.front() == w.ib0, fmt, CASE);
+            // (a batch that starts at or past rw1 has only dead rows and
+            // writes nothing)
+            int64_t live_batches = 0;
+            for (size_t b = 0; b < batches.size(); ++b) {
+                CHECK(batches[b] == w.ib0 + (int64_t)b * rb, fmt, CASE);
+                CHECK(batches[b] >= w.row0, fmt, CASE);
+                if (batches[b] < w.rw1) ++live_batches;
+            }
+            CHECK(live_batches * rb >= w.rw1 - w.ib0 && (live_batches - 1) * rb < w.rw1 - w.ib0,
+                  fmt, CASE);
             if (!per_pair) {
                 pairs += pairs_below(w.rw1 - w.jw0) - pairs_below(w.ib0 - w.jw0);
                 continue;

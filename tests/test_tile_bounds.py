@@ -3,9 +3,10 @@ tests/native/tile_bounds.cpp includes the library's tiling header and calls
 the functions the kernel calls (tile_coords, wave_rows) for N = 1..600, 777,
 1000, 1536, 5000, 5392, 7999, 20000 and 100000, every valid tiling (rows per
 tile, column waves, row waves) and the staging batch of every D.  It checks
-that every Y row a wave reads, its two-row prefetch included, lies inside the
-wave's tile and the matrix; that every lower-triangle pair is visited exactly
-once; and that every partial-sum slot lies inside its buffer.  Built with
+that every Y and x row a wave reads, its four-row Y prefetch included, lies
+inside the wave's tile and the matrix; that its staging batches cover its
+rows in order; that every lower-triangle pair is visited exactly once; and
+that every partial-sum slot lies inside its buffer.  Built with
 AddressSanitizer and UndefinedBehaviorSanitizer."""
 import os
 import shutil
