@@ -129,13 +129,14 @@ def fmt(v, dt):
 
 
 def emit_array(name, vals, dt):
-    # FP64 tables live in constant memory: VOP3 instructions on gfx950 take no
-    # 64-bit literal, but they do take a scalar-register operand, so uniform
-    # loads of the table let every Horner step be one v_fma_f64.  FP32
-    # coefficients fit the 32-bit literal field and stay compile-time constants.
+    # FP64 tables end up in constant memory (mds_math.h gathers them into one
+    # object): VOP3 instructions on gfx950 take no 64-bit literal, but they do
+    # take a scalar-register operand, so uniform loads of the table let every
+    # Horner step be one v_fma_f64.  FP32 coefficients fit the 32-bit literal
+    # field and stay compile-time constants.
     body = ",\n    ".join(fmt(v, dt) for v in vals)
     if dt is np.float64:
-        return f"static __constant__ double {name}[{len(vals)}] = {{\n    {body}}};\n"
+        return f"constexpr double {name}[{len(vals)}] = {{\n    {body}}};\n"
     return f"constexpr float {name}[{len(vals)}] = {{\n    {body}}};\n"
 
 

@@ -189,10 +189,11 @@ int check_problem(int64_t n, int32_t d, const double* x, int64_t ldx, const void
     if (n > 1 && !y) return fail(MDS_ERR_INVALID_ARGUMENT, "y is NULL");
     if (n > 0 && ldy < n)
         return fail(MDS_ERR_INVALID_ARGUMENT, "ldy=%lld < n=%lld", (long long)ldy, (long long)n);
-    // a wave addresses the rows of one tile (at most 256) by 32-bit byte
-    // offsets from its first row; 257 rows of Y must span less than 2^31
-    // bytes (ldy below about 10^6 elements: far beyond any Y that fits a GPU)
-    if (n > 1 && ldy > (((int64_t)1 << 31) - 1) / (257 * (int64_t)dtype_size(y_dtype)))
+    // a wave addresses the rows of its tile (at most 256) and the four rows
+    // after them by 32-bit byte offsets from its first row; 261 rows of Y
+    // must span less than 2^31 bytes (ldy below about 10^6 elements: far
+    // beyond any Y that fits a GPU)
+    if (n > 1 && ldy > (((int64_t)1 << 31) - 1) / (261 * (int64_t)dtype_size(y_dtype)))
         return fail(MDS_ERR_UNSUPPORTED, "ldy=%lld: rows of Y too long for 32-bit offsets",
                     (long long)ldy);
     if (!sigma_dev) return fail(MDS_ERR_INVALID_ARGUMENT, "sigma_dev is NULL");

@@ -76,7 +76,7 @@ __device__ void block_sum3(double& a, double& b, double& c)
 // elements per wave: coalesced reads), and wave 0 adds the kFinChunks chunk
 // sums in chunk order.  Every order is fixed, so the result is reproducible.
 constexpr int kFinChunks = 8;
-constexpr int kFinUnroll = 8;  // partial loads in flight per lane
+constexpr int kFinUnroll = 16;  // partial loads in flight per lane
 
 // The scalar part: L, dL/dsigma and dL/d(ln sigma) from the per-tile sums,
 // by one work-group of kWave * kFinChunks threads in a fixed order: thread t
@@ -88,26 +88,25 @@ __device__ void finalize_scalars(const FinalizeArgs& a, double scale)
     __shared__ double s[3][kFinChunks];
     const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
     double sr = 0.0, ss = 0.0, sm = 0.0;
-    int64_t u = t;
-    for (; u + (kFinUnroll - 1) * T < a.ntiles; u += kFinUnroll * T) {
+    // batches of kFinUnroll tiles, each batch's loads issued together (index
+    // clamped into the list, a tile past the end replaced by 0)
+    const int64_t last = a.ntiles - 1;
+    for (int64_t u = t; u < a.ntiles; u += kFinUnroll * T) {
         double r[kFinUnroll], q[kFinUnroll], c[kFinUnroll];
 #pragma unroll
         for (int k = 0; k < kFinUnroll; ++k) {
-            r[k] = a.tscal[2 * (u + k * T) + 0];
-            q[k] = a.tscal[2 * (u + k * T) + 1];
-            c[k] = (double)a.tcount[u + k * T];
+            const int64_t v = min(u + (int64_t)k * T, last);
+            r[k] = a.tscal[2 * v + 0];
+            q[k] = a.tscal[2 * v + 1];
+            c[k] = (double)a.tcount[v];
         }
 #pragma unroll
         for (int k = 0; k < kFinUnroll; ++k) {
-            sr += r[k];
-            ss += q[k];
-            sm += c[k];
+            const bool in = u + (int64_t)k * T < a.ntiles;
+            sr += in ? r[k] : 0.0;
+            ss += in ? q[k] : 0.0;
+            sm += in ? c[k] : 0.0;
         }
-    }
-    for (; u < a.ntiles; u += T) {
-        sr += a.tscal[2 * u + 0];
-        ss += a.tscal[2 * u + 1];
-        sm += (double)a.tcount[u];
     }
 #pragma unroll
     for (int m = kWave / 2; m >= 1; m >>= 1) {

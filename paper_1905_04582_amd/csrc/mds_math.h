@@ -48,17 +48,46 @@ __device__ __forceinline__ double fma_sc(double acc, double x, double c)
     return r;
 }
 
-// Horner's rule over a coefficient table in constant memory.  The empty asm
-// hides the table's identity from the optimiser, so the coefficients are
-// fetched by uniform scalar loads (s_load) instead of being folded into
-// immediates, which a 64-bit VALU operand cannot encode.
-typedef const __attribute__((address_space(4))) double* const_f64_ptr;
+// The FP64 coefficient tables in one constant-memory object, so that one
+// scalar base address reaches every coefficient by an immediate offset.
+struct CoefTables64 {
+    double exp[sizeof(kExpC64) / sizeof(double)];
+    double erfcx_p[sizeof(kErfcxP64) / sizeof(double)];
+    double erfcx_q[sizeof(kErfcxQ64) / sizeof(double)];
+    double atanh[sizeof(kAtanhA64) / sizeof(double)];
+};
 
-template <int N>
-__device__ __forceinline__ double horner_tab(const double (&tab)[N], double x)
+constexpr CoefTables64 make_tables64()
 {
-    const_f64_ptr c = (const_f64_ptr)tab;
-    asm volatile("" : "+s"(c));
+    CoefTables64 t{};
+    for (size_t k = 0; k < sizeof(kExpC64) / sizeof(double); ++k) t.exp[k] = kExpC64[k];
+    for (size_t k = 0; k < sizeof(kErfcxP64) / sizeof(double); ++k) t.erfcx_p[k] = kErfcxP64[k];
+    for (size_t k = 0; k < sizeof(kErfcxQ64) / sizeof(double); ++k) t.erfcx_q[k] = kErfcxQ64[k];
+    for (size_t k = 0; k < sizeof(kAtanhA64) / sizeof(double); ++k) t.atanh[k] = kAtanhA64[k];
+    return t;
+}
+
+static __constant__ CoefTables64 kTab64 = make_tables64();
+
+typedef const __attribute__((address_space(4))) double* const_f64_ptr;
+typedef const __attribute__((address_space(4))) CoefTables64* tab64_ptr;
+
+// The tables' address, hidden from the optimiser by an empty asm: the
+// coefficients are then fetched by uniform scalar loads (s_load) instead of
+// being folded into immediates, which a 64-bit VALU operand cannot encode.
+// A caller that evaluates the special functions in a loop takes the address
+// once and passes it in.
+__device__ __forceinline__ tab64_ptr tab64()
+{
+    tab64_ptr p = (tab64_ptr)&kTab64;
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Horner's rule over a table of N coefficients in constant memory.
+template <int N>
+__device__ __forceinline__ double horner_tab(const_f64_ptr c, double x)
+{
     double acc = fma_sc(c[N - 1], x, c[N - 2]);
 #pragma unroll
     for (int k = N - 3; k >= 0; --k) acc = fma_sc(acc, x, c[k]);
@@ -68,11 +97,9 @@ __device__ __forceinline__ double horner_tab(const double (&tab)[N], double x)
 // Horner's rule for two arguments at once: each coefficient is loaded once
 // and feeds both chains (two independent dependency chains interleave).
 template <int N>
-__device__ __forceinline__ void horner2_tab(const double (&tab)[N], double x1, double x2,
-                                            double& r1, double& r2)
+__device__ __forceinline__ void horner2_tab(const_f64_ptr c, double x1, double x2, double& r1,
+                                            double& r2)
 {
-    const_f64_ptr c = (const_f64_ptr)tab;
-    asm volatile("" : "+s"(c));
     double a1 = fma_sc(c[N - 1], x1, c[N - 2]);
     double a2 = fma_sc(c[N - 1], x2, c[N - 2]);
 #pragma unroll
@@ -107,36 +134,44 @@ __device__ __forceinline__ double rsqrt_f64(double x)
     return fma(r, fma(-hx, r * r, 0.5), r);
 }
 
+constexpr int kExpN = sizeof(kExpC64) / sizeof(double);
+constexpr int kErfcxPN = sizeof(kErfcxP64) / sizeof(double);
+constexpr int kErfcxQN = sizeof(kErfcxQ64) / sizeof(double);
+constexpr int kAtanhN = sizeof(kAtanhA64) / sizeof(double);
+
 // exp(-t^2/2) for t >= 0; 0 once the value leaves the FP64 range
-__device__ __forceinline__ double exp_neg_half_sq(double t)
+__device__ __forceinline__ double exp_neg_half_sq(double t, tab64_ptr tb)
 {
     const double x = fmax(-0.5 * (t * t), -760.0);
     const double k = rint(x * kLog2e);
     double r = fma(k, -kLn2Head, x);
     r = fma(k, -kLn2Tail, r);
-    return ldexp(horner_tab(kExpC64, r), (int)k);
+    return ldexp(horner_tab<kExpN>(tb->exp, r), (int)k);
 }
 
 // ln Phi(t) and phi(t)/Phi(t) for t >= 0 (the sweep's domain)
 __device__ __forceinline__ void trunc_terms_f64(double t, double& lnphi, double& mills)
 {
-    const double e = exp_neg_half_sq(t);
+    const tab64_ptr tb = tab64();
+    const double e = exp_neg_half_sq(t, tb);
     // beyond the fitted range e == 0, so any finite positive erfcx will do
     const double z = fmin(t * kInvSqrt2, kErfcxZmax64 + 1.0);
-    const double P = horner_tab(kErfcxP64, z);
-    const double Q = horner_tab(kErfcxQ64, z);
+    const double P = horner_tab<kErfcxPN>(tb->erfcx_p, z);
+    const double Q = horner_tab<kErfcxQN>(tb->erfcx_q, z);
     const double a = e * P;               // 2 q Q
     const double d1 = fma(4.0, Q, -a);    // 4Q - a   = 2Q (2 - q)
     const double d2 = d1 - a;             // 4Q - 2a  = 4Q (1 - q)
     const double rr = rcp_f64(d1 * d2);
     const double s = a * d2 * rr;         // q / (2 - q)
-    lnphi = -2.0 * s * horner_tab(kAtanhA64, s * s);
+    lnphi = -2.0 * s * horner_tab<kAtanhN>(tb->atanh, s * s);
     mills = (4.0 * kInvSqrt2Pi) * (e * Q) * (d1 * rr);
 }
 
-// trunc_terms_f64 for two arguments, sharing every coefficient load
+// trunc_terms_f64 for two arguments, sharing every coefficient load; `tb`
+// is the tables' address (tab64())
 __device__ __forceinline__ void trunc_terms2_f64(double t1, double t2, double& lnphi1,
-                                                 double& mills1, double& lnphi2, double& mills2)
+                                                 double& mills1, double& lnphi2, double& mills2,
+                                                 tab64_ptr tb)
 {
     const double x1 = fmax(-0.5 * (t1 * t1), -760.0);
     const double x2 = fmax(-0.5 * (t2 * t2), -760.0);
@@ -145,20 +180,20 @@ __device__ __forceinline__ void trunc_terms2_f64(double t1, double t2, double& l
     r1 = fma(k1, -kLn2Tail, r1);
     r2 = fma(k2, -kLn2Tail, r2);
     double p1, p2;
-    horner2_tab(kExpC64, r1, r2, p1, p2);
+    horner2_tab<kExpN>(tb->exp, r1, r2, p1, p2);
     const double e1 = ldexp(p1, (int)k1), e2 = ldexp(p2, (int)k2);
     const double z1 = fmin(t1 * kInvSqrt2, kErfcxZmax64 + 1.0);
     const double z2 = fmin(t2 * kInvSqrt2, kErfcxZmax64 + 1.0);
     double P1, P2, Q1, Q2;
-    horner2_tab(kErfcxP64, z1, z2, P1, P2);
-    horner2_tab(kErfcxQ64, z1, z2, Q1, Q2);
+    horner2_tab<kErfcxPN>(tb->erfcx_p, z1, z2, P1, P2);
+    horner2_tab<kErfcxQN>(tb->erfcx_q, z1, z2, Q1, Q2);
     const double a1 = e1 * P1, a2 = e2 * P2;
     const double d11 = fma(4.0, Q1, -a1), d12 = fma(4.0, Q2, -a2);
     const double d21 = d11 - a1, d22 = d12 - a2;
     const double rr1 = rcp_f64(d11 * d21), rr2 = rcp_f64(d12 * d22);
     const double s1 = a1 * d21 * rr1, s2 = a2 * d22 * rr2;
     double A1, A2;
-    horner2_tab(kAtanhA64, s1 * s1, s2 * s2, A1, A2);
+    horner2_tab<kAtanhN>(tb->atanh, s1 * s1, s2 * s2, A1, A2);
     lnphi1 = -2.0 * s1 * A1;
     lnphi2 = -2.0 * s2 * A2;
     mills1 = (4.0 * kInvSqrt2Pi) * (e1 * Q1) * (d11 * rr1);

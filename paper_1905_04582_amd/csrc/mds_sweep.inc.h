@@ -33,6 +33,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "mds_internal.h"
 #include "mds_math.h"
 
@@ -88,18 +90,19 @@ __device__ __forceinline__ float rsqrt_t<float>(float x)
     return __builtin_amdgcn_rsqf(x);
 }
 
-// both rows of a two-row step
+// both rows of a two-row step (`tb`: the FP64 coefficient tables)
 template <typename T>
-__device__ __forceinline__ void trunc_terms2(T t1, T t2, T& l1, T& m1, T& l2, T& m2)
+__device__ __forceinline__ void trunc_terms2(T t1, T t2, T& l1, T& m1, T& l2, T& m2, tab64_ptr)
 {
     trunc_terms_f32(t1, l1, m1);
     trunc_terms_f32(t2, l2, m2);
 }
 template <>
 __device__ __forceinline__ void trunc_terms2<double>(double t1, double t2, double& l1,
-                                                     double& m1, double& l2, double& m2)
+                                                     double& m1, double& l2, double& m2,
+                                                     tab64_ptr tb)
 {
-    trunc_terms2_f64(t1, t2, l1, m1, l2, m2);
+    trunc_terms2_f64(t1, t2, l1, m1, l2, m2, tb);
 }
 
 // Skip point of the truncation terms.  For t >= T, 0 <= -ln Phi(t) <=
@@ -204,6 +207,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
         const double tb = (double)skip_t<T>() * sig;
         const T thr2 = (T)(tb * tb);
         const T* __restrict__ Y = static_cast<const T*>(a.y);
+        // the FP64 special functions' coefficient tables, addressed once
+        const tab64_ptr ctab = sizeof(T) == 8 ? tab64() : nullptr;
 
         // Y is read two steps (four rows) ahead of use into two register
         // pairs that alternate, so each load has two steps of arithmetic to
@@ -246,10 +251,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             ++xnext;
             return p;
         };
-        T pa0 = load_y(), pa1 = load_y();
-        // keep the issue order: the first pair is consumed first
-        __builtin_amdgcn_sched_barrier(0);
-        T pb0 = load_y(), pb1 = load_y();
+        int cntv = 0;  // observed pairs counted per lane (fast walk)
 
         constexpr int NO = RB * D;
         constexpr int RG = reduce_group(NO);
@@ -270,14 +272,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
         // (row, dimension) output gets RG lanes -- lane h of its group adds
         // the staged values of lanes h, h+RG, ..., then the group combines by
         // log2(RG) exchanges
-        auto batch_flush = [&](const int b0) {
+        auto batch_flush = [&](auto fast_tag, const int b0) {
+            constexpr bool FAST = decltype(fast_tag)::value;
             acc_A += (double)bA;
             acc_L += (double)bL;
             acc_M += (double)bM;
             if (GRAD) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) gj[d] = fma((double)gjb[d], inv_s2, gj[d]);
-                const bool live = o < NO && b0 + orow < rw1;
+                const bool live = o < NO && (FAST || b0 + orow < rw1);
                 T sum = T(0);
                 if (live) {
                     const T* src = stage + (size_t)orow * SROW + (size_t)h * D + odim;
@@ -293,12 +296,23 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
         batch_reset();
 
         // One step: rows i0 and i0 + 1, staged at positions q and q + 1 of
-        // the batch.  A row at or past rw1 is dead: no lane's pair counts,
-        // and its loads repeat the wave's last row.
-        auto step = [&](const int i0, const int q, const T ya, const T yb) {
-            const bool live0 = i0 < rw1, live1 = i0 + 1 < rw1;
-            const const_f64_ptr xa = next_x();
-            const const_f64_ptr xb = next_x();
+        // the batch.  FAST (a compile-time tag) is the walk of a wave whose
+        // rows are whole iterations with x rows contiguous (ldx == D); the
+        // general walk has dead rows (at or past rw1: no lane's pair counts,
+        // their loads repeat the wave's last row) and counts pairs by lane
+        // masks.  The fast walk counts them per lane.
+        auto step = [&](auto fast_tag, const int i0, const int q, const T ya, const T yb) {
+            constexpr bool FAST = decltype(fast_tag)::value;
+            const bool live0 = FAST || i0 < rw1, live1 = FAST || i0 + 1 < rw1;
+            const_f64_ptr xa, xb;
+            if constexpr (FAST) {
+                xa = (const_f64_ptr)xrow;
+                xb = xa + D;
+                xrow += 2 * D;
+            } else {
+                xa = next_x();
+                xb = next_x();
+            }
             T da[D], db[D];
             T s2a = T(0), s2b = T(0);
 #pragma unroll
@@ -309,26 +323,40 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 s2b = fma(db[d], db[d], s2b);
             }
             // observed pairs of the strict lower triangle: each condition is
-            // one compare, the counts come from the compares' own lane masks,
-            // and bitwise operators keep the conditions branch-free
+            // one compare, and bitwise operators keep the conditions
+            // branch-free
             const bool tra = j32 < i0, trb = j32 < i0 + 1;
             const bool nna = !isnan(ya), nnb = !isnan(yb);
-            const uint64_t ma = __builtin_amdgcn_ballot_w64(tra) &
-                                __builtin_amdgcn_ballot_w64(nna) & colmask &
-                                (0ull - (uint64_t)live0);
-            const uint64_t mb = __builtin_amdgcn_ballot_w64(trb) &
-                                __builtin_amdgcn_ballot_w64(nnb) & colmask &
-                                (0ull - (uint64_t)live1);
-            cnt += (int)__builtin_popcountll(ma) + (int)__builtin_popcountll(mb);
             const bool oka = live0 & colok & tra & nna;
             const bool okb = live1 & colok & trb & nnb;
+            uint64_t near;
+            if constexpr (FAST) {
+                cntv += (int)oka + (int)okb;
+                // (add now: deferring the adds would keep every step's lane
+                // masks alive to the end of the iteration)
+                asm volatile("" : "+v"(cntv));
+                // any lane with a close pair sends the wave through the
+                // special functions (its terms are masked by oka / okb)
+                near = __builtin_amdgcn_ballot_w64(s2a < thr2) |
+                       __builtin_amdgcn_ballot_w64(s2b < thr2);
+            } else {
+                // counts from the compares' own lane masks
+                const uint64_t ma = __builtin_amdgcn_ballot_w64(tra) &
+                                    __builtin_amdgcn_ballot_w64(nna) & colmask &
+                                    (0ull - (uint64_t)live0);
+                const uint64_t mb = __builtin_amdgcn_ballot_w64(trb) &
+                                    __builtin_amdgcn_ballot_w64(nnb) & colmask &
+                                    (0ull - (uint64_t)live1);
+                cnt += (int)__builtin_popcountll(ma) + (int)__builtin_popcountll(mb);
+                near = (__builtin_amdgcn_ballot_w64(s2a < thr2) & ma) |
+                       (__builtin_amdgcn_ballot_w64(s2b < thr2) & mb);
+            }
             // delta and 1/delta from one reciprocal square root.  A coincident
             // pair (s2 below the normal range) has no direction: 1/delta is
             // taken as 0, and delta = s2 * rsqrt(min normal) is 0 for s2 = 0
             // (tiny otherwise)
             const T rsa = rsqrt_t(fmax(s2a, min_normal<T>()));
             const T rsb = rsqrt_t(fmax(s2b, min_normal<T>()));
-            const T dla = s2a * rsa, dlb = s2b * rsb;
             const T ria = (s2a >= min_normal<T>()) ? rsa : T(0);
             const T rib = (s2b >= min_normal<T>()) ? rsb : T(0);
             // a pair outside the sums gets residual 0 (and, below, ln Phi =
@@ -341,11 +369,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             // x_j)/delta; far pairs (t past the skip point for every lane of
             // the wave) take m = ln Phi = 0 without evaluating them
             T ca = -ra * ria, cb = -rb * rib;
-            const uint64_t near = (__builtin_amdgcn_ballot_w64(s2a < thr2) & ma) |
-                                  (__builtin_amdgcn_ballot_w64(s2b < thr2) & mb);
             if (a.truncated && near) {
+                const T dla = s2a * rsa, dlb = s2b * rsb;
                 T la, mla, lb, mlb;
-                trunc_terms2<T>(dla * inv_sT, dlb * inv_sT, la, mla, lb, mlb);
+                trunc_terms2<T>(dla * inv_sT, dlb * inv_sT, la, mla, lb, mlb, ctab);
                 la = oka ? la : T(0);
                 mla = oka ? mla : T(0);
                 lb = okb ? lb : T(0);
@@ -367,35 +394,78 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 }
             }
         };
+        const std::true_type fast_walk;
+        const std::false_type general_walk;
 
-        // The walk: four rows per iteration in two steps that take the two
-        // register pairs in turn; a staging batch of RB rows closes after
-        // RB/2 steps.  The wave's rows [ib0, rw1) are a whole number of
-        // batches except at the matrix's last row; rows past rw1 in the last
-        // iteration are dead.
-        int q = 0;  // staging position of the next step
-        int ib = ib0;
+        // The fast walk: the wave's rows are a whole number of staging
+        // batches of at least four rows, x rows are contiguous, and the four
+        // rows after the wave's last row exist in the matrix and lie below
+        // all its columns (the Y prefetch reads them, in the strict lower
+        // triangle, and discards them), so no pointer is clamped and no row
+        // is dead.  Two steps of two rows per
+        // iteration take the two register pairs in turn; a batch of RB rows
+        // closes after RB/2 steps.
+        constexpr int IT = RB > 4 ? RB : 4;
+        const bool fast = ((rw1 - ib0) % IT == 0) && ((int64_t)rw1 + 4 <= a.n) &&
+                          (wv.jw0 + kWave <= (int64_t)rw1) && (a.ldx == D);
+        if (fast) {
+            auto load_fast = [&]() -> T {
+                const T v = load_buf<T>(yres, joff, yoff);
+                yoff += ystep;
+                return v;
+            };
+            T pa0 = load_fast(), pa1 = load_fast();
+            // keep the issue order: the first pair is consumed first
+            __builtin_amdgcn_sched_barrier(0);
+            T pb0 = load_fast(), pb1 = load_fast();
+            int q = 0;  // staging position of the iteration's first row
 #pragma unroll 1
-        for (; ib < rw1; ib += 4) {
-            step(ib, q, pa0, pa1);
-            pa0 = load_y();
-            pa1 = load_y();
-            q += 2;
-            if (q == RB) {
-                batch_flush(ib + 2 - RB);
-                q = 0;
+            for (int ib = ib0; ib < rw1; ib += 4) {
+                step(fast_walk, ib, q, pa0, pa1);
+                pa0 = load_fast();
+                pa1 = load_fast();
+                if (RB == 2) batch_flush(fast_walk, ib);
+                step(fast_walk, ib + 2, RB == 2 ? 0 : q + 2, pb0, pb1);
+                pb0 = load_fast();
+                pb1 = load_fast();
+                q += 4;
+                if (q >= RB) {
+                    batch_flush(fast_walk, ib + 4 - RB);
+                    q = 0;
+                }
             }
-            step(ib + 2, q, pb0, pb1);
-            pb0 = load_y();
-            pb1 = load_y();
-            q += 2;
-            if (q == RB) {
-                batch_flush(ib + 4 - RB);
-                q = 0;
+        } else {
+            // The general walk: four rows per iteration; rows past rw1 in the
+            // last iteration are dead, and a batch the walk leaves open
+            // closes after it.
+            T pa0 = load_y(), pa1 = load_y();
+            __builtin_amdgcn_sched_barrier(0);
+            T pb0 = load_y(), pb1 = load_y();
+            int q = 0;  // staging position of the next step
+            int ib = ib0;
+#pragma unroll 1
+            for (; ib < rw1; ib += 4) {
+                step(general_walk, ib, q, pa0, pa1);
+                pa0 = load_y();
+                pa1 = load_y();
+                q += 2;
+                if (q == RB) {
+                    batch_flush(general_walk, ib + 2 - RB);
+                    q = 0;
+                }
+                step(general_walk, ib + 2, q, pb0, pb1);
+                pb0 = load_y();
+                pb1 = load_y();
+                q += 2;
+                if (q == RB) {
+                    batch_flush(general_walk, ib + 4 - RB);
+                    q = 0;
+                }
             }
+            // (rows [ib - q, ib))
+            if (q != 0) batch_flush(general_walk, ib - q);
         }
-        // a batch the walk left open (rows [ib - q, ib))
-        if (q != 0) batch_flush(ib - q);
+        cnt += wave_sum(cntv);
     }
 
     double acc_r = fma(acc_A, 0.5 * inv_s2, acc_L);

@@ -86,6 +86,43 @@ static void replay_walk(const WaveRows& w, int rb, std::vector<int64_t>& yrows,
     if (q != 0) batches.push_back(ib - q);
 }
 
+// The fast walk (taken when the wave's rows are a whole number of
+// iterations of max(rb, 4) rows, the four rows after rw1 exist and lie below
+// all the wave's columns, and x rows are contiguous): Y rows ib0 .. rw1+3
+// with no clamp, x rows ib0 .. rw1-1, and a batch closed every rb rows.
+static bool fast_walk(const WaveRows& w, int rb, int64_t n)
+{
+    const int it = rb > 4 ? rb : 4;
+    return w.active && (w.rw1 - w.ib0) % it == 0 && w.rw1 + 4 <= n && w.jw0 + 64 <= w.rw1;
+}
+
+static void replay_fast(const WaveRows& w, int rb, std::vector<int64_t>& yrows,
+                        std::vector<int64_t>& xrows, std::vector<int64_t>& batches)
+{
+    yrows.clear();
+    xrows.clear();
+    batches.clear();
+    int64_t y = w.ib0;
+    for (int k = 0; k < 4; ++k) yrows.push_back(y++);
+    int q = 0;
+    for (int64_t ib = w.ib0; ib < w.rw1; ib += 4) {
+        xrows.push_back(ib);
+        xrows.push_back(ib + 1);
+        yrows.push_back(y++);
+        yrows.push_back(y++);
+        if (rb == 2) batches.push_back(ib);
+        xrows.push_back(ib + 2);
+        xrows.push_back(ib + 3);
+        yrows.push_back(y++);
+        yrows.push_back(y++);
+        q += 4;
+        if (q >= rb) {
+            batches.push_back(ib + 4 - rb);
+            q = 0;
+        }
+    }
+}
+
 // sum over k < m of min(max(k, 0), 64): the pairs of a wave's 64 columns in
 // the rows i < jw0 + m
 static long double pairs_below(int64_t m)
@@ -170,6 +207,21 @@ static void check_case(int64_t n, const Tile& tl, int rb, bool per_pair, bool sa
             }
             CHECK(live_batches * rb >= w.rw1 - w.ib0 && (live_batches - 1) * rb < w.rw1 - w.ib0,
                   fmt, CASE);
+            if (fast_walk(w, rb, n)) {
+                // the fast walk: every Y row it reads lies in the matrix and
+                // below every column of the wave; x rows in the wave's rows;
+                // batches cover the rows exactly, in order
+                replay_fast(w, rb, loads, xloads, batches);
+                for (int64_t y : loads) {
+                    CHECK(y >= w.ib0 && y < n && y <= w.rw1 + 3, fmt, CASE);
+                    CHECK(y >= w.rw1 || y < w.row1, fmt, CASE);
+                    if (y >= w.rw1) CHECK(y > w.jw0 + 63, fmt, CASE);
+                }
+                for (int64_t x : xloads) CHECK(x >= w.ib0 && x < w.rw1, fmt, CASE);
+                CHECK((int64_t)batches.size() * rb == w.rw1 - w.ib0, fmt, CASE);
+                for (size_t b = 0; b < batches.size(); ++b)
+                    CHECK(batches[b] == w.ib0 + (int64_t)b * rb, fmt, CASE);
+            }
             if (!per_pair) {
                 pairs += pairs_below(w.rw1 - w.jw0) - pairs_below(w.ib0 - w.jw0);
                 continue;
