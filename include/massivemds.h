@@ -249,7 +249,7 @@ MDS_API int mds_gradient(int64_t n, int32_t d, const double* x, int64_t ldx, con
  * device for the life of the process; the call itself allocates nothing.
  * A problem whose workspace (mds_workspace_bytes with the same arguments)
  * exceeds that size is rejected with MDS_ERR_WORKSPACE_TOO_SMALL (at the
- * default tiling N = 5392 needs 16.2 MB in either dtype).  Every call on one
+ * default tiling N = 5392 needs 11.2 MB in either dtype).  Every call on one
  * device shares that device's array: calls that overlap on one device (other
  * streams, other threads) race and must be ordered by the caller.  The first
  * call on a device looks the array's address up (hipGetSymbolAddress), which

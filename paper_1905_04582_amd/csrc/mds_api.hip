@@ -95,31 +95,38 @@ int split_ytype(int32_t& y_dtype, int* truncated)
 // Largest LDS a sweep work-group may use (row sums of all its waves).
 constexpr size_t kMaxSweepLds = 64 * 1024;
 
-// Tile shape used when the caller passes 0 (measured for D = 2 on spatially
-// ordered locations).  Small problems need short tiles: a wave walks its
-// tile's rows one after another, so at N = 1000 8-row tiles (about 1000
-// one-wave work-groups) finish in 60% of the time of 32-row ones.  Up to
-// N ~ 6000 many small work-groups keep every SIMD supplied with waves and let
-// the dispatcher balance tiles of uneven cost (tiles whose wavefronts skip the
-// truncation terms are cheap); larger problems run long enough for 64 x 256
-// tiles, which write fewer partial sums.
+// Tile shape used when the caller passes 0: the autotuner's grid on
+// spatially ordered random problems (D = 2, 4, 6; both precisions) rounded
+// to one rule per N range, each within a few percent of the grid's best.
+// Small problems need short tiles: a wave walks its rows one after another,
+// so at N = 1000 8-row tiles (about 1000 one-wave work-groups) fill the chip.
+// Up to N ~ 12000 tiles one column group wide whose rows are split over 2 or
+// 4 waves keep every wave's walk short, so the last waves of the launch
+// finish soon after the others; larger problems run long enough for taller,
+// wider tiles, which write fewer partial sums.
 void default_tiling(int64_t n, int d, int dtype, int* br, int* wc, int* wr)
 {
-    (void)d;
     (void)dtype;
-    *wr = 1;
     if (n <= 1536) {
         *br = 8;
         *wc = 1;
+        *wr = 1;
     } else if (n <= 3072) {
-        *br = 16;
-        *wc = 1;
-    } else if (n <= 6144) {
         *br = 32;
-        *wc = 4;
-    } else {
+        *wc = 1;
+        *wr = 2;
+    } else if (n <= 6144) {
         *br = 64;
-        *wc = 4;
+        *wc = 1;
+        *wr = d <= 2 ? 4 : 2;
+    } else if (n <= 12288) {
+        *br = 64;
+        *wc = 1;
+        *wr = 2;
+    } else {
+        *br = 128;
+        *wc = 2;
+        *wr = d <= 2 ? 2 : 1;
     }
 }
 

@@ -286,10 +286,14 @@ def test_resolve_tiling():
     f64, f32 = api.MDS_F64, api.MDS_F32
     assert api.mds_resolve_tiling(1000, 2, f64) == (8, 1)
     assert api.mds_resolve_tiling(1000, 2, f32) == (8, 1)
-    assert api.mds_resolve_tiling(2500, 2, f64) == (16, 1)
-    assert api.mds_resolve_tiling(5392, 2, f64) == (32, 4)
-    assert api.mds_resolve_tiling(5392, 2, f32) == (32, 4)
-    assert api.mds_resolve_tiling(20000, 6, f32) == (64, 4)
+    tw = api.tile_waves
+    assert api.mds_resolve_tiling(2500, 2, f64) == (32, tw(1, 2))
+    assert api.mds_resolve_tiling(5392, 2, f64) == (64, tw(1, 4))
+    assert api.mds_resolve_tiling(5392, 2, f32) == (64, tw(1, 4))
+    assert api.mds_resolve_tiling(5392, 6, f32) == (64, tw(1, 2))
+    assert api.mds_resolve_tiling(8000, 2, f64) == (64, tw(1, 2))
+    assert api.mds_resolve_tiling(20000, 2, f32) == (128, tw(2, 2))
+    assert api.mds_resolve_tiling(20000, 6, f32) == (128, 2)
     assert api.mds_resolve_tiling(5392, 2, f64, 128, 2) == (128, 2)
     r, w = ctypes.c_int32(), ctypes.c_int32()
     assert L.mds_resolve_tiling(100, 2, 0, 48, 1, ctypes.byref(r), ctypes.byref(w)) == ERR_UNSUP

@@ -37,7 +37,7 @@ def _same(a, b, label):
 
 
 def test_noalloc_matches_workspace_call_twice_second_smaller():
-    # first call: the paper-scale problem (N = 5392, 16.2 MB of partials)
+    # first call: the paper-scale problem (N = 5392, 11.2 MB of partials)
     p = synth.preset("paper_fp64")
     P = api.MDSProblem(p.y, p.d, p.mask, torch.float64, DEV)
     x = torch.as_tensor(p.x, device=DEV)
