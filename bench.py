@@ -501,14 +501,18 @@ def main():
         ys.append(yk)
         xs.append(xk)
         xts.append(xtk)
-    # the batch with its tiles picked by the batch autotuner (the cached
-    # per-(D, N bucket) entries of autotune.tune_batch), timed beside the
-    # library's batch default below
+    # the batch with its tiles picked by the batch autotuner: the plan from
+    # the cached per-(D, N bucket) entries, then MDSBatch.autotune() timing
+    # that plan, the library default and the other wave layouts on this
+    # batch; timed beside the library's batch default below
     Bt = api.MDSBatch([dict(y=yk, d=sp["d"], order=xtk) for yk, xtk, sp in zip(ys, xts, specs)],
                       torch.float32, dev, autotuned=True)
     for k, sp in enumerate(specs):
         Bt.set_x(k, xs[k])
         Bt.sigma[k] = sp["sigma"]
+    t0 = time.perf_counter()
+    tune_rec = Bt.autotune()
+    tune_s = time.perf_counter() - t0
     for _ in range(3):
         Bt.eval()
     torch.cuda.synchronize()
@@ -579,10 +583,12 @@ def main():
         "y_stream_gbs": round(bpairs * 4 / (bsweep_mean * 1e-3) / 1e9, 1),
         "y_stream_frac": round(bpairs * 4 / (bsweep_mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "leapfrog_20_steps_graph_ms": round(btraj_ms, 3),
-        "tiles": "library batch default (128-row tiles, 4 column waves)",
+        "tiles": "library batch default (128-row tiles, 2 column waves)",
         "autotuned": {"ms_per_batch_eval": round(tuned_ms, 4),
                       "gpairs_per_s": round(bpairs / (tuned_ms * 1e-3) / 1e9, 2),
-                      "tile_waves": tuned_tw, "tile_rows": tuned_rows,
+                      "choice": tune_rec["choice"], "tile_waves": tuned_tw,
+                      "tile_rows": tuned_rows, "tuning_s": round(tune_s, 2),
+                      "candidates_ms": tune_rec["ms"],
                       "speedup_vs_default": round(batch_ms / tuned_ms, 3)},
         "workload": "64 problems, N ~ U[500, 8000], D in {2,4,6}, sigma ~ U(0.2,1), 10% "
                     "missing, FP32 Y drawn in device memory; each problem relabelled in "

@@ -446,7 +446,9 @@ typedef struct mds_batch_plan {
  * one finalize launch per evaluation.  Each problem's results equal, bit for
  * bit, those of mds_gradient with the same tile_rows and tile_waves.
  *   mds_batch_workspace_bytes: workspace for the batch (tile_waves common to
- *     the batch, 0 = MDS_TILE_WAVES(4, 1); y_dtype common to the batch).
+ *     the batch, 0 = MDS_TILE_WAVES(2, 1); y_dtype common to the batch; a
+ *     descriptor's tile_rows 0 = 128 rows where the tiling allows, else the
+ *     single-problem default).
  *   mds_batch_init: validates every descriptor, writes the device-side
  *     problem table into the workspace with one host-to-device copy on
  *     `stream` and waits for it (not capturable; call once per batch layout),

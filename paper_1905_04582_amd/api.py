@@ -31,6 +31,7 @@ MDS_F64 = 0
 MDS_F32 = 1
 MDS_MAX_DIM = 8
 WORKSPACE_ALIGN = 256
+BATCH_DEFAULT_WAVES = 2      # the library's batch tile_waves when 0 is passed
 
 _c_i64 = ctypes.c_int64
 _c_i32 = ctypes.c_int32
@@ -699,25 +700,54 @@ class MDSBatch:
             q.p, q.ldp = pk.data_ptr(), max(d, 1)
             q.step = self.step.data_ptr() + 8 * k
         self._descs = descs
-        code = _dtype_code(dtype) | (0 if truncated else MDS_UNTRUNCATED)
+        self._code = _dtype_code(dtype) | (0 if truncated else MDS_UNTRUNCATED)
+        self._plan_tiles(tile_waves, stream)
+
+    def _plan_tiles(self, tile_waves, stream=None):
+        """Resolve every problem's tiling under the common tile_waves and
+        (re)build the batch plan and its workspace (``mds_batch_init``)."""
+        descs, count = self._descs, self.count
+        self.tile_waves = tile_waves
+        self.tiles = []
         for k in range(count):
             q = descs[k]
+            code, waves = _dtype_code(self.dtype), tile_waves or BATCH_DEFAULT_WAVES
             if q.tile_rows == 0:
                 try:
-                    t = mds_resolve_tiling(q.n, q.d, _dtype_code(dtype), 128, tile_waves or 4)
+                    t = mds_resolve_tiling(q.n, q.d, code, 128, waves)
                 except MDSError:
-                    t = mds_resolve_tiling(q.n, q.d, _dtype_code(dtype), 0, tile_waves or 4)
+                    t = mds_resolve_tiling(q.n, q.d, code, 0, waves)
             else:
-                t = mds_resolve_tiling(q.n, q.d, _dtype_code(dtype), q.tile_rows, tile_waves or 4)
+                t = mds_resolve_tiling(q.n, q.d, code, q.tile_rows, waves)
             self.tiles.append(t)
         nb = ctypes.c_size_t(0)
-        _check(lib().mds_batch_workspace_bytes(descs, count, code, tile_waves, ctypes.byref(nb)),
-               "mds_batch_workspace_bytes")
+        _check(lib().mds_batch_workspace_bytes(descs, count, self._code, tile_waves,
+                                               ctypes.byref(nb)), "mds_batch_workspace_bytes")
         self.workspace = alloc_workspace(int(nb.value), self.device)
         self.plan = BatchPlan()
-        _check(lib().mds_batch_init(descs, count, code, tile_waves, _ptr(self.workspace),
+        _check(lib().mds_batch_init(descs, count, self._code, tile_waves, _ptr(self.workspace),
                                     self.workspace.numel(), ctypes.byref(self.plan),
                                     _stream(stream)), "mds_batch_init")
+
+    def retile(self, tile_waves: int = 0, rows=None, stream=None):
+        """New tiles for the batch without preparing Y again: a common
+        tile_waves and each problem's tile_rows (a list; None or 0 = the
+        library's batch default).  The gradient, x, p and sigma buffers are
+        kept; the workspace is replaced."""
+        torch.cuda.synchronize(self.device)
+        for k in range(self.count):
+            self._descs[k].tile_rows = int(rows[k]) if rows is not None and rows[k] else 0
+        self._plan_tiles(tile_waves, stream)
+
+    def autotune(self, reps: int = 5, path: str | None = None):
+        """Pick the batch's tiles by timing whole evaluations of this batch
+        (``autotune.tune_batch_plan``): the library default, the plan from
+        the batch tuner's cache, and every common wave layout with the
+        cache's row tiles or uniform 128-row tiles.  Call it once x and sigma
+        hold representative values (the cost of a tile depends on how many
+        of its wavefronts skip the truncation terms).  Returns the timings."""
+        from . import autotune
+        return autotune.tune_batch_plan(self, reps=reps, path=path)
 
     def set_x(self, k, x):
         """x in the problem's own (original) labelling."""

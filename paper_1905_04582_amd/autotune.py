@@ -14,7 +14,9 @@ evaluation of a batch of copies of a problem of that size for every row tile
 under each common wave layout and records, per layout, the fastest row tile
 and its time.  A batch built with ``autotuned=True`` takes the layout whose
 recorded times, scaled by each problem's pairs, add up to the least, and each
-problem's fastest row tile under it (``batch_plan``).
+problem's fastest row tile under it (``batch_plan``).  ``MDSBatch.autotune()``
+then times that plan, the library default and the other layouts on the batch
+itself and keeps the fastest (``tune_batch_plan``).
 
 The tuning problems are generated on the device: locations X ~ N(0, 9 I) in
 spatial order (as ``MDSProblem(order=...)`` stores a problem) and a random
@@ -344,6 +346,56 @@ def batch_plan(sizes, dtype, device=None, path: str | None = None, tile_waves: i
         r = e["by_waves"].get(str(tile_waves)) if (e is not None and tile_waves) else None
         rows.append(int(r["tile_rows"]) if r else 0)
     return tile_waves, rows
+
+
+def tune_batch_plan(B, reps: int = 5, path: str | None = None) -> dict:
+    """Tiles for one batch by timing its whole evaluation (``MDSBatch.autotune``).
+
+    The cached per-bucket entries time batches of copies of one problem
+    size; a mixed batch shares one register budget (its largest D) and one
+    LDS budget (its largest tile) in a single persistent launch, which those
+    entries do not see.  So the candidates -- the library's batch default,
+    the cache's plan, and every common wave layout with the cache's row
+    tiles or uniform 128-row tiles -- are timed on the batch itself (median
+    of ``reps`` evaluations after two warm-up ones) and the fastest is kept.
+    Returns the choice and every candidate's time."""
+    sizes = [(int(B._descs[k].n), int(B._descs[k].d)) for k in range(B.count)]
+    cands = [("library default", 0, None)]
+    tw0, rows0 = batch_plan(sizes, B.dtype, B.device, path=path)
+    if tw0:
+        cands.append(("cache plan", tw0, rows0))
+    for wc, wr in BATCH_WAVES:
+        tw = api.tile_waves(wc, wr)
+        _, rows = batch_plan(sizes, B.dtype, B.device, path=path, tile_waves=tw)
+        if any(rows):
+            cands.append((f"cache rows, {wc}x{wr} waves", tw, rows))
+        cands.append((f"128 rows, {wc}x{wr} waves", tw, [128] * B.count))
+    seen, times = set(), {}
+    for name, tw, rows in cands:
+        key = (tw, tuple(rows) if rows is not None else None)
+        if key in seen:
+            continue
+        seen.add(key)
+        try:
+            B.retile(tw, rows)
+        except api.MDSError:
+            continue          # a tiling this batch's LDS budget rejects
+        for _ in range(2):
+            B.eval()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            B.eval()
+            b.record()
+        torch.cuda.synchronize()
+        ts = sorted(a.elapsed_time(b) for a, b in ev)
+        times[name] = (ts[len(ts) // 2], tw, rows)
+    best = min(times, key=lambda k: times[k][0])
+    _, tw, rows = times[best]
+    B.retile(tw, rows)
+    return {"choice": best, "tile_waves": tw, "tile_rows": rows,
+            "ms": {k: round(v[0], 4) for k, v in times.items()}}
 
 
 def tune_batch_grid(dtypes=(torch.float32,), dims=(2, 4, 6), ns=(512, 768, 1024, 1536, 2048,

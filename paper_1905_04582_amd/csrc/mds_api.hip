@@ -941,10 +941,13 @@ namespace {
 
 constexpr int kFinElemsPerBlock = 64;  // finalize element block (one wave wide)
 constexpr int32_t kBatchLeapfrogReady = 1;  // mds_batch_plan.flags bit 0
-// rows per tile of a batched problem whose descriptor says 0 (measured on
-// 64 problems of N ~ U[500, 8000]: 1.80 ms per evaluation against 2.10 ms
-// with the single-problem defaults)
+// rows per tile of a batched problem whose descriptor says 0, and the
+// batch's waves when tile_waves is 0: 128-row tiles two column groups wide
+// (on 64 problems of N ~ U[500, 8000], D in {2, 4, 6}, timed against every
+// common wave layout by the batch autotuner: 1.9 ms per evaluation against
+// 2.1 ms with four column groups)
 constexpr int kBatchDefaultRows = 128;
+constexpr int kBatchDefaultWaves = 2;
 
 struct BatchLayout {
     size_t table;   // BatchProblem[count]
@@ -961,7 +964,7 @@ static int batch_layout(const mds_problem_desc* descs, int32_t count, int32_t y_
     if (!descs) return fail(MDS_ERR_INVALID_ARGUMENT, "descs is NULL");
     if (y_dtype != MDS_F64 && y_dtype != MDS_F32)
         return fail(MDS_ERR_UNSUPPORTED, "y_dtype=%d unsupported", y_dtype);
-    const int waves = tile_waves ? tile_waves : 4;  // packed: column and row waves
+    const int waves = tile_waves ? tile_waves : kBatchDefaultWaves;  // packed: column and row waves
     size_t off = 0;
     L->table = off;
     off = align_up(off + sizeof(BatchProblem) * (size_t)count, 256);

@@ -74,3 +74,35 @@ def test_autotuned_batch_equals_single_calls_and_oracle(tmp_path, monkeypatch):
     got = B.grad[1].cpu().numpy()
     assert abs(B.loglik[1].item() - ref.loglik) <= 1e-12 * abs(ref.loglik)
     assert np.all(np.max(np.abs(got - ref.grad), axis=1) <= 1e-12 * ref.condrow)
+
+
+def test_batch_autotune_times_the_batch_and_keeps_results(tmp_path, monkeypatch):
+    # MDSBatch.autotune() times candidate tilings on the batch itself, keeps
+    # the fastest (the library default is a candidate), and the retiled
+    # batch still gives each problem's single-problem result bit for bit
+    monkeypatch.setenv("MDS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    specs = [dict(n=700, d=2, sigma=0.6, missing=0.1, seed=41),
+             dict(n=1100, d=4, sigma=0.4, missing=0.1, seed=42),
+             dict(n=500, d=6, sigma=0.9, missing=0.1, seed=43)]
+    probs = [synth.make_problem(**s) for s in specs]
+    B = api.MDSBatch([dict(y=p.y.astype(np.float32), d=p.d, mask=p.mask) for p in probs],
+                     torch.float32, "cuda", autotuned=True)
+    for k, p in enumerate(probs):
+        B.set_x(k, p.x)
+        B.sigma[k] = p.sigma
+    rec = B.autotune(reps=3)
+    assert "library default" in rec["ms"]
+    assert rec["ms"][rec["choice"]] == min(rec["ms"].values())
+    assert B.tile_waves == rec["tile_waves"]
+    B.eval()
+    torch.cuda.synchronize()
+    for k, p in enumerate(probs):
+        P = api.MDSProblem(p.y.astype(np.float32), p.d, p.mask, torch.float32, "cuda",
+                           *B.tiles[k])
+        g, L, _ = P.gradient(B.x[k], p.sigma)
+        torch.cuda.synchronize()
+        assert torch.equal(g, B.grad[k]) and L.item() == B.loglik[k].item(), k
+    # and the oracle's result (FP32 arithmetic: the FP32 form's tolerance)
+    ref = oracle.evaluate(probs[0].x, probs[0].y.astype(np.float32).astype(np.float64),
+                          probs[0].sigma, probs[0].mask)
+    assert abs(B.loglik[0].item() - ref.loglik) <= 1e-5 * abs(ref.loglik)
