@@ -172,6 +172,10 @@ int resolve_tiling(int64_t n, int d, int dtype, int tile_rows, int tile_waves, T
     // staged rows hold Y's element type; a model flag in dtype's high bits
     // does not change it
     *out = make_tiling(n, br, wc, wr, (dtype & 0xff) == MDS_F32 ? 4 : 8);
+    // one work-group per tile, indexed in 32 bits
+    if (out->ntiles > INT32_MAX)
+        return fail(MDS_ERR_UNSUPPORTED, "tile %dx%d at n=%lld gives %lld tiles (max 2^31-1)", br,
+                    cw, (long long)n, (long long)out->ntiles);
     if (sweep_lds_bytes(*out, d) > kMaxSweepLds)
         return fail(MDS_ERR_UNSUPPORTED, "tile %dx%d with D=%d needs %zu B of LDS (max %zu)", br,
                     cw, d, sweep_lds_bytes(*out, d), kMaxSweepLds);
@@ -196,11 +200,10 @@ int check_problem(int64_t n, int32_t d, const double* x, int64_t ldx, const void
     if (n > 1 && !y) return fail(MDS_ERR_INVALID_ARGUMENT, "y is NULL");
     if (n > 0 && ldy < n)
         return fail(MDS_ERR_INVALID_ARGUMENT, "ldy=%lld < n=%lld", (long long)ldy, (long long)n);
-    // a wave addresses the rows of its tile (at most 256) and the four rows
-    // after them by 32-bit byte offsets from its first row; 261 rows of Y
-    // must span less than 2^31 bytes (ldy below about 10^6 elements: far
-    // beyond any Y that fits a GPU)
-    if (n > 1 && ldy > (((int64_t)1 << 31) - 1) / (261 * (int64_t)dtype_size(y_dtype)))
+    // a wave addresses the rows of its tile (at most 256) by 32-bit byte
+    // offsets from its first row; 257 rows of Y must span less than 2^31
+    // bytes (ldy below about 10^6 elements: far beyond any Y that fits a GPU)
+    if (n > 1 && ldy > (((int64_t)1 << 31) - 1) / (257 * (int64_t)dtype_size(y_dtype)))
         return fail(MDS_ERR_UNSUPPORTED, "ldy=%lld: rows of Y too long for 32-bit offsets",
                     (long long)ldy);
     if (!sigma_dev) return fail(MDS_ERR_INVALID_ARGUMENT, "sigma_dev is NULL");

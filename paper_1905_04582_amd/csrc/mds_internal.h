@@ -60,8 +60,10 @@ __host__ __device__ inline int first_row_block_of_column(int c, int br, int cw)
 }
 
 // (row block, column block) of linear tile index `tile` (row blocks in
-// order, then column blocks in order within a row block)
-__host__ __device__ inline void tile_coords(int64_t tile, int nrb, int br, int cw, int* r, int* c)
+// order, then column blocks in order within a row block), by a binary search
+// on the prefix count (the reference form; the host tests compare the two)
+__host__ __device__ inline void tile_coords_search(int64_t tile, int nrb, int br, int cw, int* r,
+                                                   int* c)
 {
     int lo = 0, hi = nrb - 1;
     while (lo < hi) {
@@ -73,6 +75,45 @@ __host__ __device__ inline void tile_coords(int64_t tile, int nrb, int br, int c
     }
     *r = lo;
     *c = (int)(tile - tiles_before(lo, br, cw));
+}
+
+// The largest a >= 0 with a (a + 1) / 2 <= m, for 0 <= m < 2^31: the root
+// of the triangular number in single precision (off by at most one), then
+// corrected by one step either way in integers.
+__host__ __device__ inline uint32_t tri_root(uint32_t m)
+{
+    uint32_t a = (uint32_t)((sqrtf(8.0f * (float)m + 1.0f) - 1.0f) * 0.5f);
+    const uint64_t mm = m;
+    if ((uint64_t)(a + 1) * (a + 2) / 2 <= mm) ++a;
+    if (a > 0 && (uint64_t)a * (a + 1) / 2 > mm) --a;
+    return a;
+}
+
+// tile_coords_search in closed form (32-bit: a tiling has fewer than 2^31
+// tiles): with k = cw/br row blocks per column block, the a-th group of k row
+// blocks holds k (a + 1) tiles; with k = br/cw column blocks per row block,
+// row block r holds k (r + 1).  Either way the group is the root of a
+// triangular number.  k is a power of two.
+__host__ __device__ inline void tile_coords(int64_t tile, int nrb, int br, int cw, int* r, int* c)
+{
+    (void)nrb;
+    const uint32_t g = (uint32_t)tile;
+    const int lbr = __builtin_ctz((unsigned)br), lcw = __builtin_ctz((unsigned)cw);
+    if (br <= cw) {
+        const int sh = lcw - lbr;  // log2 k
+        const uint32_t a = tri_root(g >> sh);
+        // the group's first tile is k a (a + 1) / 2; its row blocks hold
+        // a + 1 tiles each
+        const uint32_t rem = g - ((a * (a + 1) / 2) << sh);
+        const uint32_t b = rem / (a + 1);
+        *r = (int)((a << sh) + b);
+        *c = (int)(rem - b * (a + 1));
+    } else {
+        const int sh = lbr - lcw;
+        const uint32_t a = tri_root(g >> sh);
+        *r = (int)a;
+        *c = (int)(g - ((a * (a + 1) / 2) << sh));
+    }
 }
 
 // rows staged per reduction step of the sweep (keeps the per-wave staging
@@ -87,27 +128,30 @@ __host__ __device__ constexpr int sweep_stage_rows(int d) { return d <= 2 ? 8 : 
 // reads -- its Y prefetch included -- lies in [ib0, rw1), inside both the
 // tile and the matrix.
 struct WaveRows {
-    int64_t row0, row1;  // the tile's rows [row0, row1), row1 <= n
-    int64_t rw0, rw1;    // the wave's row group, rw1 <= row1
-    int64_t jw0;         // the wave's first column
-    int64_t ib0;         // first row visited
-    bool active;         // ib0 < rw1
+    int row0, row1;  // the tile's rows [row0, row1), row1 <= n
+    int rw0, rw1;    // the wave's row group, rw1 <= row1
+    int jw0;         // the wave's first column
+    int ib0;         // first row visited
+    bool active;     // ib0 < rw1
 };
 
+// Row and column indices fit 32 bits (n <= 2^30 plus one tile); wc, wr and
+// rb are powers of two, so the divisions are shifts.
 __host__ __device__ inline WaveRows wave_rows(int64_t n, int br, int cw, int wc, int wr, int r,
                                               int c, int wave, int rb)
 {
     WaveRows w;
-    const int u = wave % wc, v = wave / wc;
-    const int rpw = br / wr;
-    w.row0 = (int64_t)r * br;
-    w.row1 = w.row0 + br < n ? w.row0 + br : n;
-    w.rw0 = w.row0 + (int64_t)v * rpw;
-    const int64_t e = w.rw0 + rpw;
+    const int u = wave & (wc - 1), v = wave >> __builtin_ctz((unsigned)wc);
+    const int rpw = br >> __builtin_ctz((unsigned)wr);
+    const int n32 = (int)n;
+    w.row0 = r * br;
+    w.row1 = w.row0 + br < n32 ? w.row0 + br : n32;
+    w.rw0 = w.row0 + v * rpw;
+    const int e = w.rw0 + rpw;
     w.rw1 = e < w.row1 ? e : w.row1;
-    w.jw0 = (int64_t)c * cw + (int64_t)u * 64;
-    const int64_t istart = w.rw0 > w.jw0 + 1 ? w.rw0 : w.jw0 + 1;
-    w.ib0 = w.rw0 + ((istart - w.rw0) / rb) * rb;
+    w.jw0 = c * cw + u * 64;
+    const int istart = w.rw0 > w.jw0 + 1 ? w.rw0 : w.jw0 + 1;
+    w.ib0 = w.rw0 + (int)((unsigned)(istart - w.rw0) & ~(unsigned)(rb - 1));
     w.active = w.ib0 < w.rw1;
     return w;
 }

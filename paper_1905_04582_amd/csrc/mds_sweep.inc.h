@@ -161,7 +161,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int waves = blockDim.x / kWave;
     const int br = a.br, cw = a.cw, wc = a.wc;
-    const int wu = w % wc;  // this wave's column group
+    const int wu = w & (wc - 1);  // this wave's column group (wc is a power of two)
 
     int r, c;
     tile_coords(tile, a.nrb, br, cw, &r, &c);
@@ -398,19 +398,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
         const std::false_type general_walk;
 
         // The fast walk: the wave's rows are a whole number of staging
-        // batches of at least four rows, x rows are contiguous, and the four
-        // rows after the wave's last row exist in the matrix and lie below
-        // all its columns (the Y prefetch reads them, in the strict lower
-        // triangle, and discards them), so no pointer is clamped and no row
-        // is dead.  Two steps of two rows per
+        // batches of at least four rows and its x rows are contiguous, so no
+        // row is dead and x of two rows is one scalar load.  The Y prefetch
+        // of the last iteration (rows past rw1) repeats the wave's last row:
+        // its offset is capped by one scalar min.  Two steps of two rows per
         // iteration take the two register pairs in turn; a batch of RB rows
         // closes after RB/2 steps.
         constexpr int IT = RB > 4 ? RB : 4;
-        const bool fast = ((rw1 - ib0) % IT == 0) && ((int64_t)rw1 + 4 <= a.n) &&
-                          (wv.jw0 + kWave <= (int64_t)rw1) && (a.ldx == D);
+        const bool fast = ((rw1 - ib0) % IT == 0) && (a.ldx == D);
         if (fast) {
+            const uint32_t ylast = (uint32_t)(rw1 - 1 - ib0) * ystep;
             auto load_fast = [&]() -> T {
-                const T v = load_buf<T>(yres, joff, yoff);
+                const T v = load_buf<T>(yres, joff, min(yoff, ylast));
                 yoff += ystep;
                 return v;
             };

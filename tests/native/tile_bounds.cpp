@@ -1,6 +1,7 @@
 // Host-only replay of the pair sweep's tile and wave arithmetic (no GPU).
 //
-// The sweep kernel maps a work-group index to a tile with tile_coords() and
+// The sweep kernel maps a work-group index to a tile with tile_coords() (a
+// closed form, checked against the prefix-count search tile_coords_search) and
 // each of its waves to a row range with wave_rows(); this program calls the
 // same functions (mds_internal.h) and checks, for many N, every valid tiling
 // and the staging batch of every D:
@@ -87,13 +88,13 @@ static void replay_walk(const WaveRows& w, int rb, std::vector<int64_t>& yrows,
 }
 
 // The fast walk (taken when the wave's rows are a whole number of
-// iterations of max(rb, 4) rows, the four rows after rw1 exist and lie below
-// all the wave's columns, and x rows are contiguous): Y rows ib0 .. rw1+3
-// with no clamp, x rows ib0 .. rw1-1, and a batch closed every rb rows.
-static bool fast_walk(const WaveRows& w, int rb, int64_t n)
+// iterations of max(rb, 4) rows and x rows are contiguous): Y rows ib0 ..
+// rw1-1, the prefetch past rw1 capped at rw1-1; x rows ib0 .. rw1-1; a batch
+// closed every rb rows.
+static bool fast_walk(const WaveRows& w, int rb)
 {
     const int it = rb > 4 ? rb : 4;
-    return w.active && (w.rw1 - w.ib0) % it == 0 && w.rw1 + 4 <= n && w.jw0 + 64 <= w.rw1;
+    return w.active && (w.rw1 - w.ib0) % it == 0;
 }
 
 static void replay_fast(const WaveRows& w, int rb, std::vector<int64_t>& yrows,
@@ -103,18 +104,22 @@ static void replay_fast(const WaveRows& w, int rb, std::vector<int64_t>& yrows,
     xrows.clear();
     batches.clear();
     int64_t y = w.ib0;
-    for (int k = 0; k < 4; ++k) yrows.push_back(y++);
+    auto load = [&]() {
+        yrows.push_back(y < w.rw1 - 1 ? y : w.rw1 - 1);
+        ++y;
+    };
+    for (int k = 0; k < 4; ++k) load();
     int q = 0;
     for (int64_t ib = w.ib0; ib < w.rw1; ib += 4) {
         xrows.push_back(ib);
         xrows.push_back(ib + 1);
-        yrows.push_back(y++);
-        yrows.push_back(y++);
+        load();
+        load();
         if (rb == 2) batches.push_back(ib);
         xrows.push_back(ib + 2);
         xrows.push_back(ib + 3);
-        yrows.push_back(y++);
-        yrows.push_back(y++);
+        load();
+        load();
         q += 4;
         if (q >= rb) {
             batches.push_back(ib + 4 - rb);
@@ -148,8 +153,12 @@ static void check_case(int64_t n, const Tile& tl, int rb, bool per_pair, bool sa
     long double pairs = 0;
     int64_t prev_tile_r = 0;
     for (int64_t tile = 0; tile < t.ntiles; ++tile) {
-        int r, c;
+        int r, c, rs, cs;
         tile_coords(tile, t.nrb, t.br, cw, &r, &c);
+        // the closed form the kernel uses against the prefix-count search
+        tile_coords_search(tile, t.nrb, t.br, cw, &rs, &cs);
+        CHECK(r == rs && c == cs, "n=%lld br=%d cw=%d tile=%lld: (%d,%d) vs (%d,%d)", (long long)n,
+              t.br, cw, (long long)tile, r, c, rs, cs);
         CHECK(r >= 0 && r < t.nrb && c >= 0 && c < tiles_in_row_block(r, t.br, cw),
               "n=%lld br=%d cw=%d tile=%lld -> (%d,%d)", (long long)n, t.br, cw, (long long)tile, r, c);
         CHECK(tiles_before(r, t.br, cw) + c == tile && r >= prev_tile_r, "tile order n=%lld", (long long)n);
@@ -207,16 +216,11 @@ static void check_case(int64_t n, const Tile& tl, int rb, bool per_pair, bool sa
             }
             CHECK(live_batches * rb >= w.rw1 - w.ib0 && (live_batches - 1) * rb < w.rw1 - w.ib0,
                   fmt, CASE);
-            if (fast_walk(w, rb, n)) {
-                // the fast walk: every Y row it reads lies in the matrix and
-                // below every column of the wave; x rows in the wave's rows;
-                // batches cover the rows exactly, in order
+            if (fast_walk(w, rb)) {
+                // the fast walk: every Y and x row it reads lies in the
+                // wave's rows; batches cover the rows exactly, in order
                 replay_fast(w, rb, loads, xloads, batches);
-                for (int64_t y : loads) {
-                    CHECK(y >= w.ib0 && y < n && y <= w.rw1 + 3, fmt, CASE);
-                    CHECK(y >= w.rw1 || y < w.row1, fmt, CASE);
-                    if (y >= w.rw1) CHECK(y > w.jw0 + 63, fmt, CASE);
-                }
+                for (int64_t y : loads) CHECK(y >= w.ib0 && y < w.rw1 && y < n, fmt, CASE);
                 for (int64_t x : xloads) CHECK(x >= w.ib0 && x < w.rw1, fmt, CASE);
                 CHECK((int64_t)batches.size() * rb == w.rw1 - w.ib0, fmt, CASE);
                 for (size_t b = 0; b < batches.size(); ++b)
