@@ -22,6 +22,10 @@ the sweep kernel's roofline (each launch of a second pass of the same K
 steps timed by HIP events attached to the kernel's own start and end; the
 events stay out of the wall-clock pass, whose steps they would slow) and the
 serial CPU oracle timed on a bounded sample on this host.
+
+Every timed pass follows W warm-up evaluations, continued until at least
+MIN_WARMUP_S seconds of warm-up have run (the GPU clock settles only after
+some hundreds of milliseconds of sustained work; `warmup_min_s` in the line).
 """
 from __future__ import annotations
 
@@ -80,12 +84,34 @@ class HipEvents:
         self.hip.hipEventDestroy(ctypes.c_void_p(e))
 
 
-def timed_evals(P, x, sigma, steps, warmup, events):
+# Untimed evaluations run before each timed pass for at least this long (on
+# top of the W warm-up steps): the GPU's clock takes a few hundred
+# milliseconds of sustained work to settle, and a pass timed before that
+# measures the ramp (at N=5392, 20 warm-up evaluations are about 1 ms).
+MIN_WARMUP_S = 0.3
+
+
+def settle(fn, min_s=None):
+    """Run fn (one untimed unit of GPU work) until min_s seconds have passed."""
+    import torch
+
+    min_s = MIN_WARMUP_S if min_s is None else min_s
+    t0 = time.perf_counter()
+    while True:
+        fn()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= min_s:
+            return
+
+
+def timed_evals(P, x, sigma, steps, warmup, events, min_warmup_s=None):
     """K fused evaluations timed by the wall clock between two device
     synchronisations, then K more with HIP events attached to each sweep
     launch (the kernel's own start and end; attaching them costs the step a
-    few microseconds, so they stay out of the wall-clock pass).  Returns
-    (wall ms per eval, mean sweep ms, median sweep ms, outputs)."""
+    few microseconds, so they stay out of the wall-clock pass).  W warm-up
+    evaluations come first, continued until min_warmup_s of warm-up has
+    passed.  Returns (wall ms per eval, mean sweep ms, median sweep ms,
+    outputs)."""
     import torch
     from paper_1905_04582_amd import api
 
@@ -93,9 +119,15 @@ def timed_evals(P, x, sigma, steps, warmup, events):
     L = torch.empty((), dtype=torch.float64, device=x.device)
     ds = torch.empty((), dtype=torch.float64, device=x.device)
     sig = torch.tensor(sigma, dtype=torch.float64, device=x.device)
+    min_warmup_s = MIN_WARMUP_S if min_warmup_s is None else min_warmup_s
+    tw = time.perf_counter()
     for _ in range(warmup):
         P.gradient(x, sig, grad=g, loglik=L, dsigma=ds)
     torch.cuda.synchronize()
+    while time.perf_counter() - tw < min_warmup_s:
+        for _ in range(50):
+            P.gradient(x, sig, grad=g, loglik=L, dsigma=ds)
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         P.gradient(x, sig, grad=g, loglik=L, dsigma=ds)
@@ -332,10 +364,14 @@ def heldout_lpd(prob, xd, sigma, dev, draws=100, per_pass=10):
 
 
 def main():
+    global MIN_WARMUP_S
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--min-warmup-s", type=float, default=MIN_WARMUP_S,
+                    help="least seconds of warm-up before each timed pass (0: W steps only, "
+                         "e.g. under a profiler)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-evals", type=int, default=10)
     ap.add_argument("--only", choices=("fp64", "fp32", "fp64-plain", "fp32-plain", "lpd"),
@@ -357,6 +393,7 @@ def main():
                     help="only run plain device copies of MB megabytes (calibrates the HBM "
                          "byte counters) and exit")
     args = ap.parse_args()
+    MIN_WARMUP_S = max(0.0, args.min_warmup_s)
     if args.copy_calibration:
         import torch
         nbytes = args.copy_calibration << 20
@@ -510,12 +547,11 @@ def main():
     for k, sp in enumerate(specs):
         Bt.set_x(k, xs[k])
         Bt.sigma[k] = sp["sigma"]
+    settle(Bt.eval)
     t0 = time.perf_counter()
     tune_rec = Bt.autotune()
     tune_s = time.perf_counter() - t0
-    for _ in range(3):
-        Bt.eval()
-    torch.cuda.synchronize()
+    settle(Bt.eval)
     t0 = time.perf_counter()
     for _ in range(20):
         Bt.eval()
@@ -533,9 +569,7 @@ def main():
         B.set_x(k, xs[k])
         B.sigma[k] = sp["sigma"]
     bpairs = sum(sp["n"] * (sp["n"] - 1) // 2 for sp in specs)
-    for _ in range(3):
-        B.eval()
-    torch.cuda.synchronize()
+    settle(B.eval)
     breps = 20
     t0 = time.perf_counter()
     for _ in range(breps):
@@ -640,6 +674,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_min_s": MIN_WARMUP_S,
         "ms_per_step": round(wall64, 5),
         "higher_is_better": True,
         "scaling": "weak",

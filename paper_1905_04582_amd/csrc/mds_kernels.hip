@@ -138,57 +138,52 @@ __device__ void finalize_scalars(const FinalizeArgs& a, double scale)
 }
 
 // The gradient part for element block `blk` (64 consecutive elements).
+// Indices are 32-bit: n D < 2^31 (the host bounds n through Y's leading
+// dimension) and tile and row-block counts are below 2^31.
 __device__ void finalize_elements(const FinalizeArgs& a, int D, int64_t blk, double scale)
 {
     __shared__ double part[kFinChunks][kWave];
     const int lane = threadIdx.x % kWave;
     const int chunk = threadIdx.x / kWave;
-    const int64_t e = blk * kWave + lane;
-    const bool live = e < a.n * D;
+    const uint32_t e = (uint32_t)blk * kWave + lane;
+    const bool live = e < (uint32_t)(a.n * D);
     const int br = a.br, cw = a.cw;
+    const int lbr = __builtin_ctz((unsigned)br), lcw = __builtin_ctz((unsigned)cw);
 
     double s = 0.0;
-    int64_t k = 0;
+    uint32_t k = 0;
     int d = 0;
     if (live) {
-        k = e / D;
-        d = (int)(e - k * D);
-        const int r = (int)(k / br);
-        const int64_t roff = k - (int64_t)r * br;
+        k = e / (uint32_t)D;
+        d = (int)(e - k * (uint32_t)D);
+        const int r = (int)(k >> lbr);
+        const uint32_t roff = k & (uint32_t)(br - 1);
         const int64_t t0 = tiles_before(r, br, cw);
-        const int64_t nrow = tiles_in_row_block(r, br, cw);
-        const int c = (int)(k / cw);
-        const int64_t coff = k - (int64_t)c * cw;
+        const int nrow = (int)tiles_in_row_block(r, br, cw);
+        const int c = (int)(k >> lcw);
+        const uint32_t coff = k & (uint32_t)(cw - 1);
         const int rb0 = first_row_block_of_column(c, br, cw);
-        const int64_t total = nrow + (a.nrb - rb0);
-        // items chunk, chunk + kFinChunks, ... of the list (row-side
-        // partials of row block r, then column-side partials of column
-        // block c from row block rb0 on), added in list order; kFinUnroll
-        // loads are issued before their adds
-        // Items i0, i0 + kFinChunks, ... < cnt of a strided list, added in
-        // order.  Loads are unconditional (index clamped into the list, an
-        // item past the end replaced by 0), so each batch of kFinUnroll
-        // loads is in flight together.
-        auto add_list = [&](const double* base, int64_t step, int64_t i0, int64_t cnt) {
-            for (; i0 < cnt; i0 += kFinUnroll * kFinChunks) {
-                double v[kFinUnroll];
+        const int total = nrow + (a.nrb - rb0);
+        // The element's list: the row-side partials of row k over the nrow
+        // tiles of its row block, then the column-side partials of column k
+        // over row blocks rb0 .. nrb-1.  Chunk `chunk` adds items chunk,
+        // chunk + kFinChunks, ... in list order.  Loads are unconditional
+        // (index clamped into the list, an item past the end replaced by 0),
+        // so each batch of kFinUnroll loads -- row and column items alike --
+        // is in flight together.
+        const double* rbase = a.rowpart + ((t0 * br + roff) * D + d);
+        const double* cbase = a.colpart + ((((int64_t)c * a.nrb + rb0) * cw + coff) * D + d);
+        const int64_t rstep = (int64_t)br * D, cstep = (int64_t)cw * D;
+        for (int i0 = chunk; i0 < total; i0 += kFinUnroll * kFinChunks) {
+            double v[kFinUnroll];
 #pragma unroll
-                for (int u = 0; u < kFinUnroll; ++u) {
-                    const int64_t q = i0 + u * kFinChunks;
-                    v[u] = base[min(q, cnt - 1) * step];
-                }
-#pragma unroll
-                for (int u = 0; u < kFinUnroll; ++u)
-                    s += (i0 + u * kFinChunks < cnt) ? v[u] : 0.0;
+            for (int u = 0; u < kFinUnroll; ++u) {
+                const int q = min(i0 + u * kFinChunks, total - 1);
+                v[u] = q < nrow ? rbase[q * rstep] : cbase[(q - nrow) * cstep];
             }
-        };
-        add_list(a.rowpart + ((t0 * br + roff) * D + d), (int64_t)br * D, chunk, nrow);
-        // the column items continue the list: the first one of this chunk is
-        // the first list index >= nrow congruent to chunk
-        const int64_t jt = (chunk >= nrow) ? chunk - nrow
-                                           : (kFinChunks - (nrow - chunk) % kFinChunks) % kFinChunks;
-        add_list(a.colpart + ((((int64_t)c * a.nrb + rb0) * cw + coff) * D + d), (int64_t)cw * D,
-                 jt, total - nrow);
+#pragma unroll
+            for (int u = 0; u < kFinUnroll; ++u) s += (i0 + u * kFinChunks < total) ? v[u] : 0.0;
+        }
     }
     part[chunk][lane] = s;
     __syncthreads();

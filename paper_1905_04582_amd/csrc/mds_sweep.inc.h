@@ -40,24 +40,68 @@
 
 namespace mds {
 
+// Cross-lane sums by DPP (the VALU's lane-routing operand modifier): no LDS
+// traffic and no address arithmetic, unlike a shuffle.  dpp<CTRL, ROWS>(v) is
+// the value CTRL routes to this lane; lanes of rows that the mask ROWS leaves
+// out read 0.
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int kDppRowMirror = 0x140;   // lane 15 - l within a row of 16
+constexpr int kDppHalfMirror = 0x141;  // lane 7 - l within each half row
+constexpr int kDppBcast15 = 0x142;     // lane 15 of the row before
+constexpr int kDppBcast31 = 0x143;     // lane 31
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ int dpp(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(dpp<CTRL, ROWS>(__float_as_int(v)));
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)dpp<CTRL, ROWS>((int)(unsigned)b);
+    const unsigned hi = (unsigned)dpp<CTRL, ROWS>((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over each aligned group of G lanes (G = 4, 8 or 16); every lane of a
+// group ends with the same value (each exchange adds two equal pairs of
+// operands in either order).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+    static_assert(G == 4 || G == 8 || G == 16, "group of 4, 8 or 16 lanes");
+    v += dpp<kDppXor1>(v);
+    v += dpp<kDppXor2>(v);
+    if constexpr (G >= 8) v += dpp<kDppHalfMirror>(v);
+    if constexpr (G >= 16) v += dpp<kDppRowMirror>(v);
+    return v;
+}
+
+__device__ __forceinline__ int read_lane63(int v) { return __builtin_amdgcn_readlane(v, 63); }
+__device__ __forceinline__ double read_lane63(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes in a fixed order, returned to every lane: row sums
+// of 16, then row 1 += row 0 and row 3 += row 2, then row 3 += rows 0-1.
 template <typename T>
-__device__ __forceinline__ T shfl_xor_t(T v, int m)
+__device__ __forceinline__ T wave_sum(T v)
 {
-    return __shfl_xor(v, m, kWave);
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-    return v;
-}
-
-__device__ __forceinline__ int wave_sum(int v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-    return v;
+    v = group_sum<16>(v);
+    v += dpp<kDppBcast15, 0xA>(v);
+    v += dpp<kDppBcast31, 0xC>(v);
+    return read_lane63(v);
 }
 
 // Per-pair arithmetic.  T = double: everything in FP64.  T = float: the
@@ -287,8 +331,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
 #pragma unroll
                     for (int k = 0; k < kWave / RG; ++k) sum += src[(size_t)k * RG * D];
                 }
-#pragma unroll
-                for (int m = RG / 2; m >= 1; m >>= 1) sum += shfl_xor_t(sum, m);
+                sum = group_sum<RG>(sum);
                 if (live && h == 0) lrows[(b0 - row0 + orow) * D + odim] = (double)sum * inv_s2;
             }
             batch_reset();
