@@ -51,10 +51,12 @@ constexpr int kDppHalfMirror = 0x141;  // lane 7 - l within each half row
 constexpr int kDppBcast15 = 0x142;     // lane 15 of the row before
 constexpr int kDppBcast31 = 0x143;     // lane 31
 
+// ROWS = 0xF routes a value to every lane (the patterns used here never
+// leave a row), so the lane's old value is not needed (bound_ctrl).
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ int dpp(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, ROWS == 0xF);
 }
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ float dpp(float v)
@@ -237,7 +239,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
     // sigma^2), so a pair past the skip point adds one product to them
     double acc_A = 0.0, acc_L = 0.0, acc_M = 0.0;
     int cnt = 0;
-    const double sig = *a.sigma;
+    // sigma is read-only for the launch: a scalar load
+    const double sig = *(const_f64_ptr)a.sigma;
     const double inv_s = 1.0 / sig;
     const double inv_s2 = inv_s * inv_s;
 
@@ -394,14 +397,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 near = (__builtin_amdgcn_ballot_w64(s2a < thr2) & ma) |
                        (__builtin_amdgcn_ballot_w64(s2b < thr2) & mb);
             }
-            // delta and 1/delta from one reciprocal square root.  A coincident
-            // pair (s2 below the normal range) has no direction: 1/delta is
-            // taken as 0, and delta = s2 * rsqrt(min normal) is 0 for s2 = 0
-            // (tiny otherwise)
+            // delta and 1/delta from one reciprocal square root of s2 clamped
+            // to the smallest normal number.  A coincident pair (s2 = 0) gets
+            // delta = 0 and a gradient term (coefficient) * (x_i - x_j) = 0;
+            // below the normal range the clamp keeps 1/delta finite, and the
+            // term stays below the residual in size, as it is at any distance
             const T rsa = rsqrt_t(fmax(s2a, min_normal<T>()));
             const T rsb = rsqrt_t(fmax(s2b, min_normal<T>()));
-            const T ria = (s2a >= min_normal<T>()) ? rsa : T(0);
-            const T rib = (s2b >= min_normal<T>()) ? rsb : T(0);
             // a pair outside the sums gets residual 0 (and, below, ln Phi =
             // m = 0): all its terms vanish
             const T ra = oka ? fma(-s2a, rsa, ya) : T(0);
@@ -411,7 +413,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             // sigma^2 w (x_i - x_j)/delta = (m sigma - (y - delta)) (x_i -
             // x_j)/delta; far pairs (t past the skip point for every lane of
             // the wave) take m = ln Phi = 0 without evaluating them
-            T ca = -ra * ria, cb = -rb * rib;
+            T ca = -ra * rsa, cb = -rb * rsb;
             if (a.truncated && near) {
                 const T dla = s2a * rsa, dlb = s2b * rsb;
                 T la, mla, lb, mlb;
@@ -423,8 +425,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 bL += la + lb;
                 bM = fma(dla, mla, bM);
                 bM = fma(dlb, mlb, bM);
-                ca = fma(mla * sigT, ria, ca);
-                cb = fma(mlb * sigT, rib, cb);
+                ca = fma(mla * sigT, rsa, ca);
+                cb = fma(mlb * sigT, rsb, cb);
             }
             if (GRAD) {
                 T* st = stage + (size_t)q * SROW + (size_t)lane * D;
