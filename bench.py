@@ -49,11 +49,42 @@ KERNEL_SOURCES = ["mds_sweep.inc.h", "mds_math.h", "mds_coeffs.h", "mds_internal
                   "mds_sweep_f64.hip", "mds_sweep_f32.hip"]
 
 
-def kernel_source_hash() -> str:
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments and with runs of whitespace collapsed
+    (string and character literals kept), so that an edit of the comments
+    alone leaves the hash of the kernel sources unchanged."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def kernel_source_hash(read=None) -> str:
+    """Hash of the sweep kernel's sources, comments aside.  `read(name)`
+    returns a source's text (default: the file under csrc/)."""
+    if read is None:
+        def read(f):
+            with open(os.path.join(ROOT, "paper_1905_04582_amd", "csrc", f)) as fh:
+                return fh.read()
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1905_04582_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        h.update(strip_comments(read(f)).encode())
     return h.hexdigest()[:16]
 
 

@@ -20,8 +20,7 @@ constexpr int kWave = 64;     // CDNA wavefront width
 // work-groups of a launch keep the machine partly idle) without changing the
 // tile.  A tile exists when it can hold a pair with j < i.  With one of br
 // and cw dividing the other, row block r holds a closed-form number of tiles,
-// so a linear tile index maps back to (r, c) by a short binary search on the
-// prefix count.
+// so a linear tile index maps back to (r, c) in closed form (tile_coords).
 struct Tiling {
     int64_t n;
     int br;     // rows per tile

@@ -39,6 +39,19 @@ def test_kernel_source_hash_is_deterministic_and_names_existing_sources():
         assert os.path.isfile(os.path.join(ROOT, "paper_1905_04582_amd", "csrc", f)), f
 
 
+def test_kernel_source_hash_ignores_comments_only():
+    import bench
+    src = {f: "int a = 1; // one\n" for f in bench.KERNEL_SOURCES}
+    h = bench.kernel_source_hash(src.__getitem__)
+    commented = {f: "/* block */ int a = 1;   // another\n" for f in bench.KERNEL_SOURCES}
+    assert bench.kernel_source_hash(commented.__getitem__) == h
+    changed = dict(src)
+    changed[bench.KERNEL_SOURCES[0]] = "int a = 2; // one\n"
+    assert bench.kernel_source_hash(changed.__getitem__) != h
+    # comment markers inside literals are code
+    assert bench.strip_comments('s = "//x"; c = \'/\';') == 's = "//x"; c = \'/\';'
+
+
 def test_committed_counter_file_is_well_formed():
     # the counter figures the bench line quotes: per-form traffic, calibration
     # factor and the fingerprint of the sources they were taken on
