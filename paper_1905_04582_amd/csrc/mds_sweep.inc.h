@@ -250,9 +250,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
         for (int d = 0; d < D; ++d) xj[d] = colok ? a.x[j * a.ldx + d] : 0.0;
         const T sigT = (T)sig, inv_sT = (T)inv_s;
         // skip test on the squared distance: s2 >= (skip point * sigma)^2
-        // means t >= the skip point (to the rounding of the bound)
+        // means t >= the skip point (to the rounding of the bound).  The
+        // model without truncation has no ln Phi and m terms: a negative
+        // bound sends every step past them.
         const double tb = (double)skip_t<T>() * sig;
-        const T thr2 = (T)(tb * tb);
+        const T thr2 = a.truncated ? (T)(tb * tb) : T(-1);
         const T* __restrict__ Y = static_cast<const T*>(a.y);
         // the FP64 special functions' coefficient tables, addressed once
         const tab64_ptr ctab = sizeof(T) == 8 ? tab64() : nullptr;
@@ -414,7 +416,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             // x_j)/delta; far pairs (t past the skip point for every lane of
             // the wave) take m = ln Phi = 0 without evaluating them
             T ca = -ra * rsa, cb = -rb * rsb;
-            if (a.truncated && near) {
+            if (near) {
                 const T dla = s2a * rsa, dlb = s2b * rsb;
                 T la, mla, lb, mlb;
                 trunc_terms2<T>(dla * inv_sT, dlb * inv_sT, la, mla, lb, mlb, ctab);
@@ -444,34 +446,34 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
 
         // The fast walk: the wave's rows are a whole number of staging
         // batches of at least four rows and its x rows are contiguous, so no
-        // row is dead and x of two rows is one scalar load.  The Y prefetch
-        // of the last iteration (rows past rw1) repeats the wave's last row:
-        // its offset is capped by one scalar min.  Two steps of two rows per
-        // iteration take the two register pairs in turn; a batch of RB rows
-        // closes after RB/2 steps.
+        // row is dead and x of two rows is one scalar load.  Each iteration
+        // prefetches the next four rows from one base offset, capped at the
+        // wave's last four rows: the last iteration reads those again (its
+        // values are never used) instead of rows past rw1.  Two steps of two
+        // rows per iteration take the two register pairs in turn; a batch of
+        // RB rows closes after RB/2 steps.
         constexpr int IT = RB > 4 ? RB : 4;
         const bool fast = ((rw1 - ib0) % IT == 0) && (a.ldx == D);
         if (fast) {
-            const uint32_t ylast = (uint32_t)(rw1 - 1 - ib0) * ystep;
-            auto load_fast = [&]() -> T {
-                const T v = load_buf<T>(yres, joff, min(yoff, ylast));
-                yoff += ystep;
-                return v;
-            };
-            T pa0 = load_fast(), pa1 = load_fast();
+            const uint32_t ystep2 = 2 * ystep, ystep3 = 3 * ystep;
+            const uint32_t ycap = (uint32_t)(rw1 - 4 - ib0) * ystep;
+            T pa0 = load_buf<T>(yres, joff, 0), pa1 = load_buf<T>(yres, joff, ystep);
             // keep the issue order: the first pair is consumed first
             __builtin_amdgcn_sched_barrier(0);
-            T pb0 = load_fast(), pb1 = load_fast();
+            T pb0 = load_buf<T>(yres, joff, ystep2), pb1 = load_buf<T>(yres, joff, ystep3);
+            uint32_t ynext = 4 * ystep;  // offset of the row after the loaded ones
             int q = 0;  // staging position of the iteration's first row
 #pragma unroll 1
             for (int ib = ib0; ib < rw1; ib += 4) {
+                const uint32_t yb = min(ynext, ycap);
+                ynext += 4 * ystep;
                 step(fast_walk, ib, q, pa0, pa1);
-                pa0 = load_fast();
-                pa1 = load_fast();
+                pa0 = load_buf<T>(yres, joff, yb);
+                pa1 = load_buf<T>(yres, joff, yb + ystep);
                 if (RB == 2) batch_flush(fast_walk, ib);
                 step(fast_walk, ib + 2, RB == 2 ? 0 : q + 2, pb0, pb1);
-                pb0 = load_fast();
-                pb1 = load_fast();
+                pb0 = load_buf<T>(yres, joff, yb + ystep2);
+                pb1 = load_buf<T>(yres, joff, yb + ystep3);
                 q += 4;
                 if (q >= RB) {
                     batch_flush(fast_walk, ib + 4 - RB);

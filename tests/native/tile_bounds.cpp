@@ -89,37 +89,47 @@ static void replay_walk(const WaveRows& w, int rb, std::vector<int64_t>& yrows,
 
 // The fast walk (taken when the wave's rows are a whole number of
 // iterations of max(rb, 4) rows and x rows are contiguous): Y rows ib0 ..
-// rw1-1, the prefetch past rw1 capped at rw1-1; x rows ib0 .. rw1-1; a batch
-// closed every rb rows.
+// ib0+3 first, then each iteration's four prefetched rows from one base row,
+// capped at rw1-4 (the last iteration reads the wave's last four rows
+// again); x rows ib0 .. rw1-1; a batch closed every rb rows.
 static bool fast_walk(const WaveRows& w, int rb)
 {
     const int it = rb > 4 ? rb : 4;
     return w.active && (w.rw1 - w.ib0) % it == 0;
 }
 
+// `misuse` counts steps whose register pair does not hold the Y rows the
+// step evaluates.
 static void replay_fast(const WaveRows& w, int rb, std::vector<int64_t>& yrows,
-                        std::vector<int64_t>& xrows, std::vector<int64_t>& batches)
+                        std::vector<int64_t>& xrows, std::vector<int64_t>& batches, int& misuse)
 {
     yrows.clear();
     xrows.clear();
     batches.clear();
-    int64_t y = w.ib0;
-    auto load = [&]() {
-        yrows.push_back(y < w.rw1 - 1 ? y : w.rw1 - 1);
-        ++y;
-    };
-    for (int k = 0; k < 4; ++k) load();
+    misuse = 0;
+    for (int k = 0; k < 4; ++k) yrows.push_back(w.ib0 + k);
+    int64_t pa0 = w.ib0, pa1 = w.ib0 + 1, pb0 = w.ib0 + 2, pb1 = w.ib0 + 3;
+    int64_t next = w.ib0 + 4;
+    const int64_t cap = w.rw1 - 4;
     int q = 0;
     for (int64_t ib = w.ib0; ib < w.rw1; ib += 4) {
+        const int64_t base = next < cap ? next : cap;
+        next += 4;
         xrows.push_back(ib);
         xrows.push_back(ib + 1);
-        load();
-        load();
+        misuse += (pa0 != ib || pa1 != ib + 1);
+        pa0 = base;
+        pa1 = base + 1;
+        yrows.push_back(pa0);
+        yrows.push_back(pa1);
         if (rb == 2) batches.push_back(ib);
         xrows.push_back(ib + 2);
         xrows.push_back(ib + 3);
-        load();
-        load();
+        misuse += (pb0 != ib + 2 || pb1 != ib + 3);
+        pb0 = base + 2;
+        pb1 = base + 3;
+        yrows.push_back(pb0);
+        yrows.push_back(pb1);
         q += 4;
         if (q >= rb) {
             batches.push_back(ib + 4 - rb);
@@ -219,7 +229,9 @@ static void check_case(int64_t n, const Tile& tl, int rb, bool per_pair, bool sa
             if (fast_walk(w, rb)) {
                 // the fast walk: every Y and x row it reads lies in the
                 // wave's rows; batches cover the rows exactly, in order
-                replay_fast(w, rb, loads, xloads, batches);
+                int misuse = 0;
+                replay_fast(w, rb, loads, xloads, batches, misuse);
+                CHECK(misuse == 0, fmt, CASE);
                 for (int64_t y : loads) CHECK(y >= w.ib0 && y < w.rw1 && y < n, fmt, CASE);
                 for (int64_t x : xloads) CHECK(x >= w.ib0 && x < w.rw1, fmt, CASE);
                 CHECK((int64_t)batches.size() * rb == w.rw1 - w.ib0, fmt, CASE);
