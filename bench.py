@@ -199,6 +199,53 @@ def cold_sweep_ms(P, x, sigma, reps, events):
     return sorted(out)[len(out) // 2]
 
 
+def batch_problems(dev):
+    """The batched workload: 64 independent problems, N ~ U[500, 8000], D in
+    {2, 4, 6}, sigma ~ U(0.2, 1), 10% missing, FP32 Y drawn on the device.
+    Returns (specs, Y list, evaluation points, generating configurations)."""
+    import torch
+
+    from paper_1905_04582_amd import synth
+
+    specs = synth.batch_specs(64, seed=64)
+    ys, xs, xts = [], [], []
+    for sp in specs:
+        xtk, xk, yk = synth.device_problem(sp["n"], sp["d"], sp["sigma"], seed=sp["seed"],
+                                           device=dev, dtype=torch.float32, missing=sp["missing"])
+        ys.append(yk)
+        xs.append(xk)
+        xts.append(xtk)
+    return specs, ys, xs, xts
+
+
+def only_batch(args):
+    """The batched form alone (library default tiles), for profiler runs:
+    W + K evaluations of the whole batch, one JSON line."""
+    import torch
+
+    from paper_1905_04582_amd import api
+
+    dev = torch.device("cuda:0")
+    specs, ys, xs, xts = batch_problems(dev)
+    B = api.MDSBatch([dict(y=yk, d=sp["d"], order=xtk) for yk, xtk, sp in zip(ys, xts, specs)],
+                     torch.float32, dev)
+    del ys
+    for k, sp in enumerate(specs):
+        B.set_x(k, xs[k])
+        B.sigma[k] = sp["sigma"]
+    for _ in range(args.warmup):
+        B.eval()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.eval()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
+    pairs = sum(sp["n"] * (sp["n"] - 1) // 2 for sp in specs)
+    print(json.dumps({"form": "batch", "steps": args.steps, "ms_per_batch_eval": ms,
+                      "pairs": pairs, "tiles": [list(t) for t in B.tiles]}), flush=True)
+
+
 def progress(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -405,7 +452,7 @@ def main():
                          "e.g. under a profiler)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-evals", type=int, default=10)
-    ap.add_argument("--only", choices=("fp64", "fp32", "fp64-plain", "fp32-plain", "lpd"),
+    ap.add_argument("--only", choices=("fp64", "fp32", "fp64-plain", "fp32-plain", "lpd", "batch"),
                     default=None,
                     help="time one form only (for profiler runs); prints a short JSON line")
     ap.add_argument("--n-sweep", action="store_true",
@@ -449,6 +496,9 @@ def main():
         import torch
         torch.cuda.init()      # the HIP runtime torch loads is the one the events use
         n_sweep(args, HipEvents())
+        return
+    if args.only == "batch":
+        only_batch(args)
         return
 
     import numpy as np
@@ -561,14 +611,7 @@ def main():
     # sigma ~ U(0.2, 1), 10% missing, FP32 Y drawn in device memory; one
     # persistent sweep and one finalize per evaluation of the whole batch, and
     # 20-step leapfrog trajectories of every problem captured as one graph
-    specs = synth.batch_specs(64, seed=64)
-    ys, xs, xts = [], [], []
-    for sp in specs:
-        xtk, xk, yk = synth.device_problem(sp["n"], sp["d"], sp["sigma"], seed=sp["seed"],
-                                           device=dev, dtype=torch.float32, missing=sp["missing"])
-        ys.append(yk)
-        xs.append(xk)
-        xts.append(xtk)
+    specs, ys, xs, xts = batch_problems(dev)
     # the batch with its tiles picked by the batch autotuner: the plan from
     # the cached per-(D, N bucket) entries, then MDSBatch.autotune() timing
     # that plan, the library default and the other wave layouts on this

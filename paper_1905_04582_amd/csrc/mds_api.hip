@@ -943,6 +943,12 @@ int mds_log_phi(const double* t, double* lnphi, double* mills, int64_t count, in
 namespace {
 
 constexpr int kFinElemsPerBlock = 64;  // finalize element block (one wave wide)
+
+// finalize element blocks of one problem of a batch (none without a gradient)
+int64_t batch_elem_blocks(const mds_problem_desc& q)
+{
+    return q.grad ? (q.n * q.d + kFinElemsPerBlock - 1) / kFinElemsPerBlock : 0;
+}
 constexpr int32_t kBatchLeapfrogReady = 1;  // mds_batch_plan.flags bit 0
 // rows per tile of a batched problem whose descriptor says 0, and the
 // batch's waves when tile_waves is 0: 128-row tiles two column groups wide
@@ -955,6 +961,8 @@ constexpr int kBatchDefaultWaves = 2;
 struct BatchLayout {
     size_t table;   // BatchProblem[count]
     size_t cursor;  // uint64 tile cursor
+    size_t blkmap;  // int32[blocks]: the problem of each finalize element block
+    int64_t blocks;
     std::vector<size_t> ws;  // per-problem partial buffers
     std::vector<Tiling> tilings;
     size_t total;
@@ -973,6 +981,11 @@ static int batch_layout(const mds_problem_desc* descs, int32_t count, int32_t y_
     off = align_up(off + sizeof(BatchProblem) * (size_t)count, 256);
     L->cursor = off;
     off = align_up(off + sizeof(unsigned long long), 256);
+    // element blocks of the problems that want a gradient
+    L->blocks = 0;
+    for (int32_t k = 0; k < count; ++k) L->blocks += batch_elem_blocks(descs[k]);
+    L->blkmap = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)L->blocks, 256);
     L->ws.resize(count);
     L->tilings.resize(count);
     *max_lds = 0;
@@ -1004,6 +1017,15 @@ static int batch_layout(const mds_problem_desc* descs, int32_t count, int32_t y_
     }
     L->total = off;
     return MDS_OK;
+}
+
+// the block map of an initialised batch: after the table and the cursor
+// (the layout of batch_layout)
+static const int32_t* batch_blkmap(const mds_batch_plan* plan)
+{
+    const size_t off = align_up(align_up(sizeof(BatchProblem) * (size_t)plan->count, 256) +
+                                    sizeof(unsigned long long), 256);
+    return reinterpret_cast<const int32_t*>(static_cast<const char*>(plan->workspace) + off);
 }
 
 static int device_cu_count(int* cus)
@@ -1059,9 +1081,10 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
     // waves per work-group (column x row waves, common to the batch)
     const int waves = L.tilings[0].waves;
 
-    // host image of [table | cursor]; copied in one transfer
-    std::vector<unsigned char> img(L.cursor + sizeof(unsigned long long), 0);
+    // host image of [table | cursor | block map]; copied in one transfer
+    std::vector<unsigned char> img(L.blkmap + sizeof(int32_t) * (size_t)L.blocks, 0);
     BatchProblem* tab = reinterpret_cast<BatchProblem*>(img.data());
+    int32_t* blkmap = reinterpret_cast<int32_t*>(img.data() + L.blkmap);
     char* base = static_cast<char*>(workspace);
     int64_t tiles = 0, blocks = 0;
     int leapfrog_ready = 1;
@@ -1076,7 +1099,7 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
         P.tile_base = tiles;
         P.ntiles = t.ntiles;
         P.blk_base = blocks;
-        P.nblk = q.grad ? (q.n * q.d + kFinElemsPerBlock - 1) / kFinElemsPerBlock : 0;
+        P.nblk = batch_elem_blocks(q);
         P.scale = q.scale;
         P.grad = q.grad;
         P.ldg = q.ldg;
@@ -1089,6 +1112,7 @@ int mds_batch_init(const mds_problem_desc* descs, int32_t count, int32_t y_dtype
         P.step = q.step;
         tab[k] = P;
         if (!q.step || !q.loglik || (q.n > 0 && (!q.p || !q.grad))) leapfrog_ready = 0;
+        for (int64_t b = 0; b < P.nblk; ++b) blkmap[blocks + b] = k;
         tiles += t.ntiles;
         blocks += P.nblk;
     }
@@ -1132,8 +1156,8 @@ int mds_batch_eval(const mds_batch_plan* plan, int32_t want_grad, hipStream_t st
     if (e != hipSuccess) return hip_fail(e, "batch sweep launch");
     if (g_ev_after && (e = hipEventRecord(g_ev_after, stream)) != hipSuccess)
         return hip_fail(e, "event record");
-    e = launch_batch_finalize(probs, plan->count, want_grad ? plan->elem_blocks : 0, cursor, 0.0,
-                              0, 0, stream);
+    e = launch_batch_finalize(probs, batch_blkmap(plan), plan->count,
+                              want_grad ? plan->elem_blocks : 0, cursor, 0.0, 0, 0, stream);
     if (e != hipSuccess) return hip_fail(e, "batch finalize launch");
     return MDS_OK;
 }
@@ -1157,8 +1181,8 @@ int mds_batch_leapfrog(const mds_batch_plan* plan, int32_t n_steps, int32_t cach
                                             plan->total_tiles, cursor, plan->tile_waves,
                                             plan->lds_bytes, plan->grid, stream);
         if (err != hipSuccess) return hip_fail(err, "batch sweep launch");
-        err = launch_batch_finalize(probs, plan->count, plan->elem_blocks, cursor, mult, kick,
-                                    drift, stream);
+        err = launch_batch_finalize(probs, batch_blkmap(plan), plan->count, plan->elem_blocks,
+                                    cursor, mult, kick, drift, stream);
         if (err != hipSuccess) return hip_fail(err, "batch finalize launch");
         return MDS_OK;
     };
@@ -1168,8 +1192,8 @@ int mds_batch_leapfrog(const mds_batch_plan* plan, int32_t n_steps, int32_t cach
     const bool fuse_first = !cache_valid && n_steps > 0;
     if (!cache_valid && (st = evaluate(0.5, fuse_first ? 1 : 0, fuse_first ? 1 : 0))) return st;
     if (n_steps > 0 && !fuse_first) {
-        hipError_t e = launch_batch_kick_drift(probs, plan->count, plan->elem_blocks, 0.5, 1,
-                                               stream);
+        hipError_t e = launch_batch_kick_drift(probs, batch_blkmap(plan), plan->count,
+                                               plan->elem_blocks, 0.5, 1, stream);
         if (e != hipSuccess) return hip_fail(e, "batch kick launch");
     }
     for (int s = 1; s <= n_steps; ++s) {

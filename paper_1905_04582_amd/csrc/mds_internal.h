@@ -306,11 +306,13 @@ int batch_sweep_blocks_per_cu(int y_dtype, bool grad, int maxd, int waves, size_
 // kick_mult / kick / drift: the leapfrog update fused into the finalize
 // (p += kick_mult eps g when kick, then x += eps p when drift); 0, 0, 0 for
 // a plain evaluation
-hipError_t launch_batch_finalize(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
-                                 unsigned long long* cursor, double kick_mult, int kick, int drift,
-                                 hipStream_t s);
+// blkmap: the problem of each finalize element block
+hipError_t launch_batch_finalize(const BatchProblem* probs, const int32_t* blkmap, int32_t count,
+                                 int64_t elem_blocks, unsigned long long* cursor, double kick_mult,
+                                 int kick, int drift, hipStream_t s);
 // p += kick_mult eps g, then x += eps p (drift != 0), every problem's elements
-hipError_t launch_batch_kick_drift(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
-                                   double kick_mult, int drift, hipStream_t s);
+hipError_t launch_batch_kick_drift(const BatchProblem* probs, const int32_t* blkmap,
+                                   int32_t count, int64_t elem_blocks, double kick_mult, int drift,
+                                   hipStream_t s);
 
 }  // namespace mds

@@ -220,22 +220,16 @@ __global__ void __launch_bounds__(kWave * kFinChunks) finalize_kernel(FinalizeAr
 // per problem.  Also rewinds the persistent sweep's tile cursor for the next
 // call (this kernel runs after the sweep on the same stream).
 __global__ void __launch_bounds__(kWave * kFinChunks)
-    batch_finalize_kernel(const BatchProblem* __restrict__ probs, int32_t count,
-                          int64_t elem_blocks, unsigned long long* cursor, double kick_mult,
-                          int kick, int drift)
+    batch_finalize_kernel(const BatchProblem* __restrict__ probs,
+                          const int32_t* __restrict__ blkmap, int32_t count, int64_t elem_blocks,
+                          unsigned long long* cursor, double kick_mult, int kick, int drift)
 {
     int64_t b = blockIdx.x;
     int k;
     if (b < elem_blocks) {
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (probs[mid].blk_base <= b)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        k = lo;
+        // the block's problem from the map the batch set-up wrote (one load
+        // instead of a search over the problem table)
+        k = blkmap[b];
     } else {
         k = (int)(b - elem_blocks);
         if (k == 0 && threadIdx.x == 0) *cursor = 0ull;
@@ -273,32 +267,24 @@ __global__ void __launch_bounds__(kWave * kFinChunks)
         finalize_scalars(a, scale);
 }
 
-hipError_t launch_batch_finalize(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
-                                 unsigned long long* cursor, double kick_mult, int kick, int drift,
-                                 hipStream_t s)
+hipError_t launch_batch_finalize(const BatchProblem* probs, const int32_t* blkmap, int32_t count,
+                                 int64_t elem_blocks, unsigned long long* cursor, double kick_mult,
+                                 int kick, int drift, hipStream_t s)
 {
     const unsigned nblk = (unsigned)(elem_blocks + count);
     hipLaunchKernelGGL(batch_finalize_kernel, dim3(nblk), dim3(kWave * kFinChunks), 0, s, probs,
-                       count, elem_blocks, cursor, kick_mult, kick, drift);
+                       blkmap, count, elem_blocks, cursor, kick_mult, kick, drift);
     return hipGetLastError();
 }
 
 // one work-group of 64 threads per finalize element block (64 consecutive
 // elements of one problem): p += kick_mult eps g, then x += eps p
 __global__ void __launch_bounds__(kWave)
-    batch_kick_drift_kernel(const BatchProblem* __restrict__ probs, int32_t count,
-                            double kick_mult, int drift)
+    batch_kick_drift_kernel(const BatchProblem* __restrict__ probs,
+                            const int32_t* __restrict__ blkmap, double kick_mult, int drift)
 {
     const int64_t b = blockIdx.x;
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].blk_base <= b)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const BatchProblem& P = probs[lo];
+    const BatchProblem& P = probs[blkmap[b]];
     const int D = P.d;
     const int64_t e = (b - P.blk_base) * kWave + threadIdx.x;
     if (e >= P.sweep.n * D) return;
@@ -311,12 +297,14 @@ __global__ void __launch_bounds__(kWave)
     if (drift) P.x[k * P.sweep.ldx + d] += eps * pn;
 }
 
-hipError_t launch_batch_kick_drift(const BatchProblem* probs, int32_t count, int64_t elem_blocks,
-                                   double kick_mult, int drift, hipStream_t s)
+hipError_t launch_batch_kick_drift(const BatchProblem* probs, const int32_t* blkmap,
+                                   int32_t count, int64_t elem_blocks, double kick_mult, int drift,
+                                   hipStream_t s)
 {
+    (void)count;
     if (elem_blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(batch_kick_drift_kernel, dim3((unsigned)elem_blocks), dim3(kWave), 0, s,
-                       probs, count, kick_mult, drift);
+                       probs, blkmap, kick_mult, drift);
     return hipGetLastError();
 }
 
