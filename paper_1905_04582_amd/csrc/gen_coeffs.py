@@ -11,7 +11,9 @@ Everything is computed here from the mathematics with mpmath (50 digits):
   least squares (Loeb's linearisation with Lawson weights, which converges
   towards the minimax fit in relative error).  Z is where exp(-z^2) leaves the
   range of the format (FP64: z^2 > 745; FP32: z^2 > 104), beyond which the
-  product exp(-z^2) erfcx(z) is 0 whatever erfcx is.
+  product exp(-z^2) erfcx(z) is 0 whatever erfcx is.  A second, shorter FP64
+  rational covers [2.1, 6.6] only (t = z sqrt 2 from 2.97 to 9.33), for the
+  wavefronts whose pairs all lie at t >= 3.
 * exp(r) on |r| <= ln(2)/2 by its Taylor polynomial (FP64), after the
   Cody-Waite reduction x = k ln 2 + r with ln 2 split into a head with 20
   trailing zero bits and a tail.
@@ -40,8 +42,9 @@ def erfcx(z):
     return mp.erfc(z) * mp.exp(z * z)
 
 
-def fit_erfcx(n: int, zmax, npts: int = 500, iters: int = 12):
-    xs = [zmax * (mp.mpf(1) / 2 - mp.cos(mp.pi * (k + mp.mpf(1) / 2) / npts) / 2)
+def fit_erfcx(n: int, zmax, npts: int = 500, iters: int = 12, zmin=0):
+    zmin = mp.mpf(zmin)
+    xs = [zmin + (zmax - zmin) * (mp.mpf(1) / 2 - mp.cos(mp.pi * (k + mp.mpf(1) / 2) / npts) / 2)
           for k in range(npts)]
     ys = [erfcx(x) for x in xs]
     w = [mp.mpf(1)] * npts
@@ -85,8 +88,8 @@ def horner_np(c, x, dt):
     return acc
 
 
-def check_erfcx(p, q, zmax, dt):
-    zs = np.linspace(0.0, float(zmax), 4001).astype(dt)
+def check_erfcx(p, q, zmax, dt, zmin=0.0):
+    zs = np.linspace(float(zmin), float(zmax), 4001).astype(dt)
     P = horner_np([float(v) for v in p], zs, dt)
     Q = horner_np([float(v) for v in q], zs, dt)
     r = (P.astype(np.longdouble) / Q.astype(np.longdouble))
@@ -162,6 +165,17 @@ def main():
     lines.append(f"constexpr float kErfcxZmax32 = {float(z32)!r}f;")
     lines.append(emit_array("kErfcxP32", p32, np.float32))
     lines.append(emit_array("kErfcxQ32", q32, np.float32))
+    # the far range: every pair of the wavefront at t >= 3
+    zf0, zf1, tfar = mp.mpf("2.1"), mp.mpf("6.6"), 3.0
+    pf, qf = fit_erfcx(7, zf1, zmin=zf0)
+    ef = check_erfcx(pf, qf, zf1, np.float64, zmin=zf0)
+    lines.append(f"// erfcx(z) ~ P(z)/Q(z) on [{zf0}, {zf1}] (FP64, t = z sqrt 2 >= {tfar} up to "
+                 f"rounding); worst relative error {ef:.2e} with FP64 coefficients")
+    lines.append(f"constexpr double kFarT = {tfar!r};")
+    lines.append(f"constexpr double kErfcxFarZmin64 = {float(zf0)!r};")
+    lines.append(f"constexpr double kErfcxFarZmax64 = {float(zf1)!r};")
+    lines.append(emit_array("kErfcxFarP64", pf, np.float64))
+    lines.append(emit_array("kErfcxFarQ64", qf, np.float64))
 
     # ---- exp: Cody-Waite split of ln 2 and Taylor coefficients
     ln2 = mp.log(2)
@@ -196,7 +210,7 @@ def main():
     lines += ["}  // namespace mds", ""]
     with open(OUT, "w") as f:
         f.write("\n".join(lines))
-    print(f"wrote {OUT}: erfcx64 {e64:.2e} erfcx32 {e32:.2e} exp {ex_err:.2e} "
+    print(f"wrote {OUT}: erfcx64 {e64:.2e} erfcx32 {e32:.2e} erfcx-far {ef:.2e} exp {ex_err:.2e} "
           f"atanh64 {ea64:.2e} atanh32 {ea32:.2e}")
     return 0
 

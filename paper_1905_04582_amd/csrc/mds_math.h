@@ -50,11 +50,18 @@ __device__ __forceinline__ double fma_sc(double acc, double x, double c)
 
 // The FP64 coefficient tables in one constant-memory object, so that one
 // scalar base address reaches every coefficient by an immediate offset.
+// terms of the series -log1p(-q)/q = sum_k q^k/(k+1) kept for q <= 1.5e-3
+// (t >= 2.97): the next term is below 2e-18 of the sum
+constexpr int kLog1pN = 6;
+
 struct CoefTables64 {
     double exp[sizeof(kExpC64) / sizeof(double)];
     double erfcx_p[sizeof(kErfcxP64) / sizeof(double)];
     double erfcx_q[sizeof(kErfcxQ64) / sizeof(double)];
     double atanh[sizeof(kAtanhA64) / sizeof(double)];
+    double erfcx_fp[sizeof(kErfcxFarP64) / sizeof(double)];
+    double erfcx_fq[sizeof(kErfcxFarQ64) / sizeof(double)];
+    double log1p[kLog1pN];  // 1/(k+1), k = 0 .. kLog1pN-1
 };
 
 constexpr CoefTables64 make_tables64()
@@ -64,6 +71,11 @@ constexpr CoefTables64 make_tables64()
     for (size_t k = 0; k < sizeof(kErfcxP64) / sizeof(double); ++k) t.erfcx_p[k] = kErfcxP64[k];
     for (size_t k = 0; k < sizeof(kErfcxQ64) / sizeof(double); ++k) t.erfcx_q[k] = kErfcxQ64[k];
     for (size_t k = 0; k < sizeof(kAtanhA64) / sizeof(double); ++k) t.atanh[k] = kAtanhA64[k];
+    for (size_t k = 0; k < sizeof(kErfcxFarP64) / sizeof(double); ++k)
+        t.erfcx_fp[k] = kErfcxFarP64[k];
+    for (size_t k = 0; k < sizeof(kErfcxFarQ64) / sizeof(double); ++k)
+        t.erfcx_fq[k] = kErfcxFarQ64[k];
+    for (int k = 0; k < kLog1pN; ++k) t.log1p[k] = 1.0 / (k + 1);
     return t;
 }
 
@@ -138,6 +150,8 @@ constexpr int kExpN = sizeof(kExpC64) / sizeof(double);
 constexpr int kErfcxPN = sizeof(kErfcxP64) / sizeof(double);
 constexpr int kErfcxQN = sizeof(kErfcxQ64) / sizeof(double);
 constexpr int kAtanhN = sizeof(kAtanhA64) / sizeof(double);
+constexpr int kErfcxFarPN = sizeof(kErfcxFarP64) / sizeof(double);
+constexpr int kErfcxFarQN = sizeof(kErfcxFarQ64) / sizeof(double);
 
 // exp(-t^2/2) for t >= 0; 0 once the value leaves the FP64 range
 __device__ __forceinline__ double exp_neg_half_sq(double t, tab64_ptr tb)
@@ -198,6 +212,47 @@ __device__ __forceinline__ void trunc_terms2_f64(double t1, double t2, double& l
     lnphi2 = -2.0 * s2 * A2;
     mills1 = (4.0 * kInvSqrt2Pi) * (e1 * Q1) * (d11 * rr1);
     mills2 = (4.0 * kInvSqrt2Pi) * (e2 * Q2) * (d12 * rr2);
+}
+
+// The same two pairs of values when both t lie at or past kFarT (up to the
+// rounding of the caller's test, t >= 2.97): q = 1 - Phi(t) = exp(-t^2/2)
+// erfcx(t/sqrt 2)/2 <= 1.5e-3 from the far-range rational, ln Phi = log1p(-q)
+// by its series in q (kLog1pN terms), and phi/Phi = phi(t) / (1 - q) by the
+// geometric series (terms to q^6, the next below 1.2e-17).  z is capped at
+// the top of the fit range: past it exp(-t^2/2) < 1e-18, and the values are
+// negligible however erfcx is approximated.
+__device__ __forceinline__ void trunc_terms2_far_f64(double t1, double t2, double& lnphi1,
+                                                     double& mills1, double& lnphi2,
+                                                     double& mills2, tab64_ptr tb)
+{
+    const double x1 = fmax(-0.5 * (t1 * t1), -760.0);
+    const double x2 = fmax(-0.5 * (t2 * t2), -760.0);
+    const double k1 = rint(x1 * kLog2e), k2 = rint(x2 * kLog2e);
+    double r1 = fma(k1, -kLn2Head, x1), r2 = fma(k2, -kLn2Head, x2);
+    r1 = fma(k1, -kLn2Tail, r1);
+    r2 = fma(k2, -kLn2Tail, r2);
+    double p1, p2;
+    horner2_tab<kExpN>(tb->exp, r1, r2, p1, p2);
+    const double e1 = ldexp(p1, (int)k1), e2 = ldexp(p2, (int)k2);
+    const double z1 = fmin(t1 * kInvSqrt2, kErfcxFarZmax64);
+    const double z2 = fmin(t2 * kInvSqrt2, kErfcxFarZmax64);
+    double P1, P2, Q1, Q2;
+    horner2_tab<kErfcxFarPN>(tb->erfcx_fp, z1, z2, P1, P2);
+    horner2_tab<kErfcxFarQN>(tb->erfcx_fq, z1, z2, Q1, Q2);
+    const double q1 = 0.5 * (e1 * P1) * rcp_f64(Q1);
+    const double q2 = 0.5 * (e2 * P2) * rcp_f64(Q2);
+    double L1, L2;
+    horner2_tab<kLog1pN>(tb->log1p, q1, q2, L1, L2);
+    lnphi1 = -q1 * L1;
+    lnphi2 = -q2 * L2;
+    double g1 = 1.0, g2 = 1.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        g1 = fma(g1, q1, 1.0);
+        g2 = fma(g2, q2, 1.0);
+    }
+    mills1 = kInvSqrt2Pi * e1 * g1;
+    mills2 = kInvSqrt2Pi * e2 * g2;
 }
 
 // ---------------------------------------------------------------- FP32 --

@@ -255,6 +255,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
         // bound sends every step past them.
         const double tb = (double)skip_t<T>() * sig;
         const T thr2 = a.truncated ? (T)(tb * tb) : T(-1);
+        // FP64: a step whose pairs all lie at t >= kFarT takes the shorter
+        // far-range forms of the special functions
+        const double tf = kFarT * sig;
+        const T thrf = (T)(tf * tf);
         const T* __restrict__ Y = static_cast<const T*>(a.y);
         // the FP64 special functions' coefficient tables, addressed once
         const tab64_ptr ctab = sizeof(T) == 8 ? tab64() : nullptr;
@@ -419,7 +423,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             if (near) {
                 const T dla = s2a * rsa, dlb = s2b * rsb;
                 T la, mla, lb, mlb;
-                trunc_terms2<T>(dla * inv_sT, dlb * inv_sT, la, mla, lb, mlb, ctab);
+                if constexpr (sizeof(T) == 8) {
+                    if ((__builtin_amdgcn_ballot_w64(s2a < thrf) |
+                         __builtin_amdgcn_ballot_w64(s2b < thrf)) == 0)
+                        trunc_terms2_far_f64(dla * inv_sT, dlb * inv_sT, la, mla, lb, mlb, ctab);
+                    else
+                        trunc_terms2<T>(dla * inv_sT, dlb * inv_sT, la, mla, lb, mlb, ctab);
+                } else {
+                    trunc_terms2<T>(dla * inv_sT, dlb * inv_sT, la, mla, lb, mlb, ctab);
+                }
                 la = oka ? la : T(0);
                 mla = oka ? mla : T(0);
                 lb = okb ? lb : T(0);

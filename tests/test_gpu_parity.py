@@ -259,6 +259,41 @@ def test_all_missing_and_coincident():
     check64(got, ref, "coincident")
 
 
+def _grid_problem(side, spacing, sigma, seed, nan_frac=0.05):
+    """Points on a jittered square grid (jitter +-0.05 sigma per coordinate):
+    every pair lies at least spacing - 0.15 sigma apart."""
+    rng = np.random.default_rng(seed)
+    g = np.stack(np.meshgrid(np.arange(side), np.arange(side), indexing="ij"), -1)
+    x = g.reshape(-1, 2) * spacing + rng.uniform(-0.05, 0.05, (side * side, 2)) * sigma
+    n = x.shape[0]
+    d = np.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1))
+    y = np.abs(d + sigma * rng.standard_normal((n, n)))
+    y = np.tril(y, -1)
+    y = y + y.T
+    miss = np.tril(rng.random((n, n)) < nan_frac, -1)
+    y[miss | miss.T] = np.nan
+    return x, y
+
+
+def test_far_range_special_functions():
+    # Every pair at t >= 3.25 (grid spacing 3.4 sigma), about twenty
+    # neighbours per point inside the skip point: every step that evaluates
+    # the special functions takes their far-range forms (FP64).  Then a few
+    # points moved next to a neighbour (t ~ 0.5): their steps take the
+    # full-range forms, the others still the far ones.
+    sigma = 0.5
+    x, y = _grid_problem(30, 3.4 * sigma, sigma, seed=31)
+    ref = oracle.evaluate(x, y, sigma)
+    got, _ = gpu_eval(y, x, sigma)
+    check64(got, ref, "far range")
+    xm = x.copy()
+    for k in (7, 300, 451, 812):
+        xm[k] = x[k + 1] + 0.25 * sigma
+    ref = oracle.evaluate(xm, y, sigma)
+    got, _ = gpu_eval(y, xm, sigma)
+    check64(got, ref, "far and near")
+
+
 def test_y_equal_delta():
     # quadratic term zero: L is -sum ln Phi(delta/sigma) - M ln sigma
     from scipy.spatial.distance import cdist
