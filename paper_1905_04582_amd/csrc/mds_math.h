@@ -135,15 +135,17 @@ __device__ __forceinline__ double rcp_f64(double d)
     return fma(r, e, r);
 }
 
-// 1/sqrt(x) for finite x >= DBL_MIN: hardware estimate (relative error
-// below 2^-24 on gfx950) + 2 Newton steps (each roughly squares the error:
-// one step leaves it below 2^-47, two reach the rounding)
+// 1/sqrt(x) for finite x >= DBL_MIN: hardware estimate r (relative error
+// below 2^-24 on gfx950), then one correction of third order: with
+// e = (1 - x r^2)/2, 1/sqrt(x) = r (1 + e + 3/2 e^2 + 5/2 e^3 + ...), and
+// the first omitted term is below 2^-70 of the result, so the final fma's
+// rounding sets the error (a Newton step only squares it: two would be
+// needed)
 __device__ __forceinline__ double rsqrt_f64(double x)
 {
-    double r = __builtin_amdgcn_rsq(x);
-    const double hx = 0.5 * x;
-    r = fma(r, fma(-hx, r * r, 0.5), r);
-    return fma(r, fma(-hx, r * r, 0.5), r);
+    const double r = __builtin_amdgcn_rsq(x);
+    const double e = fma(-0.5 * x, r * r, 0.5);
+    return fma(r * e, fma(1.5, e, 1.0), r);
 }
 
 constexpr int kExpN = sizeof(kExpC64) / sizeof(double);
