@@ -327,7 +327,7 @@ def n_sweep(args, events):
 def tile_trace(out_path, events, tile_rows=0, tile_waves=0):
     """Per-wave timeline of the FP64 sweep at N = 5392 (relabelled; default
     tiles unless given): start and end clock and hardware slot of every wave
-    (mds_set_tile_trace)."""
+    (mds_set_tile_trace), in one evaluation after the warm-up."""
     import numpy as np
     import torch
 
@@ -345,9 +345,7 @@ def tile_trace(out_path, events, tile_rows=0, tile_waves=0):
     buf = torch.zeros(ntiles * w * 3, dtype=torch.int64, device=dev)
     xr = P.relabel(torch.as_tensor(prob.x, device=dev))
     sig = torch.tensor(prob.sigma, dtype=torch.float64, device=dev)
-    for _ in range(20):
-        P.gradient(xr, sig)
-    torch.cuda.synchronize()
+    settle(lambda: P.gradient(xr, sig))
     api.mds_set_tile_trace(buf)
     P.gradient(xr, sig)
     torch.cuda.synchronize()
