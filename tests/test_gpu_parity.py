@@ -294,6 +294,26 @@ def test_far_range_special_functions():
     check64(got, ref, "far and near")
 
 
+def test_grid_fp32():
+    # the same grid (every pair at t >= 3.25) and the same grid with near
+    # pairs in the FP32 form (which keeps one form of the special functions),
+    # against the oracle on the FP32-rounded Y at the precision form's bounds
+    sigma = 0.5
+    x, y = _grid_problem(30, 3.4 * sigma, sigma, seed=32)
+    y32 = y.astype(np.float32)
+    xm = x.copy()
+    for k in (7, 300, 451, 812):
+        xm[k] = x[k + 1] + 0.25 * sigma
+    for xx, label in ((x, "far"), (xm, "far and near")):
+        got, _ = gpu_eval(y32, xx, sigma, dtype=torch.float32)
+        ref = oracle.evaluate(xx, y32.astype(np.float64), sigma)
+        el = abs(got["loglik"] - ref.loglik) / abs(ref.loglik)
+        rb = np.max(np.max(np.abs(got["grad"] - ref.grad), axis=1) / ref.condrow)
+        es = abs(got["dsigma"] - ref.dsigma) / ref.abs_dsigma
+        _log(f"FP32 {label}: loglik rel {el:.2e}; grad row err/B_i {rb:.2e}; dsigma err/abs {es:.2e}")
+        assert el <= TOL32_LOGLIK and rb <= TOL32_ROW and es <= TOL32_DSIGMA, label
+
+
 def test_y_equal_delta():
     # quadratic term zero: L is -sum ln Phi(delta/sigma) - M ln sigma
     from scipy.spatial.distance import cdist
