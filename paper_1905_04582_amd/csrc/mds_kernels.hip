@@ -2,6 +2,8 @@
 // finalize (partials -> gradient rows, L, dL/dsigma, fused leapfrog kick and
 // drift), the Hamiltonian energy, the Y preparation and the elementwise
 // special-function helper.
+#include <type_traits>
+
 #include "mds_internal.h"
 #include "mds_math.h"
 
@@ -169,21 +171,33 @@ __device__ void finalize_elements(const FinalizeArgs& a, int D, int64_t blk, dou
         // over row blocks rb0 .. nrb-1.  Chunk `chunk` adds items chunk,
         // chunk + kFinChunks, ... in list order.  Loads are unconditional
         // (index clamped into the list, an item past the end replaced by 0),
-        // so each batch of kFinUnroll loads -- row and column items alike --
-        // is in flight together.
+        // so each batch of loads -- row and column items alike -- is in
+        // flight together.  The batch is 4, 8 or kFinUnroll loads, the
+        // fewest that cover a chunk's items in one batch where that is
+        // possible (the order of the additions is the same whatever the
+        // batch).
         const double* rbase = a.rowpart + ((t0 * br + roff) * D + d);
         const double* cbase = a.colpart + ((((int64_t)c * a.nrb + rb0) * cw + coff) * D + d);
         const int64_t rstep = (int64_t)br * D, cstep = (int64_t)cw * D;
-        for (int i0 = chunk; i0 < total; i0 += kFinUnroll * kFinChunks) {
-            double v[kFinUnroll];
+        auto add_items = [&](auto batch) {
+            constexpr int U = decltype(batch)::value;
+            for (int i0 = chunk; i0 < total; i0 += U * kFinChunks) {
+                double v[U];
 #pragma unroll
-            for (int u = 0; u < kFinUnroll; ++u) {
-                const int q = min(i0 + u * kFinChunks, total - 1);
-                v[u] = q < nrow ? rbase[q * rstep] : cbase[(q - nrow) * cstep];
+                for (int u = 0; u < U; ++u) {
+                    const int q = min(i0 + u * kFinChunks, total - 1);
+                    v[u] = q < nrow ? rbase[q * rstep] : cbase[(q - nrow) * cstep];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) s += (i0 + u * kFinChunks < total) ? v[u] : 0.0;
             }
-#pragma unroll
-            for (int u = 0; u < kFinUnroll; ++u) s += (i0 + u * kFinChunks < total) ? v[u] : 0.0;
-        }
+        };
+        if (total <= 4 * kFinChunks)
+            add_items(std::integral_constant<int, 4>());
+        else if (total <= 8 * kFinChunks)
+            add_items(std::integral_constant<int, 8>());
+        else
+            add_items(std::integral_constant<int, kFinUnroll>());
     }
     part[chunk][lane] = s;
     __syncthreads();
