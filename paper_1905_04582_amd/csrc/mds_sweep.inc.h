@@ -14,13 +14,15 @@
 //     the wave's rows.  The row side is a sum across the 64 lanes: the lanes
 //     stage their terms of a few rows in LDS, then every (row, dimension)
 //     output is summed by a small group of lanes reading the staged values
-//     and finished by log2(group) exchanges;
+//     and finished by log2(group) DPP lane exchanges;
 //   * a wavefront whose pairs in two rows all have delta/sigma beyond a skip
 //     point branches over the special functions as a whole (no divergence),
 //     and the pair then adds one product to the wave's sums: the residual
 //     square, which both the likelihood and dL/dsigma scale by a power of
 //     1/sigma once per wave, and its gradient coefficient (scaled by
-//     1/sigma^2 once per staging batch);
+//     1/sigma^2 once per staging batch); in FP64 a wavefront whose pairs in
+//     two rows all have delta/sigma >= 3 takes shorter far-range forms of the
+//     special functions;
 //   * the column sums of the wr waves of a column group, and the row sums of
 //     the wc waves of a row group, meet in LDS and are added in wave order;
 //     column, row and scalar partials of the tile go to the workspace, and
