@@ -45,7 +45,7 @@ FP64_VALU_TOPS = 39.3216       # 256 CU x 64 FP64 lanes/clk x 2.4 GHz (lane-ops,
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
 # sources of the sweep kernel: counter figures in profiles/sweep_traffic.json
 # are used only while they and the tiling match
-KERNEL_SOURCES = ["mds_sweep.inc.h", "mds_math.h", "mds_coeffs.h", "mds_internal.h",
+KERNEL_SOURCES = ["mds_sweep.inc.h", "mds_math.h", "mds_coeffs.h", "mds_internal.h", "mds_wave.h",
                   "mds_sweep_f64.hip", "mds_sweep_f32.hip"]
 
 

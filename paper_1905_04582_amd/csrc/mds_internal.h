@@ -33,29 +33,32 @@ struct Tiling {
     int elem;   // bytes of one Y element (8 in FP64, 4 in FP32): the staged rows' type
 };
 
+// br and cw are powers of two, so the ratios below are shifts
+__host__ __device__ inline int log2_pow2(int v) { return __builtin_ctz((unsigned)v); }
+
 __host__ __device__ inline int64_t tiles_in_row_block(int r, int br, int cw)
 {
-    if (br >= cw) return (int64_t)(r + 1) * (br / cw);
-    return (int64_t)(r / (cw / br)) + 1;
+    if (br >= cw) return (int64_t)(r + 1) << (log2_pow2(br) - log2_pow2(cw));
+    return (int64_t)(r >> (log2_pow2(cw) - log2_pow2(br))) + 1;
 }
 
 // number of tiles in row blocks 0..r-1
 __host__ __device__ inline int64_t tiles_before(int r, int br, int cw)
 {
     if (br >= cw) {
-        const int64_t k = br / cw;
-        return k * (int64_t)r * (r + 1) / 2;
+        const int sh = log2_pow2(br) - log2_pow2(cw);  // log2 of br / cw
+        return (((int64_t)r * (r + 1)) >> 1) << sh;
     }
-    const int64_t k = cw / br;
-    const int64_t a = r / k, b = r % k;
-    return (int64_t)r + k * a * (a - 1) / 2 + a * b;
+    const int sh = log2_pow2(cw) - log2_pow2(br);      // log2 of k = cw / br
+    const int64_t a = r >> sh, b = r & ((1 << sh) - 1);
+    return (int64_t)r + (((a * (a - 1)) >> 1) << sh) + a * b;
 }
 
 // first row block that holds a tile in column block c
 __host__ __device__ inline int first_row_block_of_column(int c, int br, int cw)
 {
-    if (br >= cw) return c / (br / cw);
-    return c * (cw / br);
+    if (br >= cw) return c >> (log2_pow2(br) - log2_pow2(cw));
+    return c << (log2_pow2(cw) - log2_pow2(br));
 }
 
 // (row block, column block) of linear tile index `tile` (row blocks in

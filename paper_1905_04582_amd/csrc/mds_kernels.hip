@@ -6,6 +6,7 @@
 
 #include "mds_internal.h"
 #include "mds_math.h"
+#include "mds_wave.h"
 
 namespace mds {
 
@@ -82,41 +83,51 @@ constexpr int kFinUnroll = 16;  // partial loads in flight per lane
 
 // The scalar part: L, dL/dsigma and dL/d(ln sigma) from the per-tile sums,
 // by one work-group of kWave * kFinChunks threads in a fixed order: thread t
-// adds tiles t, t + T, ... (kFinUnroll loads in flight), each wave combines
-// its lanes by a butterfly, and thread 0 adds the waves in order.
+// adds tiles t, t + T, ... (loads issued in batches sized to the tile count),
+// each wave sums its lanes by DPP exchanges (the pair counts are integers
+// below 2^53, so their sums in FP64 are exact in any order), and thread 0
+// adds the waves in order.  ln sigma and 1/sigma are
+// formed while the loads are in flight.
 __device__ void finalize_scalars(const FinalizeArgs& a, double scale)
 {
     constexpr int T = kWave * kFinChunks;
     __shared__ double s[3][kFinChunks];
-    const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+    const int t = threadIdx.x, w = t / kWave;
+    const double sigma = *a.sigma;
     double sr = 0.0, ss = 0.0, sm = 0.0;
-    // batches of kFinUnroll tiles, each batch's loads issued together (index
-    // clamped into the list, a tile past the end replaced by 0)
     const int64_t last = a.ntiles - 1;
-    for (int64_t u = t; u < a.ntiles; u += kFinUnroll * T) {
-        double r[kFinUnroll], q[kFinUnroll], c[kFinUnroll];
+    auto add_tiles = [&](auto batch) {
+        constexpr int U = decltype(batch)::value;
+        for (int64_t u = t; u < a.ntiles; u += U * T) {
+            double r[U], q[U];
+            uint32_t c[U];
 #pragma unroll
-        for (int k = 0; k < kFinUnroll; ++k) {
-            const int64_t v = min(u + (int64_t)k * T, last);
-            r[k] = a.tscal[2 * v + 0];
-            q[k] = a.tscal[2 * v + 1];
-            c[k] = (double)a.tcount[v];
+            for (int k = 0; k < U; ++k) {
+                const int64_t v = min(u + (int64_t)k * T, last);
+                r[k] = a.tscal[2 * v + 0];
+                q[k] = a.tscal[2 * v + 1];
+                c[k] = a.tcount[v];
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const bool in = u + (int64_t)k * T < a.ntiles;
+                sr += in ? r[k] : 0.0;
+                ss += in ? q[k] : 0.0;
+                sm += in ? (double)c[k] : 0.0;
+            }
         }
-#pragma unroll
-        for (int k = 0; k < kFinUnroll; ++k) {
-            const bool in = u + (int64_t)k * T < a.ntiles;
-            sr += in ? r[k] : 0.0;
-            ss += in ? q[k] : 0.0;
-            sm += in ? c[k] : 0.0;
-        }
-    }
-#pragma unroll
-    for (int m = kWave / 2; m >= 1; m >>= 1) {
-        sr += __shfl_xor(sr, m, kWave);
-        ss += __shfl_xor(ss, m, kWave);
-        sm += __shfl_xor(sm, m, kWave);
-    }
-    if (lane == 0) {
+    };
+    if (a.ntiles <= 4 * T)
+        add_tiles(std::integral_constant<int, 4>());
+    else if (a.ntiles <= 8 * T)
+        add_tiles(std::integral_constant<int, 8>());
+    else
+        add_tiles(std::integral_constant<int, kFinUnroll>());
+    const double ln_sigma = log(sigma), inv_sigma = 1.0 / sigma;
+    sr = wave_sum(sr);
+    ss = wave_sum(ss);
+    sm = wave_sum(sm);
+    if ((t & (kWave - 1)) == 0) {
         s[0][w] = sr;
         s[1][w] = ss;
         s[2][w] = sm;
@@ -129,10 +140,8 @@ __device__ void finalize_scalars(const FinalizeArgs& a, double scale)
             q0 += s[1][k];
             m += s[2][k];
         }
-        // m is an exact integer below 2^53
-        const double sigma = *a.sigma;
-        const double L = (m > 0.0) ? -m * log(sigma) - r0 : 0.0;
-        const double ds = (m > 0.0) ? (-m / sigma + q0) * scale : 0.0;
+        const double L = (m > 0.0) ? -m * ln_sigma - r0 : 0.0;
+        const double ds = (m > 0.0) ? (-m * inv_sigma + q0) * scale : 0.0;
         if (a.loglik) *a.loglik = L;
         if (a.dsigma) *a.dsigma = ds;
         if (a.dlogsigma) *a.dlogsigma = ds * sigma;
