@@ -258,6 +258,12 @@ static void check_case(int64_t n, const Tile& tl, int rb, bool per_pair, bool sa
 #undef CASE
         }
     }
+    // the finalize's row-side lists: row block r's tiles are the run
+    // tiles_before(r) .. + tiles_in_row_block(r)
+    for (int r = 0; r < t.nrb; ++r)
+        CHECK(tiles_before(r + 1, t.br, cw) == tiles_before(r, t.br, cw) + tiles_in_row_block(r, t.br, cw),
+              "row block %d of n=%lld br=%d cw=%d", r, (long long)n, t.br, cw);
+    CHECK(tiles_before(t.nrb, t.br, cw) == t.ntiles, "tile count n=%lld", (long long)n);
     // column-side slots: one tile in each row block from the first of the column
     for (int64_t c = 0; c < ncb; ++c)
         CHECK(col_tiles[c] == t.nrb - first_row_block_of_column((int)c, t.br, cw),
