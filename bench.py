@@ -734,6 +734,16 @@ def main():
     c64, c32 = counters.get("fp64", {}), counters.get("fp32", {})
     traffic = c64.get("traffic_bytes_per_launch")
 
+    def busy_warm(c, sweep_ms):
+        # VALU-busy fraction of the warm launch: the counter run's VALU
+        # quad-cycles over every SIMD's cycles in the bench's own mean launch
+        # time at the 2.4 GHz peak clock (a lower bound: a slower clock gives
+        # fewer cycles).  The counter runs' own fraction (valu_busy_frac) is
+        # taken over their launches, which start from caches the profiler
+        # has flushed.
+        a = c.get("sq_active_inst_valu")
+        return round(4 * a / (1024 * 2.4e9 * sweep_ms * 1e-3), 4) if a else None
+
     plain = {}
     for k in ("fp64-plain", "fp32-plain"):
         w, sw, swm, _ = res[k]
@@ -768,6 +778,7 @@ def main():
             "frac": round(gbs64 / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": y_bytes64,
             "valu_busy_frac": c64.get("valu_busy_frac"),
+            "valu_busy_frac_warm_min": busy_warm(c64, sweep64),
             "counters": "profiles/sweep_traffic.json" if counters else None,
             "sweep_ms_mean": round(sweep64, 5), "sweep_ms_median": round(sweep64_med, 5),
             "sweep_ms_cold_median": round(cold64, 5),
@@ -791,6 +802,7 @@ def main():
             "y_stream_gbs": round(gbs32, 2), "y_stream_frac": round(gbs32 / HBM_PEAK_GBS, 4),
             "traffic": c32.get("traffic_bytes_per_launch"),
             "valu_busy_frac": c32.get("valu_busy_frac"),
+            "valu_busy_frac_warm_min": busy_warm(c32, sweep32),
             "loglik_rel_diff_vs_fp64": abs(L32.item() - L64.item()) / abs(L64.item()),
             # issued VALU lane-operations (FP32 without packed math issues
             # at the FP64 rate: 16 lanes per SIMD per clock)
