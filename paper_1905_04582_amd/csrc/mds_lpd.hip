@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(kRowThreads)
 // the rounding of l).  The arithmetic of a draw does not depend on how the
 // draws are grouped into calls: S calls of one draw and one call of S draws
 // give the same bits.
-constexpr int kLpdPairs = 4;
+constexpr int kLpdPairs = 4;  // even: the special functions take two pairs at a time
+static_assert(kLpdPairs % 2 == 0, "pairs per thread");
 constexpr int kLpdThreads = 256;
 
 template <int D, bool ONE>
@@ -158,12 +159,14 @@ __global__ void __launch_bounds__(kLpdThreads)
     }
     // ONE: a single draw, with the loop known to run once (same arithmetic)
     const int32_t draws = ONE ? 1 : n_draws;
+    const tab64_ptr tb = tab64();
     for (int s = 0; s < draws; ++s) {
         const double sigma = sigmas[s];
         const double inv_sigma = 1.0 / sigma;
         const double c0 = -kLnSqrt2Pi - log(sigma);
         const double* x = xs + (int64_t)s * xstride;
         const bool start = first && s == 0;
+        double z[kLpdPairs], t[kLpdPairs];
 #pragma unroll
         for (int u = 0; u < kLpdPairs; ++u) {
             double s2 = 0.0;
@@ -173,19 +176,42 @@ __global__ void __launch_bounds__(kLpdThreads)
                 s2 = fma(diff, diff, s2);
             }
             const double delta = sqrt(s2);
-            const double z = (yv[u] - delta) * inv_sigma;
-            const double t = delta * inv_sigma;
-            double lnphi = 0.0, mills;
-            if (__builtin_amdgcn_ballot_w64(t < 9.0)) log_phi_general_f64(t, lnphi, mills);
-            const double l = c0 - 0.5 * z * z - lnphi;
-            if (start) {
-                mx[u] = l;
-                sm[u] = 1.0;
-            } else if (l > mx[u]) {
-                sm[u] = sm[u] * exp(mx[u] - l) + 1.0;
-                mx[u] = l;
-            } else {
-                sm[u] += exp(l - mx[u]);
+            z[u] = (yv[u] - delta) * inv_sigma;
+            t[u] = delta * inv_sigma;
+        }
+        // ln Phi(t) two pairs at a time: skipped by the whole wave when every
+        // t is past the skip point (9), in its far-range forms when every t
+        // is at or past kFarT, else in its full-range forms
+#pragma unroll
+        for (int u = 0; u < kLpdPairs; u += 2) {
+            double lp0 = 0.0, lp1 = 0.0, m0, m1;
+            if (__builtin_amdgcn_ballot_w64(t[u] < 9.0) | __builtin_amdgcn_ballot_w64(t[u + 1] < 9.0)) {
+                if ((__builtin_amdgcn_ballot_w64(t[u] < kFarT) |
+                     __builtin_amdgcn_ballot_w64(t[u + 1] < kFarT)) == 0)
+                    trunc_terms2_far_f64(t[u], t[u + 1], lp0, m0, lp1, m1, tb);
+                else
+                    trunc_terms2_f64(t[u], t[u + 1], lp0, m0, lp1, m1, tb);
+            }
+            const double lp[2] = {lp0, lp1};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int v = u + h;
+                const double l = c0 - 0.5 * z[v] * z[v] - lp[h];
+                // running log-sum-exp: one exp of -|l - largest| serves both
+                // cases
+                if (start) {
+                    mx[v] = l;
+                    sm[v] = 1.0;
+                } else {
+                    const double dl = l - mx[v];
+                    const double e = exp(-fabs(dl));
+                    if (dl > 0.0) {
+                        sm[v] = sm[v] * e + 1.0;
+                        mx[v] = l;
+                    } else {
+                        sm[v] += e;
+                    }
+                }
             }
         }
     }
