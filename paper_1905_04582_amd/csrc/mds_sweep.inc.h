@@ -241,7 +241,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             ++xnext;
             return p;
         };
-        int cntv = 0;  // observed pairs counted per lane (fast walk)
 
         constexpr int NO = RB * D;
         constexpr int RG = reduce_group(NO);
@@ -257,30 +256,37 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             bL = T(0);
             bM = T(0);
         };
-        // end of the staging batch of rows [b0, b0 + RB) (rows at or past rw1
-        // are dead): the batch's sums go to the FP64 accumulators, and every
-        // (row, dimension) output gets RG lanes -- lane h of its group adds
-        // the staged values of lanes h, h+RG, ..., then the group combines by
-        // log2(RG) exchanges
-        auto batch_flush = [&](auto fast_tag, const int b0) {
-            constexpr bool FAST = decltype(fast_tag)::value;
+        // In FP32 the lane sums (bA, bL, bM, gjb) close into the FP64
+        // accumulators at the end of each staging batch; in FP64 they are
+        // those accumulators and run over the whole walk.
+        constexpr bool BATCH_SUMS = sizeof(T) < sizeof(double);
+        auto close_sums = [&]() {
             acc_A += (double)bA;
             acc_L += (double)bL;
             acc_M += (double)bM;
-            if (GRAD) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) gj[d] = fma((double)gjb[d], inv_s2, gj[d]);
+            for (int d = 0; d < D; ++d) gj[d] = fma((double)gjb[d], inv_s2, gj[d]);
+        };
+        // end of the staging batch of rows [b0, b0 + RB) (rows at or past rw1
+        // are dead): every (row, dimension) output gets RG lanes -- lane h of
+        // its group adds the staged values of lanes h, h+RG, ..., then the
+        // group combines by log2(RG) exchanges
+        auto batch_flush = [&](auto fast_tag, const int b0) {
+            constexpr bool FAST = decltype(fast_tag)::value;
+            if constexpr (BATCH_SUMS) close_sums();
+            if (GRAD) {
                 const bool live = o < NO && (FAST || b0 + orow < rw1);
                 T sum = T(0);
                 if (live) {
                     const T* src = stage + (size_t)orow * SROW + (size_t)h * D + odim;
+                    sum = src[0];
 #pragma unroll
-                    for (int k = 0; k < kWave / RG; ++k) sum += src[(size_t)k * RG * D];
+                    for (int k = 1; k < kWave / RG; ++k) sum += src[(size_t)k * RG * D];
                 }
                 sum = group_sum<RG>(sum);
                 if (live && h == 0) lrows[(b0 - row0 + orow) * D + odim] = (double)sum * inv_s2;
             }
-            batch_reset();
+            if constexpr (BATCH_SUMS) batch_reset();
         };
         batch_reset();
 
@@ -288,8 +294,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
         // the batch.  FAST (a compile-time tag) is the walk of a wave whose
         // rows are whole iterations with x rows contiguous (ldx == D); the
         // general walk has dead rows (at or past rw1: no lane's pair counts,
-        // their loads repeat the wave's last row) and counts pairs by lane
-        // masks.  The fast walk counts them per lane.
+        // their loads repeat the wave's last row).
         auto step = [&](auto fast_tag, const int i0, const int q, const T ya, const T yb) {
             constexpr bool FAST = decltype(fast_tag)::value;
             const bool live0 = FAST || i0 < rw1, live1 = FAST || i0 + 1 < rw1;
@@ -311,35 +316,24 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
                 s2a = fma(da[d], da[d], s2a);
                 s2b = fma(db[d], db[d], s2b);
             }
-            // observed pairs of the strict lower triangle: each condition is
-            // one compare, and bitwise operators keep the conditions
-            // branch-free
-            const bool tra = j32 < i0, trb = j32 < i0 + 1;
-            const bool nna = !isnan(ya), nnb = !isnan(yb);
-            const bool oka = live0 & colok & tra & nna;
-            const bool okb = live1 & colok & trb & nnb;
-            uint64_t near;
-            if constexpr (FAST) {
-                cntv += (int)oka + (int)okb;
-                // (add now: deferring the adds would keep every step's lane
-                // masks alive to the end of the iteration)
-                asm volatile("" : "+v"(cntv));
-                // any lane with a close pair sends the wave through the
-                // special functions (its terms are masked by oka / okb)
-                near = __builtin_amdgcn_ballot_w64(s2a < thr2) |
-                       __builtin_amdgcn_ballot_w64(s2b < thr2);
-            } else {
-                // counts from the compares' own lane masks
-                const uint64_t ma = __builtin_amdgcn_ballot_w64(tra) &
-                                    __builtin_amdgcn_ballot_w64(nna) & colmask &
-                                    (0ull - (uint64_t)live0);
-                const uint64_t mb = __builtin_amdgcn_ballot_w64(trb) &
-                                    __builtin_amdgcn_ballot_w64(nnb) & colmask &
-                                    (0ull - (uint64_t)live1);
-                cnt += (int)__builtin_popcountll(ma) + (int)__builtin_popcountll(mb);
-                near = (__builtin_amdgcn_ballot_w64(s2a < thr2) & ma) |
-                       (__builtin_amdgcn_ballot_w64(s2b < thr2) & mb);
-            }
+            // observed pairs as wave masks: the lanes below the row (j < i),
+            // of a present y, of a column inside the problem, on a live row.
+            // Each compare feeds only its ballot, and a lane's condition is
+            // then the mask's own bit (combined and counted by scalar
+            // instructions, with no per-lane copy of the conditions)
+            const uint64_t ma = __builtin_amdgcn_ballot_w64(j32 < i0) &
+                                __builtin_amdgcn_ballot_w64(!isnan(ya)) &
+                                colmask & (0ull - (uint64_t)live0);
+            const uint64_t mb = __builtin_amdgcn_ballot_w64(j32 <= i0) &
+                                __builtin_amdgcn_ballot_w64(!isnan(yb)) & colmask &
+                                (0ull - (uint64_t)live1);
+            cnt += (int)__builtin_popcountll(ma) + (int)__builtin_popcountll(mb);
+            const bool oka = __builtin_amdgcn_inverse_ballot_w64(ma);
+            const bool okb = __builtin_amdgcn_inverse_ballot_w64(mb);
+            // any observed pair closer than the skip point sends the wave
+            // through the special functions (the others' terms are masked)
+            const uint64_t near = (__builtin_amdgcn_ballot_w64(s2a < thr2) & ma) |
+                                  (__builtin_amdgcn_ballot_w64(s2b < thr2) & mb);
             // delta and 1/delta from one reciprocal square root of s2 clamped
             // to the smallest normal number.  A coincident pair (s2 = 0) gets
             // delta = 0 and a gradient term (coefficient) * (x_i - x_j) = 0;
@@ -460,7 +454,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
             // (rows [ib - q, ib))
             if (q != 0) batch_flush(general_walk, ib - q);
         }
-        cnt += wave_sum(cntv);
+        if constexpr (!BATCH_SUMS) close_sums();
     }
 
     double acc_r = fma(acc_A, 0.5 * inv_s2, acc_L);
