@@ -80,6 +80,11 @@ __device__ void block_sum3(double& a, double& b, double& c)
 // sums in chunk order.  Every order is fixed, so the result is reproducible.
 constexpr int kFinChunks = 8;
 constexpr int kFinUnroll = 16;  // partial loads in flight per lane
+// The finalize streams partials with one round of loads per lane: its time is
+// latency, so the register budget is held to six waves per SIMD (three
+// work-groups per compute unit; at the default budget the batched kernel fit
+// one).
+constexpr int kFinWavesPerSimd = 6;
 
 // The scalar part: L, dL/dsigma and dL/d(ln sigma) from the per-tile sums,
 // by one work-group of kWave * kFinChunks threads in a fixed order: thread t
@@ -117,12 +122,12 @@ __device__ void finalize_scalars(const FinalizeArgs& a, double scale)
             }
         }
     };
+    // (at most 8 tiles per batch: larger batches cost the element blocks of
+    // the same kernel their occupancy)
     if (a.ntiles <= 4 * T)
         add_tiles(std::integral_constant<int, 4>());
-    else if (a.ntiles <= 8 * T)
-        add_tiles(std::integral_constant<int, 8>());
     else
-        add_tiles(std::integral_constant<int, kFinUnroll>());
+        add_tiles(std::integral_constant<int, 8>());
     const double ln_sigma = log(sigma), inv_sigma = 1.0 / sigma;
     sr = wave_sum(sr);
     ss = wave_sum(ss);
@@ -230,7 +235,8 @@ __device__ void finalize_elements(const FinalizeArgs& a, int D, int64_t blk, dou
     }
 }
 
-__global__ void __launch_bounds__(kWave * kFinChunks) finalize_kernel(FinalizeArgs a, int D)
+__global__ void __launch_bounds__(kWave * kFinChunks)
+    __attribute__((amdgpu_waves_per_eu(kFinWavesPerSimd))) finalize_kernel(FinalizeArgs a, int D)
 {
     const double scale = a.scale ? *a.scale : 1.0;
     if (blockIdx.x == gridDim.x - 1)
@@ -243,7 +249,7 @@ __global__ void __launch_bounds__(kWave * kFinChunks) finalize_kernel(FinalizeAr
 // per problem.  Also rewinds the persistent sweep's tile cursor for the next
 // call (this kernel runs after the sweep on the same stream).
 __global__ void __launch_bounds__(kWave * kFinChunks)
-    batch_finalize_kernel(const BatchProblem* __restrict__ probs,
+    __attribute__((amdgpu_waves_per_eu(kFinWavesPerSimd))) batch_finalize_kernel(const BatchProblem* __restrict__ probs,
                           const int32_t* __restrict__ blkmap, int32_t count, int64_t elem_blocks,
                           unsigned long long* cursor, double kick_mult, int kick, int drift)
 {
