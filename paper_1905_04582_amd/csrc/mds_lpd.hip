@@ -124,15 +124,20 @@ __global__ void __launch_bounds__(kRowThreads)
 // acc[2k+1] = sum of exp(l - largest)); `first` starts the sums with the
 // first draw.  The state stays in registers across the draws, so a call with
 // S draws reads and writes it once instead of S times.  Each thread takes
-// kLpdPairs pairs (one block covers 256 * kLpdPairs consecutive pairs,
+// lpd_pairs(S == 1) pairs (one block covers 256 times that many consecutive pairs,
 // lane-strided so every load is coalesced), so ln sigma and 1/sigma are
 // formed once per thread and draw.  A wavefront whose pairs all have
 // delta/sigma >= 9 takes ln Phi = 0 (|ln Phi(t)| < 2.3e-19 there, far below
 // the rounding of l).  The arithmetic of a draw does not depend on how the
 // draws are grouped into calls: S calls of one draw and one call of S draws
 // give the same bits.
-constexpr int kLpdPairs = 4;  // even: the special functions take two pairs at a time
-static_assert(kLpdPairs % 2 == 0, "pairs per thread");
+// Pairs per thread (even: the special functions take two pairs at a time).
+// One draw per pass streams the pair list and the state: two pairs per thread
+// give twice the work-groups to hide memory latency (7% faster than four at
+// 1.24 M pairs).  Several draws per pass are arithmetic-bound: four pairs per
+// thread share ln sigma and 1/sigma of each draw (6% faster than two).
+constexpr int lpd_pairs(bool one) { return one ? 2 : 4; }
+static_assert(lpd_pairs(true) % 2 == 0 && lpd_pairs(false) % 2 == 0, "pairs per thread");
 constexpr int kLpdThreads = 256;
 
 template <int D, bool ONE>
@@ -143,6 +148,7 @@ __global__ void __launch_bounds__(kLpdThreads)
                           int32_t n_draws, double* __restrict__ acc, int first)
 {
     constexpr double kLnSqrt2Pi = 0.91893853320467274178;
+    constexpr int kLpdPairs = lpd_pairs(ONE);
     const int64_t base = (int64_t)blockIdx.x * (kLpdThreads * kLpdPairs) + threadIdx.x;
     int64_t ii[kLpdPairs], jj[kLpdPairs];
     double yv[kLpdPairs], mx[kLpdPairs], sm[kLpdPairs];
@@ -309,7 +315,7 @@ hipError_t launch_lpd_accumulate(int64_t m, const int32_t* pi, const int32_t* pj
                                  double* acc, int first, hipStream_t s)
 {
     if (m == 0 || n_draws == 0) return hipSuccess;
-    const int64_t per_block = (int64_t)kLpdThreads * kLpdPairs;
+    const int64_t per_block = (int64_t)kLpdThreads * lpd_pairs(n_draws == 1);
     const dim3 grid((unsigned)((m + per_block - 1) / per_block)), block(kLpdThreads);
 #define MDS_LPD_CASE(DD)                                                                     \
     case DD:                                                                                 \
