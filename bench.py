@@ -739,8 +739,8 @@ def main():
         # quad-cycles over every SIMD's cycles in the bench's own mean launch
         # time at the 2.4 GHz peak clock (a lower bound: a slower clock gives
         # fewer cycles).  The counter runs' own fraction (valu_busy_frac) is
-        # taken over their launches, which last about as long as
-        # cache-flushed ones.
+        # taken over their launches' own durations at the same clock; those
+        # launches last longer than warm ones.
         a = c.get("sq_active_inst_valu")
         return round(4 * a / (1024 * 2.4e9 * sweep_ms * 1e-3), 4) if a else None
 
