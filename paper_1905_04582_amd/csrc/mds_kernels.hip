@@ -47,30 +47,6 @@ int batch_sweep_blocks_per_cu(int y_dtype, bool grad, int maxd, int waves, size_
                         : batch_sweep_blocks_per_cu_f32(grad, maxd, waves, lds);
 }
 
-constexpr int kFinBlock = 256;
-
-// Fixed-order block reduction of three values over kFinBlock threads.
-__device__ void block_sum3(double& a, double& b, double& c)
-{
-    __shared__ double s[3][kFinBlock];
-    const int t = threadIdx.x;
-    s[0][t] = a;
-    s[1][t] = b;
-    s[2][t] = c;
-    __syncthreads();
-    for (int h = kFinBlock / 2; h > 0; h >>= 1) {
-        if (t < h) {
-            s[0][t] += s[0][t + h];
-            s[1][t] += s[1][t + h];
-            s[2][t] += s[2][t + h];
-        }
-        __syncthreads();
-    }
-    a = s[0][0];
-    b = s[1][0];
-    c = s[2][0];
-}
-
 // Finalize: one work-group per 64 consecutive gradient elements e = (k, d),
 // plus one scalar work-group (the last one).  Element e owns a list of
 // partials: the row-side partials of row k over the tiles of its row block,
@@ -375,30 +351,65 @@ hipError_t launch_kick_drift(int64_t n, int d, double* x, int64_t ldx, double* p
     return hipGetLastError();
 }
 
-// H = -(L - lambda/2 ||x||^2) + 1/2 sum p^2 / m  (one work-group, fixed order)
-__global__ void __launch_bounds__(kFinBlock)
+// H = -(L - lambda/2 ||x||^2) + 1/2 sum p^2 / m  (one work-group, fixed order).
+// Thread t adds elements t, t + T, ... (T = kEnergyThreads) in that order,
+// loading kEnergyBatch of them per round so the loads are in flight together
+// (an index past the end is clamped and its term dropped); each wave sums its
+// lanes by DPP exchanges and thread 0 adds the waves in order.  Element
+// indices are 32-bit: n D < 2^31 (the host bounds n through Y's leading
+// dimension).
+constexpr int kEnergyThreads = 1024;
+constexpr int kEnergyBatch = 8;
+
+__global__ void __launch_bounds__(kEnergyThreads)
     energy_kernel(int64_t n, int D, const double* x, int64_t ldx, const double* p, int64_t ldp,
                   const double* inv_mass, const double* prior, const double* loglik, double* out)
 {
-    double kin = 0.0, pri = 0.0, unused = 0.0;
+    __shared__ double s[2][kEnergyThreads / kWave];
+    double kin = 0.0, pri = 0.0;
     const double lam = prior ? *prior : 0.0;
-    for (int64_t e = threadIdx.x; e < n * D; e += kFinBlock) {
-        const int64_t k = e / D;
-        const int d = (int)(e - k * D);
-        const double pv = p[k * ldp + d];
-        const double xv = x[k * ldx + d];
-        kin += 0.5 * pv * pv * (inv_mass ? inv_mass[e] : 1.0);
-        pri += 0.5 * lam * xv * xv;
+    const int ne = (int)(n * D);
+    for (int e0 = threadIdx.x; e0 < ne; e0 += kEnergyBatch * kEnergyThreads) {
+        double pv[kEnergyBatch], xv[kEnergyBatch], im[kEnergyBatch];
+#pragma unroll
+        for (int u = 0; u < kEnergyBatch; ++u) {
+            const int e = min(e0 + u * kEnergyThreads, ne - 1);
+            const int k = e / D, d = e - k * D;
+            pv[u] = p[(int64_t)k * ldp + d];
+            xv[u] = x[(int64_t)k * ldx + d];
+            im[u] = inv_mass ? inv_mass[e] : 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kEnergyBatch; ++u) {
+            if (e0 + u * kEnergyThreads < ne) {
+                kin += 0.5 * pv[u] * pv[u] * im[u];
+                pri += 0.5 * lam * xv[u] * xv[u];
+            }
+        }
     }
-    block_sum3(kin, pri, unused);
-    if (threadIdx.x == 0) *out = -(*loglik - pri) + kin;
+    kin = wave_sum(kin);
+    pri = wave_sum(pri);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        s[0][w] = kin;
+        s[1][w] = pri;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double k0 = 0.0, p0 = 0.0;
+        for (int v = 0; v < kEnergyThreads / kWave; ++v) {
+            k0 += s[0][v];
+            p0 += s[1][v];
+        }
+        *out = -(*loglik - p0) + k0;
+    }
 }
 
 hipError_t launch_energy(int64_t n, int d, const double* x, int64_t ldx, const double* p,
                          int64_t ldp, const double* inv_mass, const double* prior,
                          const double* loglik, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(kFinBlock), 0, s, n, d, x, ldx, p, ldp,
+    hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(kEnergyThreads), 0, s, n, d, x, ldx, p, ldp,
                        inv_mass, prior, loglik, out);
     return hipGetLastError();
 }
