@@ -20,7 +20,8 @@
 //     and the pair then adds one product to the wave's sums: the residual
 //     square, which both the likelihood and dL/dsigma scale by a power of
 //     1/sigma once per wave, and its gradient coefficient (scaled by
-//     1/sigma^2 once per staging batch); in FP64 a wavefront whose pairs in
+//     1/sigma^2 once per staging batch in FP32, once per walk in FP64); in
+//     FP64 a wavefront whose pairs in
 //     two rows all have delta/sigma >= 3 takes shorter far-range forms of the
 //     special functions;
 //   * the column sums of the wr waves of a column group, and the row sums of
