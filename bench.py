@@ -821,8 +821,10 @@ def main():
         "autograd_map": autograd_map,
         "heldout_lpd": heldout,
         "batched_form": batched,
+        # the trajectory starts without a cached gradient: one evaluation at
+        # the start, then one per step
         "leapfrog": {"steps": 20, "step_size": 1e-3, "ms_per_trajectory": round(traj_ms, 4),
-                     "gradient_evals": 20},
+                     "gradient_evals": 21, "ms_per_gradient_eval": round(traj_ms / 21, 5)},
         "hmc": {"transitions": 100, "leapfrog_steps": 20, "step_size": 1e-3,
                 "ms_per_transition": round(hmc_ms, 4), "transitions_per_s": round(1e3 / hmc_ms, 2),
                 "acceptance": round(hmc_acc, 3), "graph": "10 transitions per replay"},
