@@ -528,6 +528,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int64_t til
 // no bound above (the allocator's own choice).
 template <typename T, int D>
 constexpr int sweep_waves_per_simd() { return D > 2 ? 1 : (sizeof(T) == 8 ? 4 : 7); }
+// The persistent batch kernel carries the problem lookup on top of the walk:
+// in FP32 with D <= 2 it fits five waves per SIMD without spilling (at six
+// or seven it spills).
+template <typename T, int MAXD>
+constexpr int batch_sweep_waves_per_simd()
+{
+    return (sizeof(T) == 4 && MAXD <= 2) ? 5 : sweep_waves_per_simd<T, MAXD>();
+}
 
 template <typename T, int D, bool GRAD>
 __global__ void __launch_bounds__(512)
@@ -559,7 +567,7 @@ __global__ void __launch_bounds__(512)
 // in, so the register allocation follows the largest D of the batch.
 template <typename T, bool GRAD, int MAXD>
 __global__ void __launch_bounds__(512)
-    __attribute__((amdgpu_waves_per_eu(sweep_waves_per_simd<T, MAXD>()))) batch_sweep_kernel(const BatchProblem* __restrict__ probs,
+    __attribute__((amdgpu_waves_per_eu(batch_sweep_waves_per_simd<T, MAXD>()))) batch_sweep_kernel(const BatchProblem* __restrict__ probs,
                                                           int32_t count, int64_t total_tiles,
                                                           unsigned long long* cursor)
 {
